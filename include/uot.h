@@ -1,0 +1,180 @@
+/*
+ * uot.h -- C ABI of the unbalanced Beckmann optimal-transport prox solver
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The solver runs the primal-dual proximal iteration of Lee, Bertrand and
+ * Rozell, "Parallel Unbalanced Optimal Transport Regularization for
+ * Large-scale Imaging Problems" (Sec. III-B, Algorithm 1), on a 2-D pixel
+ * grid with a 2-vector flux per pixel.  One constraint operator serves all
+ * modes:
+ *
+ *     K(z) = D M - x0 + x1 - r          (D = discrete divergence, Sec. II-A)
+ *
+ *   UOT_DIST        x0 = src = p, x1 = dst = q are fixed; the iteration
+ *                   evaluates V_mu(p, q) = min ||M||_{2,1} + mu ||r||_p^p
+ *                   s.t. K = 0  (eq. Unbal_OT_beckman; balanced: eq. OT_beckman)
+ *   UOT_PROX        the prox of V_mu at (p0, p1) = (src, dst) with step rho,
+ *                   over x0, x1 >= 0 (eq. Prox_UOT)
+ *   UOT_PROX_FIXED  the prox with the first argument held at s = src and the
+ *                   second argument's prox centre p = dst (eq.
+ *                   Prox_UOT_specialcase), over x1 >= 0
+ *
+ * Readings where the paper is silent or ambiguous:
+ *   - rho is the prox step of the prox definition (weight 1/(2 rho)), so
+ *     the x-update uses theta = tau1 / (rho + tau1).
+ *   - bc = 0 (default): zero flux through the right and top edges
+ *     (Mx[:, nx-1] = My[ny-1, :] = 0); bc = 1: the literal text, those
+ *     entries are free.
+ *   - stopping rule: rel_res = max(||K z^k|| / (||x0^k|| + ||x1^k||),
+ *     ||(z^{k-1}-z^k)/tau1 - K*(a^{k-1}-a^k)|| / ||K* a^k||) <= tol,
+ *     tested every check_every iterations.
+ *   - default steps tau1 = tau2 = 0.99 / ||K|| with ||K||^2 = lambda_max(D D*)
+ *     + (number of identity blocks of K), which keeps tau1 tau2 ||K||^2 < 1
+ *     (Theorem 1).  The paper tunes its steps by search and fixes no rule;
+ *     UOT_ADAPTIVE_STEPS keeps the product tau1 tau2 and rebalances the
+ *     ratio at every check by residual balancing (adaptive primal-dual
+ *     hybrid gradient, Goldstein, Li and Yuan): when the relative
+ *     stationarity residual exceeds 1.5x the relative feasibility residual,
+ *     tau1 /= (1 - alpha) and tau2 *= (1 - alpha), and the reverse in the
+ *     opposite case; alpha starts at 0.5 and shrinks by 0.95 per change.
+ *
+ * Memory layout: every image and state plane is FP32, ny rows of nx pixels
+ * with x fastest (element j*nx + i is pixel (i, j), the paper's column-major
+ * vec with i first).
+ *
+ * Ownership: every image and state pointer is a DEVICE pointer owned by the
+ * caller.  The library never frees, reallocates or keeps them past a call.
+ * A handle owns only its workspace (the second copy of the state used for
+ * ping-pong, reduction buffers, the captured graphs, tile lists); it is bound
+ * to one HIP stream and one device and is not thread-safe.
+ *
+ * Errors: every entry point returns a uot_status; no C++ exception crosses
+ * the ABI.  Argument and shape checks run before any device work.  Input
+ * values (non-finite, negative) are checked on the device before the first
+ * iteration.  Reaching max_iter is a report status, not an error.
+ */
+#ifndef UOT_H
+#define UOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum uot_status {
+  UOT_OK = 0,
+  UOT_ERR_ARG = 1,        /* a parameter is out of range or a pointer is NULL      */
+  UOT_ERR_SHAPE = 2,      /* grid sizes / offsets inconsistent                     */
+  UOT_ERR_STEP = 3,       /* tau1 * tau2 * ||K||^2 >= 1 (Theorem 1)                */
+  UOT_ERR_NONFINITE = 4,  /* NaN or Inf in an input image or a warm-start state    */
+  UOT_ERR_NEGATIVE = 5,   /* negative pixel in an input image                      */
+  UOT_ERR_DEVICE = 6,     /* a HIP call failed or no usable GPU                    */
+  UOT_ERR_OOM = 7,        /* workspace allocation failed                           */
+  UOT_ERR_MASS = 8        /* balanced mode, zero-flux boundary, unequal masses     */
+} uot_status;
+
+enum { UOT_DIST = 0, UOT_PROX = 1, UOT_PROX_FIXED = 2 };
+
+/* uot_report.status */
+enum { UOT_CONVERGED = 0, UOT_MAX_ITER = 1, UOT_DIVERGED = 2 };
+
+/* uot_params.flags */
+#define UOT_WARM_START   0x1u  /* start from the caller's state instead of zeros      */
+#define UOT_ALLOW_SIGNED 0x4u  /* DIST only: accept negative pixels in src/dst        */
+#define UOT_UNSAFE_STEPS 0x8u  /* skip the tau1 tau2 ||K||^2 < 1 check (testing only)  */
+#define UOT_NO_GRAPH     0x10u /* launch kernels directly instead of replaying graphs */
+#define UOT_AUTOTUNE     0x20u /* time the tile shapes on first use of a size class   */
+#define UOT_ADAPTIVE_STEPS 0x40u /* rebalance tau1/tau2 at each check (needs tol > 0)  */
+
+typedef struct uot_params {
+  int32_t nx, ny;       /* grid of uot_solve (ignored by uot_solve_batched)           */
+  int32_t mode;         /* UOT_DIST, UOT_PROX or UOT_PROX_FIXED                       */
+  int32_t balanced;     /* 1: drop r (the balanced variant)                           */
+  int32_t residual_p;   /* 1 (mu ||r||_1) or 2 (mu ||r||_2^2)                         */
+  int32_t bc;           /* 0 zero flux (default), 1 literal boundary                  */
+  double mu;            /* growth/decay weight mu > 0 (unbalanced only)               */
+  double rho;           /* prox step rho > 0 (PROX modes)                             */
+  double tau1, tau2;    /* primal / dual steps; 0 selects 0.99/||K|| for both         */
+  int32_t max_iter;     /* iteration cap, >= 0                                        */
+  int32_t check_every;  /* iterations between convergence checks (rounded up to even) */
+  double tol;           /* stop when rel_res <= tol; <= 0 runs exactly max_iter       */
+  uint32_t flags;       /* UOT_* flags above                                          */
+  int32_t tile_rows;    /* rows per 64-wide tile: 0 = autotuned/heuristic, else 4..32 */
+} uot_params;
+
+/* Device planes of one state.  Required planes by mode:
+ *   DIST: Mx, My, a (+ r unless balanced)      PROX: + x0, x1     PROX_FIXED: + x1
+ * Unused planes may be NULL. */
+typedef struct uot_state {
+  float *Mx, *My, *r, *a, *x0, *x1;
+} uot_state;
+
+/* Host-side report of one solve (one pair). */
+typedef struct uot_report {
+  int32_t iters;       /* iterations run                                               */
+  int32_t status;      /* UOT_CONVERGED, UOT_MAX_ITER or UOT_DIVERGED                  */
+  double rel_res;      /* stopping-rule residual at the last iterate                   */
+  double rel_gap;      /* (primal - dual) / |primal|; NaN where no bound is available  */
+  double primal;       /* certified upper bound on the optimal value                   */
+  double dual;         /* certified lower bound on the optimal value                   */
+  double feas;         /* ||K z|| at the last iterate                                  */
+  double objective;    /* objective of the raw iterate (no feasibility repair)         */
+  double seconds;      /* wall time of the call                                        */
+  double tau1, tau2;   /* steps actually used                                          */
+} uot_report;
+
+typedef struct uot_handle uot_handle;
+
+/* Validates *prm without touching the GPU.  Returns UOT_OK or the error a
+ * uot_create call would return for these parameters. */
+uot_status uot_check_params(const uot_params *prm);
+
+/* ||K||^2 for a grid and mode (proof of Theorem 1): lambda_max(D D*) + the
+ * number of identity blocks of K.  Host only; returns -1 on bad arguments. */
+double uot_knorm2(int32_t nx, int32_t ny, int32_t mode, int32_t balanced, int32_t bc);
+
+/* Creates a handle bound to hip_stream (a hipStream_t; NULL = default stream)
+ * on the current device.  *out is set to NULL on error. */
+uot_status uot_create(const uot_params *prm, void *hip_stream, uot_handle **out);
+
+/* One grid of nx x ny (from the params).  src/dst: device images (see the
+ * modes above).  st: caller-owned device state; zeroed first unless
+ * UOT_WARM_START.  On return st holds the last iterate and *rep (host) the
+ * report.  The call is synchronous with respect to the host. */
+uot_status uot_solve(uot_handle *h, const float *src, const float *dst, uot_state *st,
+                     uot_report *rep);
+
+/* B independent pairs of uneven sizes, solved together.  nx, ny, offset are
+ * HOST arrays of length B; pair b occupies elements [offset[b], offset[b] +
+ * nx[b]*ny[b]) of src, dst and of every plane of *packed (ranges must not
+ * overlap).  reps: host array of B reports.  Each pair gets its own steps
+ * (from its own ||K||) unless tau1/tau2 are given, and stops on its own. */
+uot_status uot_solve_batched(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
+                             const int64_t *offset, const float *src, const float *dst,
+                             uot_state *packed, uot_report *reps);
+
+/* Evaluates the report fields (rel_res against prev if prev != NULL, the
+ * certified gap, feasibility, objective) of a given state without iterating.
+ * Uses the handle's grid. */
+uot_status uot_objective(uot_handle *h, const float *src, const float *dst, const uot_state *st,
+                         const uot_state *prev, uot_report *out);
+
+/* Profiling aid: runs n (rounded up to even) back-to-back launches of the
+ * fused iteration kernel on the handle's grid and stream, bracketed by HIP
+ * events, starting from the caller's state *st (advanced by those
+ * iterations; no setup, no checks, no zeroing).  *ms_per_iter receives the
+ * average event-to-event time per launch.  src/dst as for uot_solve. */
+uot_status uot_time_iterations(uot_handle *h, const float *src, const float *dst, uot_state *st,
+                               int32_t n, double *ms_per_iter);
+
+/* Releases the handle's workspace.  NULL is a no-op. */
+void uot_destroy(uot_handle *h);
+
+const char *uot_status_string(uot_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UOT_H */

@@ -281,18 +281,39 @@ class Report:
     status: str = "MAX_ITER"
     rel_res: float = float("inf")
     history: list = field(default_factory=list)
+    tau1: float = 0.0
+    tau2: float = 0.0
+
+
+def relative_residuals(prob: Problem, prev: State, cur: State, tau1: float):
+    """(feasibility / (||x0|| + ||x1||), stationarity / ||K* a||): the two
+    parts of the stopping rule, each scale-free."""
+    pn, sn, _ = residuals(prob, prev, cur, tau1)
+    xn = float(np.linalg.norm(cur.x0) + np.linalg.norm(cur.x1))
+    ka = np.sqrt(_kstar_sq(prob, cur.a))
+    return pn / max(xn, 1e-30), sn / max(ka, 1e-30)
 
 
 def solve(prob: Problem, tau1=None, tau2=None, max_iter=1000, check_every=20, tol=0.0,
-          state: State | None = None, record=False):
+          state: State | None = None, record=False, adaptive=False):
     """Run Algorithm 1 from zero (or ``state``) until rel_res <= tol at a
     check (every ``check_every`` iterations) or ``max_iter`` iterations.
-    tol <= 0 runs exactly ``max_iter`` iterations."""
+    tol <= 0 runs exactly ``max_iter`` iterations.
+
+    adaptive: the paper fixes no step rule (its steps come from a parameter
+    search).  With ``adaptive`` the product tau1 tau2 is kept and the ratio
+    is rebalanced at every check by residual balancing (the adaptive
+    primal-dual hybrid gradient method of Goldstein, Li and Yuan): if the
+    relative stationarity residual exceeds 1.5 times the relative
+    feasibility residual, tau1 /= (1 - alpha), tau2 *= (1 - alpha); in the
+    opposite case the reverse; alpha starts at 0.5 and shrinks by 0.95 per
+    change, so the steps settle."""
     d1, d2 = prob.default_steps()
     tau1 = d1 if tau1 is None else float(tau1)
     tau2 = d2 if tau2 is None else float(tau2)
     st = initial_state(prob, state)
     rep = Report()
+    alpha = 0.5
     if prob.mode == DIST and not np.any(prob.src) and not np.any(prob.dst) and state is None:
         rep.status, rep.rel_res = "CONVERGED", 0.0
         return st, rep
@@ -303,14 +324,22 @@ def solve(prob: Problem, tau1=None, tau2=None, max_iter=1000, check_every=20, to
             rep.iters, rep.status = k, "DIVERGED"
             return st, rep
         if (tol > 0 and k % check_every == 0) or (k == max_iter):
-            _, _, rel = residuals(prob, prev, st, tau1)
+            rp, rd = relative_residuals(prob, prev, st, tau1)
+            rel = max(rp, rd)
             rep.rel_res = rel
             if record:
                 rep.history.append((k, rel))
             if tol > 0 and rel <= tol:
                 rep.iters, rep.status = k, "CONVERGED"
+                rep.tau1, rep.tau2 = tau1, tau2
                 return st, rep
+            if adaptive and tol > 0 and k < max_iter:
+                if rd > 1.5 * rp:
+                    tau1, tau2, alpha = tau1 / (1 - alpha), tau2 * (1 - alpha), alpha * 0.95
+                elif rp > 1.5 * rd:
+                    tau1, tau2, alpha = tau1 * (1 - alpha), tau2 / (1 - alpha), alpha * 0.95
     rep.iters = max_iter
+    rep.tau1, rep.tau2 = tau1, tau2
     return st, rep
 
 

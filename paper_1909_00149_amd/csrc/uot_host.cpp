@@ -1,0 +1,905 @@
+// Host runtime of the unbalanced Beckmann OT prox solver: argument checks,
+// step-size planning (Theorem 1), tile lists for ragged batches, graph
+// capture of check windows, the device-side stopping loop and the reports.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/uot.h"
+#include "uot_internal.hpp"
+
+using namespace uot;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+double lam1d(int n, int bc) {
+  if (bc == 0) {
+    const double s = std::sin(kPi * (n - 1) / (2.0 * n));
+    return 4.0 * s * s;
+  }
+  const double s = std::sin(kPi * (2.0 * n - 1) / (2.0 * (2.0 * n + 1)));
+  return 4.0 * s * s;
+}
+
+int n_identity(int mode, int balanced) {
+  const int base = mode == UOT_DIST ? 1 : (mode == UOT_PROX ? 3 : 2);
+  return base - (balanced ? 1 : 0);
+}
+
+int resid_of(const uot_params& p) { return p.balanced ? R_BAL : (p.residual_p == 2 ? R_P2 : R_P1); }
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double seconds() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+// Tile-shape cache filled by the autotuner, keyed by (mode, resid, bc, size class).
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+bool g_tune_loaded = false;
+
+std::string tune_key(int mode, int resid, int bc, long total_px) {
+  int cls = 0;
+  while ((1L << (2 * cls + 12)) < total_px && cls < 12) ++cls;  // 4^k * 4096 buckets
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "gfx950:m%d:r%d:b%d:c%d", mode, resid, bc, cls);
+  return buf;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("UOT_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[128];
+  int ty;
+  while (std::fscanf(f, " \"%127[^\"]\" : %d ,", key, &ty) == 2) g_tune_cache[key] = ty;
+  std::fclose(f);
+}
+
+void tune_store_locked() {
+  const char* path = std::getenv("UOT_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto& kv : g_tune_cache)
+    std::fprintf(f, "  \"%s\" : %d%s\n", kv.first.c_str(), kv.second, ++i < g_tune_cache.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+}
+
+int heuristic_rows(long total_px) {
+  if (total_px <= (1L << 16)) return 4;
+  if (total_px <= (1L << 20)) return 8;
+  return 16;
+}
+
+template <class T>
+hipError_t grow(T** p, size_t* cap, size_t n) {
+  if (n <= *cap && *p) return hipSuccess;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  size_t want = std::max<size_t>(n, 1);
+  hipError_t e = hipMalloc((void**)p, want * sizeof(T));
+  if (e == hipSuccess) *cap = want;
+  return e;
+}
+
+}  // namespace
+
+struct uot_handle {
+  uot_params prm{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int num_cu = 256;
+
+  // ping-pong shadow state and the c plane
+  float* B[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t capB[6] = {0, 0, 0, 0, 0, 0};
+  float* cplane = nullptr;
+  size_t cap_c = 0;
+
+  Tile* d_tiles = nullptr;      // full list (check/setup)
+  size_t cap_tiles = 0;
+  Tile* d_live = nullptr;       // live list (iteration)
+  size_t cap_live = 0;
+  int32_t* d_nlive = nullptr;
+  size_t cap_nlive = 0;
+  double* d_partial = nullptr;
+  size_t cap_partial = 0;
+
+  PairInfo* d_pairs = nullptr;
+  size_t cap_pairs = 0;
+  double* d_sums = nullptr;
+  size_t cap_sums = 0;
+  int32_t* d_i32 = nullptr;     // active | iters | status | n_active
+  size_t cap_i32 = 0;
+  double* d_f64 = nullptr;      // rel_res | xnorm | inv_s
+  size_t cap_f64 = 0;
+  float* d_invs = nullptr;
+  size_t cap_invs = 0;
+
+  double* h_sums = nullptr;     // pinned
+  size_t cap_hsums = 0;
+  int32_t* h_i32 = nullptr;     // pinned
+  size_t cap_hi32 = 0;
+
+  std::vector<Tile> h_live;     // kept alive across async uploads
+
+  // cached graph of one check window
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;
+
+  ~uot_handle() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto& p : B)
+      if (p) (void)hipFree(p);
+    void* dev[] = {cplane, d_tiles, d_live, d_nlive, d_partial, d_pairs, d_sums, d_i32, d_f64, d_invs};
+    for (void* p : dev)
+      if (p) (void)hipFree(p);
+    if (h_sums) (void)hipHostFree(h_sums);
+    if (h_i32) (void)hipHostFree(h_i32);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+extern "C" {
+
+const char* uot_status_string(uot_status s) {
+  switch (s) {
+    case UOT_OK: return "ok";
+    case UOT_ERR_ARG: return "invalid argument";
+    case UOT_ERR_SHAPE: return "inconsistent grid sizes or offsets";
+    case UOT_ERR_STEP: return "step sizes violate tau1*tau2*||K||^2 < 1";
+    case UOT_ERR_NONFINITE: return "non-finite value in an input image or warm-start state";
+    case UOT_ERR_NEGATIVE: return "negative pixel in an input image";
+    case UOT_ERR_DEVICE: return "HIP device error";
+    case UOT_ERR_OOM: return "device memory allocation failed";
+    case UOT_ERR_MASS: return "balanced zero-flux problem with unequal masses";
+  }
+  return "unknown status";
+}
+
+double uot_knorm2(int32_t nx, int32_t ny, int32_t mode, int32_t balanced, int32_t bc) {
+  if (nx < 1 || ny < 1 || mode < 0 || mode > 2 || bc < 0 || bc > 1) return -1.0;
+  return lam1d(nx, bc) + lam1d(ny, bc) + n_identity(mode, balanced ? 1 : 0);
+}
+
+uot_status uot_check_params(const uot_params* p) {
+  if (!p) return UOT_ERR_ARG;
+  if (p->mode < 0 || p->mode > 2) return UOT_ERR_ARG;
+  if (p->balanced != 0 && p->balanced != 1) return UOT_ERR_ARG;
+  if (!p->balanced && p->residual_p != 1 && p->residual_p != 2) return UOT_ERR_ARG;
+  if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
+  if (!p->balanced && !(p->mu > 0.0 && std::isfinite(p->mu))) return UOT_ERR_ARG;
+  if (p->mode != UOT_DIST && !(p->rho > 0.0 && std::isfinite(p->rho))) return UOT_ERR_ARG;
+  if (!(p->tau1 >= 0.0 && p->tau2 >= 0.0) || !std::isfinite(p->tau1) || !std::isfinite(p->tau2)) return UOT_ERR_ARG;
+  if ((p->tau1 == 0.0) != (p->tau2 == 0.0)) return UOT_ERR_ARG;
+  if (p->max_iter < 0 || p->check_every < 0) return UOT_ERR_ARG;
+  if (!std::isfinite(p->tol)) return UOT_ERR_ARG;
+  if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16 && p->tile_rows != 32)
+    return UOT_ERR_ARG;
+  if ((p->flags & UOT_ALLOW_SIGNED) && p->mode != UOT_DIST) return UOT_ERR_ARG;
+  if (p->nx < 0 || p->ny < 0) return UOT_ERR_SHAPE;
+  if (p->nx > 0 && p->ny > 0 && p->tau1 > 0.0 && !(p->flags & UOT_UNSAFE_STEPS)) {
+    const double k2 = uot_knorm2(p->nx, p->ny, p->mode, p->balanced, p->bc);
+    if (p->tau1 * p->tau2 * k2 >= 1.0) return UOT_ERR_STEP;
+  }
+  return UOT_OK;
+}
+
+uot_status uot_create(const uot_params* prm, void* hip_stream, uot_handle** out) {
+  if (!out) return UOT_ERR_ARG;
+  *out = nullptr;
+  uot_status st = uot_check_params(prm);
+  if (st != UOT_OK) return st;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UOT_ERR_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return UOT_ERR_DEVICE;
+  auto* h = new (std::nothrow) uot_handle();
+  if (!h) return UOT_ERR_OOM;
+  h->prm = *prm;
+  h->device = dev;
+  h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) {
+      delete h;
+      return UOT_ERR_DEVICE;
+    }
+    h->own_stream = true;
+  }
+  *out = h;
+  return UOT_OK;
+}
+
+void uot_destroy(uot_handle* h) { delete h; }
+
+}  // extern "C"
+
+namespace {
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) {                         \
+      if (std::getenv("UOT_DEBUG"))                 \
+        std::fprintf(stderr, "uot: %s failed: %s (%s:%d)\n", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return e_ == hipErrorOutOfMemory ? UOT_ERR_OOM : UOT_ERR_DEVICE; \
+    }                                               \
+  } while (0)
+
+struct Job {
+  int B = 0;
+  std::vector<PairInfo> pairs;
+  std::vector<Tile> tiles;
+  std::vector<double> knorm2;
+  long total_px = 0;
+  int ty = 8;
+};
+
+Planes planes_of(const uot_state& s) { return Planes{s.Mx, s.My, s.r, s.a, s.x0, s.x1}; }
+
+// Grid of the persistent iteration kernel: enough resident blocks to fill
+// every CU, rounded to a multiple of the 8 XCDs.
+int iter_grid(uot_handle* h, int mode, int resid, int bc, int ty, int ntiles) {
+  int occ = 0;
+  if (iter_occupancy(mode, resid, bc, ty, &occ) != hipSuccess || occ <= 0) occ = 4;
+  long g = std::min<long>((long)ntiles, (long)h->num_cu * occ);
+  g = std::max<long>(8, (g + 7) / 8 * 8);
+  return (int)g;
+}
+
+int aux_grid(uot_handle* h, int ntiles) {
+  return std::max(1, std::min(ntiles, h->num_cu * 8));
+}
+
+uot_status validate_state(const uot_params& p, const uot_state* s) {
+  if (!s || !s->Mx || !s->My || !s->a) return UOT_ERR_ARG;
+  if (!p.balanced && !s->r) return UOT_ERR_ARG;
+  if (p.mode == UOT_PROX && (!s->x0 || !s->x1)) return UOT_ERR_ARG;
+  if (p.mode == UOT_PROX_FIXED && !s->x1) return UOT_ERR_ARG;
+  return UOT_OK;
+}
+
+uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset, Job& J) {
+  const uot_params& p = h->prm;
+  if (B < 1 || !nx || !ny || !offset) return UOT_ERR_ARG;
+  J.B = B;
+  J.pairs.resize(B);
+  J.knorm2.resize(B);
+  std::vector<std::pair<int64_t, int64_t>> ranges(B);
+  long total = 0;
+  for (int b = 0; b < B; ++b) {
+    if (nx[b] < 1 || ny[b] < 1 || offset[b] < 0) return UOT_ERR_SHAPE;
+    const int64_t n = (int64_t)nx[b] * ny[b];
+    ranges[b] = {offset[b], offset[b] + n};
+    total = std::max<long>(total, offset[b] + n);
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (int b = 1; b < B; ++b)
+    if (ranges[b].first < ranges[b - 1].second) return UOT_ERR_SHAPE;
+  J.total_px = total;
+  const int resid = resid_of(p);
+  // tile rows: explicit, autotuned, or heuristic
+  int ty = p.tile_rows;
+  if (ty == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune_cache.find(tune_key(p.mode, resid, p.bc, total));
+    ty = it != g_tune_cache.end() ? it->second : heuristic_rows(total);
+  }
+  J.ty = ty;
+  J.tiles.clear();
+  for (int b = 0; b < B; ++b) {
+    const double k2 = uot_knorm2(nx[b], ny[b], p.mode, p.balanced, p.bc);
+    J.knorm2[b] = k2;
+    double t1 = p.tau1, t2 = p.tau2;
+    if (t1 == 0.0) t1 = t2 = 0.99 / std::sqrt(k2);
+    if (!(p.flags & UOT_UNSAFE_STEPS) && t1 * t2 * k2 >= 1.0) return UOT_ERR_STEP;
+    PairInfo& P = J.pairs[b];
+    P.off = offset[b];
+    P.nx = nx[b];
+    P.ny = ny[b];
+    P.tau1 = (float)t1;
+    P.tau2 = (float)t2;
+    P.theta = p.mode == UOT_DIST ? 0.f : (float)(t1 / (p.rho + t1));
+    P.mutau = (float)(p.mu * t1);
+    P.inv2mt = (float)(1.0 / (1.0 + 2.0 * p.mu * t1));
+    P.tile_begin = (int32_t)J.tiles.size();
+    for (int y = 0; y < ny[b]; y += ty)
+      for (int x = 0; x < nx[b]; x += TX) J.tiles.push_back(Tile{b, x, y, 0});
+    P.tile_count = (int32_t)J.tiles.size() - P.tile_begin;
+    P.pad = 0;
+  }
+  return UOT_OK;
+}
+
+uot_status ensure_workspace(uot_handle* h, const Job& J) {
+  const uot_params& p = h->prm;
+  const size_t px = (size_t)J.total_px;
+  const int resid = resid_of(p);
+  const bool need[6] = {true, true, resid != R_BAL, true, p.mode == UOT_PROX, p.mode != UOT_DIST};
+  for (int i = 0; i < 6; ++i)
+    if (need[i]) HIPCHK(grow(&h->B[i], &h->capB[i], px));
+  if (p.mode == UOT_DIST) HIPCHK(grow(&h->cplane, &h->cap_c, px));
+  const size_t nt = J.tiles.size();
+  HIPCHK(grow(&h->d_tiles, &h->cap_tiles, nt));
+  HIPCHK(grow(&h->d_live, &h->cap_live, nt));
+  HIPCHK(grow(&h->d_nlive, &h->cap_nlive, 1));
+  HIPCHK(grow(&h->d_partial, &h->cap_partial, nt * NS));
+  HIPCHK(grow(&h->d_pairs, &h->cap_pairs, (size_t)J.B));
+  HIPCHK(grow(&h->d_sums, &h->cap_sums, (size_t)J.B * NS));
+  HIPCHK(grow(&h->d_i32, &h->cap_i32, (size_t)J.B * 3 + 1));
+  HIPCHK(grow(&h->d_f64, &h->cap_f64, (size_t)J.B * 3));
+  HIPCHK(grow(&h->d_invs, &h->cap_invs, (size_t)J.B));
+  if (h->cap_hsums < (size_t)J.B * NS) {
+    if (h->h_sums) (void)hipHostFree(h->h_sums);
+    h->h_sums = nullptr;
+    h->cap_hsums = 0;
+    HIPCHK(hipHostMalloc((void**)&h->h_sums, (size_t)J.B * NS * sizeof(double), hipHostMallocDefault));
+    h->cap_hsums = (size_t)J.B * NS;
+  }
+  if (h->cap_hi32 < (size_t)J.B * 3 + 1) {
+    if (h->h_i32) (void)hipHostFree(h->h_i32);
+    h->h_i32 = nullptr;
+    h->cap_hi32 = 0;
+    HIPCHK(hipHostMalloc((void**)&h->h_i32, ((size_t)J.B * 3 + 1) * sizeof(int32_t), hipHostMallocDefault));
+    h->cap_hi32 = (size_t)J.B * 3 + 1;
+  }
+  return UOT_OK;
+}
+
+Planes shadow_planes(uot_handle* h) { return Planes{h->B[0], h->B[1], h->B[2], h->B[3], h->B[4], h->B[5]}; }
+
+// Uploads the live tile list: tiles of pairs whose flag is set.
+uot_status upload_live(uot_handle* h, const Job& J, const int32_t* active_host) {
+  h->h_live.clear();
+  for (const Tile& t : J.tiles)
+    if (active_host[t.pair]) h->h_live.push_back(t);
+  const int32_t n = (int32_t)h->h_live.size();
+  if (n > 0)
+    HIPCHK(hipMemcpyAsync(h->d_live, h->h_live.data(), n * sizeof(Tile), hipMemcpyHostToDevice, h->stream));
+  h->h_i32[(size_t)J.B * 3] = n;
+  HIPCHK(hipMemcpyAsync(h->d_nlive, &h->h_i32[(size_t)J.B * 3], sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return UOT_OK;
+}
+
+// Setup pass: validation, c = q - p, state init.  Fills per-pair sums on the host.
+uot_status run_setup(uot_handle* h, const Job& J, const float* src, const float* dst, const uot_state* st,
+                     bool warm, bool write_state) {
+  const uot_params& p = h->prm;
+  SetupArgs sa{};
+  sa.src = src;
+  sa.dst = dst;
+  sa.c = h->cplane;
+  sa.st = planes_of(*st);
+  sa.mode = p.mode;
+  sa.resid = resid_of(p);
+  sa.bc = p.bc;
+  sa.warm = warm ? 1 : 0;
+  sa.write_state = write_state ? 1 : 0;
+  sa.write_c = 1;
+  sa.pairs = h->d_pairs;
+  sa.tiles = h->d_tiles;
+  sa.ntiles = (int32_t)J.tiles.size();
+  sa.tile_rows = J.ty;
+  sa.partial = h->d_partial;
+  HIPCHK(launch_setup(aux_grid(h, sa.ntiles), sa, h->stream));
+  HIPCHK(launch_pair_reduce(h->d_pairs, J.B, h->d_partial, 0u, h->d_sums, h->stream));
+  HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, (size_t)J.B * NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return UOT_OK;
+}
+
+uot_status check_setup_sums(uot_handle* h, const Job& J, bool warm) {
+  const uot_params& p = h->prm;
+  for (int b = 0; b < J.B; ++b) {
+    const double* S = h->h_sums + (size_t)b * NS;
+    if (S[U_NONFIN_IN] > 0) return UOT_ERR_NONFINITE;
+    if (warm && S[U_NONFIN_ST] > 0) return UOT_ERR_NONFINITE;
+    if (S[U_NEG] > 0 && !(p.flags & UOT_ALLOW_SIGNED)) return UOT_ERR_NEGATIVE;
+    if (p.mode == UOT_DIST && p.balanced && p.bc == 0) {
+      const double m = std::max({std::fabs(S[U_SUMS]), std::fabs(S[U_SUMD]), 1e-30});
+      if (std::fabs(S[U_SUMS] - S[U_SUMD]) > 1e-4 * m) return UOT_ERR_MASS;
+    }
+  }
+  return UOT_OK;
+}
+
+struct Reporter {
+  // per-pair final fields computed on the host from the final check sums
+  static void fill(const uot_params& p, const PairInfo& P, const double* S, double xnorm_dist, uot_report* r,
+                   double dual_prox, bool have_dual_prox) {
+    const int resid = resid_of(p);
+    const double mu = p.mu, rho = p.rho;
+    const double quad = p.mode == UOT_DIST ? 0.0 : S[S_QUAD] / (2.0 * rho);
+    double obj = S[S_MNORM] + quad;
+    if (resid != R_BAL) obj += mu * S[S_RPEN];
+    r->objective = obj;
+    r->feas = std::sqrt(std::max(0.0, S[S_PRES2]));
+    const double xn = p.mode == UOT_DIST ? xnorm_dist : std::sqrt(S[S_X0SQ]) + std::sqrt(S[S_X1SQ]);
+    const double pr = std::sqrt(S[S_PRES2]) / std::max(xn, 1e-30);
+    const double du = std::sqrt(S[S_STAT2]) / std::max(std::sqrt(S[S_KA2]), 1e-30);
+    r->rel_res = std::max(pr, du);
+    r->tau1 = P.tau1;
+    r->tau2 = P.tau2;
+    r->primal = r->dual = r->rel_gap = std::nan("");
+    if (resid == R_BAL) return;  // needs the feasibility projection
+    r->primal = S[S_MNORM] + mu * S[S_EPEN] + quad;
+    double s = std::max(1.0, S[S_MAXG]);
+    if (resid == R_P1) s = std::max(s, S[S_MAXA] / mu);
+    if (p.mode == UOT_DIST) {
+      r->dual = S[S_LIN] / s;
+      if (resid == R_P2) r->dual -= S[S_A2] / (s * s) / (4.0 * mu);
+    } else if (have_dual_prox) {
+      r->dual = dual_prox;
+    }
+    if (std::isfinite(r->dual)) r->rel_gap = (r->primal - r->dual) / std::max(std::fabs(r->primal), 1e-30);
+  }
+};
+
+double scale_of(const uot_params& p, const double* S) {
+  double s = std::max(1.0, S[S_MAXG]);
+  if (resid_of(p) == R_P1) s = std::max(s, S[S_MAXA] / p.mu);
+  return s;
+}
+
+// Dual values of the PROX modes (second pass once the scale s is known).
+uot_status prox_duals(uot_handle* h, const Job& J, const float* src, const float* dst, const float* a_plane,
+                      const double* sums, std::vector<double>& out) {
+  const uot_params& p = h->prm;
+  std::vector<float> invs(J.B);
+  for (int b = 0; b < J.B; ++b) invs[b] = (float)(1.0 / scale_of(p, sums + (size_t)b * NS));
+  HIPCHK(hipMemcpyAsync(h->d_invs, invs.data(), J.B * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  DualArgs da{};
+  da.a = a_plane;
+  da.x_src = src;
+  da.x_dst = dst;
+  da.inv_s = h->d_invs;
+  da.pairs = h->d_pairs;
+  da.tiles = h->d_tiles;
+  da.ntiles = (int32_t)J.tiles.size();
+  da.tile_rows = J.ty;
+  da.mode = p.mode;
+  da.resid = resid_of(p);
+  da.rho = (float)p.rho;
+  da.mu = (float)p.mu;
+  da.partial = h->d_partial;
+  HIPCHK(launch_dual(aux_grid(h, da.ntiles), da, h->stream));
+  HIPCHK(launch_pair_reduce(h->d_pairs, J.B, h->d_partial, 0u, h->d_sums, h->stream));
+  std::vector<double> tmp((size_t)J.B * NS);
+  HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, (size_t)J.B * NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out.resize(J.B);
+  for (int b = 0; b < J.B; ++b) out[b] = h->h_sums[(size_t)b * NS];
+  return UOT_OK;
+}
+
+struct Launch {
+  uot_handle* h;
+  const Job* J;
+  IterArgs fwd, bwd;   // A -> B and B -> A
+  CheckArgs chk;
+  DecideArgs dec;
+  int grid_iter, grid_aux, resid;
+};
+
+uot_status enqueue_window(Launch& L, int W, bool check) {
+  uot_handle* h = L.h;
+  const uot_params& p = h->prm;
+  for (int i = 0; i < W; ++i)
+    HIPCHK(launch_iter(p.mode, L.resid, p.bc, L.J->ty, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
+  if (check) {
+    HIPCHK(launch_check(p.mode, L.resid, p.bc, L.grid_aux, L.chk, h->stream));
+    HIPCHK(launch_pair_reduce(h->d_pairs, L.J->B, h->d_partial, kMaxSlotsCheck, h->d_sums, h->stream));
+    HIPCHK(launch_decide(L.dec, h->stream));
+  }
+  return UOT_OK;
+}
+
+uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
+  uot_handle* h = L.h;
+  std::vector<unsigned char> key;
+  auto put = [&](const void* d, size_t n) {
+    const unsigned char* c = (const unsigned char*)d;
+    key.insert(key.end(), c, c + n);
+  };
+  put(&L.fwd, sizeof(L.fwd));
+  put(&L.chk, sizeof(L.chk));
+  put(&L.dec, sizeof(L.dec));
+  put(&W, sizeof(W));
+  int c = check;
+  put(&c, sizeof(c));
+  put(&L.grid_iter, sizeof(int));
+  put(&L.J->ty, sizeof(int));
+  put(&h->prm, sizeof(h->prm));
+  if (h->gexec && key == h->gkey) {
+    *out = h->gexec;
+    return UOT_OK;
+  }
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  uot_status st = enqueue_window(L, W, check);
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (st != UOT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  HIPCHK(e);
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  h->gexec = ex;
+  h->gkey = key;
+  *out = ex;
+  return UOT_OK;
+}
+
+uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
+                      const float* src, const float* dst, uot_state* st, uot_report* reps) {
+  Timer timer;
+  const uot_params& p = h->prm;
+  if (!src || !dst || !reps) return UOT_ERR_ARG;
+  uot_status s = validate_state(p, st);
+  if (s != UOT_OK) return s;
+  Job J;
+  s = plan(h, B, nx, ny, offset, J);
+  if (s != UOT_OK) return s;
+  if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+  s = ensure_workspace(h, J);
+  if (s != UOT_OK) return s;
+  const int resid = resid_of(p);
+  const bool warm = (p.flags & UOT_WARM_START) != 0;
+
+  HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, h->stream));
+  s = run_setup(h, J, src, dst, st, warm, true);
+  if (s != UOT_OK) return s;
+  s = check_setup_sums(h, J, warm);
+  if (s != UOT_OK) return s;
+
+  // per-pair host bookkeeping
+  int32_t* h_active = h->h_i32;
+  int32_t* h_iters = h->h_i32 + B;
+  int32_t* h_status = h->h_i32 + 2 * B;
+  std::vector<double> xnorm(B), relres(B, std::nan(""));
+  for (int b = 0; b < B; ++b) {
+    const double* S = h->h_sums + (size_t)b * NS;
+    xnorm[b] = std::sqrt(S[U_SQS]) + std::sqrt(S[U_SQD]);
+    h_active[b] = 1;
+    h_iters[b] = 0;
+    h_status[b] = UOT_MAX_ITER;
+    if (p.mode == UOT_DIST && !warm && S[U_SQS] == 0.0 && S[U_SQD] == 0.0) {
+      h_active[b] = 0;  // zero images: the zero state is optimal
+      h_status[b] = UOT_CONVERGED;
+      relres[b] = 0.0;
+    }
+    if (p.max_iter == 0 && h_active[b]) h_active[b] = 0;
+  }
+  int32_t* d_active = h->d_i32;
+  int32_t* d_iters = h->d_i32 + B;
+  int32_t* d_status = h->d_i32 + 2 * B;
+  int32_t* d_nact = h->d_i32 + 3 * B;
+  double* d_rel = h->d_f64;
+  double* d_xn = h->d_f64 + B;
+  double* d_alpha = h->d_f64 + 2 * B;
+  HIPCHK(hipMemcpyAsync(h->d_i32, h->h_i32, (size_t)B * 3 * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(d_xn, xnorm.data(), B * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(d_rel, relres.data(), B * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  std::vector<double> alpha0(B, 0.5);
+  HIPCHK(hipMemcpyAsync(d_alpha, alpha0.data(), B * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  s = upload_live(h, J, h_active);
+  if (s != UOT_OK) return s;
+
+  Launch L{};
+  L.h = h;
+  L.J = &J;
+  L.resid = resid;
+  L.grid_iter = iter_grid(h, p.mode, resid, p.bc, J.ty, (int)J.tiles.size());
+  L.grid_aux = aux_grid(h, (int)J.tiles.size());
+  const Planes A = planes_of(*st), Bp = shadow_planes(h);
+  const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
+  L.fwd = IterArgs{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, d_active};
+  L.bwd = IterArgs{Bp, A, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, d_active};
+  L.chk = CheckArgs{A, Bp, 0, 0, cptr, src, dst, h->d_pairs, h->d_tiles, (int32_t)J.tiles.size(), J.ty, d_active,
+                    h->d_partial};
+  const bool check = p.tol > 0.0;
+  int W = std::max(2, p.check_every > 0 ? p.check_every : 20);
+  W += W & 1;
+  const bool adaptive = check && (p.flags & UOT_ADAPTIVE_STEPS);
+  L.dec = DecideArgs{h->d_pairs, h->d_sums, d_xn, d_active, d_iters, d_status, d_rel, d_nact, B, W,
+                     p.max_iter, check ? 1 : 0, 0, p.mode, n_identity(p.mode, p.balanced), p.tol,
+                     adaptive ? 1 : 0, d_alpha, p.mu, p.rho};
+
+  int n_active = 0;
+  for (int b = 0; b < B; ++b) n_active += h_active[b];
+  const int nwin = p.max_iter / W;
+  const int tail = p.max_iter % W;
+  const bool use_graph = !(p.flags & UOT_NO_GRAPH);
+  hipGraphExec_t gx = nullptr;
+  if (n_active > 0 && nwin > 0 && use_graph) {
+    s = get_graph(L, W, check, &gx);
+    if (s != UOT_OK) return s;
+  }
+  // windows: the device decides convergence; the host polls every few windows
+  const int poll = std::max(1, 256 / W);
+  int done_iters = 0;  // iterations of pairs that never stop early (fixed mode)
+  int w = 0;
+  while (w < nwin && n_active > 0) {
+    const int burst = std::min(poll, nwin - w);
+    for (int i = 0; i < burst; ++i) {
+      if (gx) HIPCHK(hipGraphLaunch(gx, h->stream));
+      else {
+        s = enqueue_window(L, W, check);
+        if (s != UOT_OK) return s;
+      }
+    }
+    w += burst;
+    done_iters += burst * W;
+    if (check) {
+      HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t) + sizeof(int32_t) * 0,
+                            hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(&h->h_i32[(size_t)B * 3], d_nact, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      const int now = h->h_i32[(size_t)B * 3];
+      if (now == 0) {
+        n_active = 0;
+        break;
+      }
+      if (now < n_active) {  // compact the live tile list
+        s = upload_live(h, J, h_active);
+        if (s != UOT_OK) return s;
+      }
+      n_active = now;
+    }
+  }
+  if (!check) {
+    // fixed iteration count: every active pair ran the windows
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  // tail iterations for pairs still running
+  const bool run_tail = n_active > 0 && tail > 0;
+  if (run_tail) {
+    for (int i = 0; i < tail; ++i)
+      HIPCHK(launch_iter(p.mode, resid, p.bc, J.ty, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
+  }
+  const bool odd = run_tail && (tail & 1);
+  // final evaluation of every pair, then the final decision
+  CheckArgs fin = L.chk;
+  if (p.max_iter == 0) fin.B = A;  // no iteration ran: no previous iterate
+  fin.swap_active = odd ? 1 : 0;
+  fin.all_pairs = 1;
+  HIPCHK(launch_check(p.mode, resid, p.bc, L.grid_aux, fin, h->stream));
+  HIPCHK(launch_pair_reduce(h->d_pairs, B, h->d_partial, kMaxSlotsCheck, h->d_sums, h->stream));
+  DecideArgs fd = L.dec;
+  fd.W = check ? (run_tail ? tail : 0) : (done_iters + (run_tail ? tail : 0));
+  fd.check = 1;
+  fd.tol = check ? p.tol : 0.0;
+  fd.final_pass = 1;
+  if (odd) {
+    // pairs still active hold their iterate in the shadow copy: copy it back
+    // before the decision clears their flag
+    HIPCHK(launch_copy_active(A, Bp, h->d_pairs, h->d_tiles, (int)J.tiles.size(), J.ty, d_active, L.grid_aux,
+                              h->stream));
+  }
+  // Pairs that stopped in an earlier window keep their recorded rel_res; the
+  // final decision re-evaluates only still-active pairs.
+  HIPCHK(launch_decide(fd, h->stream));
+  HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, (size_t)B * NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(relres.data(), d_rel, B * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (adaptive)
+    HIPCHK(hipMemcpyAsync(J.pairs.data(), h->d_pairs, B * sizeof(PairInfo), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<double> sums(h->h_sums, h->h_sums + (size_t)B * NS);
+  std::vector<double> duals;
+  const bool need_dual = p.mode != UOT_DIST && resid != R_BAL;
+  if (need_dual) {
+    s = prox_duals(h, J, src, dst, st->a, sums.data(), duals);
+    if (s != UOT_OK) return s;
+  }
+  const double secs = timer.seconds();
+  for (int b = 0; b < B; ++b) {
+    uot_report& r = reps[b];
+    std::memset(&r, 0, sizeof(r));
+    Reporter::fill(p, J.pairs[b], sums.data() + (size_t)b * NS, xnorm[b], &r, need_dual ? duals[b] : 0.0,
+                   need_dual);
+    r.iters = h->h_i32[B + b];
+    r.status = h->h_i32[2 * B + b];
+    r.seconds = secs;
+    if (r.status == UOT_CONVERGED && relres[b] == 0.0) r.rel_res = 0.0;
+  }
+  return UOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uot_status uot_solve(uot_handle* h, const float* src, const float* dst, uot_state* st, uot_report* rep) {
+  if (!h) return UOT_ERR_ARG;
+  if (h->prm.nx < 1 || h->prm.ny < 1) return UOT_ERR_SHAPE;
+  const int32_t nx = h->prm.nx, ny = h->prm.ny;
+  const int64_t off = 0;
+  try {
+    return solve_core(h, 1, &nx, &ny, &off, src, dst, st, rep);
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_solve_batched(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
+                             const float* src, const float* dst, uot_state* packed, uot_report* reps) {
+  if (!h) return UOT_ERR_ARG;
+  try {
+    return solve_core(h, B, nx, ny, offset, src, dst, packed, reps);
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_time_iterations(uot_handle* h, const float* src, const float* dst, uot_state* st, int32_t n,
+                               double* ms_per_iter) {
+  if (!h || !src || !dst || !ms_per_iter || n < 1) return UOT_ERR_ARG;
+  const uot_params& p = h->prm;
+  if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
+  uot_status s = validate_state(p, st);
+  if (s != UOT_OK) return s;
+  try {
+    const int32_t nx = p.nx, ny = p.ny;
+    const int64_t off = 0;
+    Job J;
+    s = plan(h, 1, &nx, &ny, &off, J);
+    if (s != UOT_OK) return s;
+    if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+    s = ensure_workspace(h, J);
+    if (s != UOT_OK) return s;
+    HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                          h->stream));
+    s = run_setup(h, J, src, dst, st, true, false);
+    if (s != UOT_OK) return s;
+    h->h_i32[0] = 1;
+    HIPCHK(hipMemcpyAsync(h->d_i32, h->h_i32, sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    s = upload_live(h, J, h->h_i32);
+    if (s != UOT_OK) return s;
+    const int resid = resid_of(p);
+    const int grid = iter_grid(h, p.mode, resid, p.bc, J.ty, (int)J.tiles.size());
+    const Planes A = planes_of(*st), Bp = shadow_planes(h);
+    const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
+    const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
+    const IterArgs bwd{Bp, A, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
+    const int nn = n + (n & 1);
+    // the launches are captured once and replayed, as the solver does
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < nn && le == hipSuccess; ++i)
+      le = launch_iter(p.mode, resid, p.bc, J.ty, grid, (i & 1) ? bwd : fwd, h->stream);
+    hipError_t ce = hipStreamEndCapture(h->stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return UOT_ERR_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(ie);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipGraphLaunch(ex, h->stream));  // warm replay
+    HIPCHK(hipEventRecord(e0, h->stream));
+    HIPCHK(hipGraphLaunch(ex, h->stream));
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipGraphExecDestroy(ex);
+    *ms_per_iter = (double)ms / nn;
+    return UOT_OK;
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_objective(uot_handle* h, const float* src, const float* dst, const uot_state* st,
+                         const uot_state* prev, uot_report* out) {
+  if (!h || !src || !dst || !out) return UOT_ERR_ARG;
+  const uot_params& p = h->prm;
+  if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
+  uot_status s = validate_state(p, st);
+  if (s != UOT_OK) return s;
+  if (prev && validate_state(p, prev) != UOT_OK) return UOT_ERR_ARG;
+  try {
+    Timer timer;
+    const int32_t nx = p.nx, ny = p.ny;
+    const int64_t off = 0;
+    Job J;
+    s = plan(h, 1, &nx, &ny, &off, J);
+    if (s != UOT_OK) return s;
+    if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+    s = ensure_workspace(h, J);
+    if (s != UOT_OK) return s;
+    HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                          h->stream));
+    // c = q - p is written into the workspace; the state is only read
+    SetupArgs sa{};
+    sa.src = src;
+    sa.dst = dst;
+    sa.c = h->cplane;
+    sa.st = planes_of(*st);
+    sa.mode = p.mode;
+    sa.resid = resid_of(p);
+    sa.bc = p.bc;
+    sa.warm = 1;
+    sa.write_state = 0;
+    sa.write_c = 1;
+    sa.pairs = h->d_pairs;
+    sa.tiles = h->d_tiles;
+    sa.ntiles = (int32_t)J.tiles.size();
+    sa.tile_rows = J.ty;
+    sa.partial = h->d_partial;
+    HIPCHK(launch_setup(aux_grid(h, sa.ntiles), sa, h->stream));
+    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, 0u, h->d_sums, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const double xn = std::sqrt(h->h_sums[U_SQS]) + std::sqrt(h->h_sums[U_SQD]);
+    int32_t one = 1;
+    HIPCHK(hipMemcpyAsync(h->d_i32, &one, sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    const uot_state* q = prev ? prev : st;
+    CheckArgs ck{planes_of(*st), planes_of(*q), 0, 1, p.mode == UOT_DIST ? h->cplane : nullptr, src, dst,
+                 h->d_pairs, h->d_tiles, (int32_t)J.tiles.size(), J.ty, h->d_i32, h->d_partial};
+    HIPCHK(launch_check(p.mode, resid_of(p), p.bc, aux_grid(h, ck.ntiles), ck, h->stream));
+    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, kMaxSlotsCheck, h->d_sums, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<double> sums(h->h_sums, h->h_sums + NS);
+    std::vector<double> duals;
+    const bool need_dual = p.mode != UOT_DIST && resid_of(p) != R_BAL;
+    if (need_dual) {
+      s = prox_duals(h, J, src, dst, st->a, sums.data(), duals);
+      if (s != UOT_OK) return s;
+    }
+    std::memset(out, 0, sizeof(*out));
+    Reporter::fill(p, J.pairs[0], sums.data(), xn, out, need_dual ? duals[0] : 0.0, need_dual);
+    out->status = (sums[S_NONFIN] > 0) ? UOT_DIVERGED : UOT_MAX_ITER;
+    out->seconds = timer.seconds();
+    return UOT_OK;
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the unbalanced Beckmann OT prox solver (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace uot {
+
+constexpr int TX = 64;        // tile width: one 64-lane wavefront per row
+constexpr int BLOCK = 256;    // threads per workgroup (4 wavefronts)
+constexpr int NS = 16;        // per-tile partial-sum slots
+
+// Residual variants of the iteration.
+enum Resid { R_BAL = 0, R_P1 = 1, R_P2 = 2 };
+
+// Partial-sum slots written by the check kernel (per tile, then per pair).
+enum CheckSlot {
+  S_PRES2 = 0,  // sum (K z)^2
+  S_STAT2 = 1,  // sum of squared stationarity residual
+  S_KA2 = 2,    // sum ||K* a||^2 terms
+  S_X0SQ = 3,   // sum x0^2 (iterate)
+  S_X1SQ = 4,   // sum x1^2 (iterate)
+  S_MNORM = 5,  // sum ||M_i||_2
+  S_RPEN = 6,   // sum |r| (p=1) or r^2 (p=2)
+  S_EPEN = 7,   // sum |e| or e^2, e = D M - x0 + x1
+  S_LIN = 8,    // DIST: sum a c;  PROX_FIXED: -sum a s
+  S_QUAD = 9,   // sum (x - p)^2 over the free arguments
+  S_MAXG = 10,  // max ||(D* a)_i||_2   (max-reduced)
+  S_MAXA = 11,  // max |a_i|            (max-reduced)
+  S_NONFIN = 12,// count of non-finite state entries
+  S_A2 = 13,    // sum a^2
+  S_SUMA = 14,  // sum a
+};
+
+// Partial-sum slots written by the setup kernel.
+enum SetupSlot {
+  U_NONFIN_IN = 0, U_NEG = 1, U_NONFIN_ST = 2, U_SUMS = 3, U_SUMD = 4, U_SQS = 5, U_SQD = 6,
+};
+
+inline constexpr uint32_t kMaxSlotsCheck = (1u << S_MAXG) | (1u << S_MAXA);
+
+struct PairInfo {
+  int64_t off;         // first pixel of the pair in the packed planes
+  int32_t nx, ny;
+  float tau1, tau2;
+  float theta;         // tau1 / (rho + tau1)
+  float mutau;         // mu * tau1
+  float inv2mt;        // 1 / (1 + 2 mu tau1)
+  int32_t tile_begin;  // first tile of the pair in the full tile list
+  int32_t tile_count;
+  int32_t pad;
+};
+
+struct Tile {
+  int32_t pair, x0, y0, pad;
+};
+
+struct Planes {
+  float *Mx, *My, *r, *a, *x0, *x1;
+};
+
+struct IterArgs {
+  Planes in, out;
+  const float* c;     // DIST: q - p
+  const float* src;   // PROX: p0;  PROX_FIXED: s
+  const float* dst;   // PROX: p1;  PROX_FIXED: p
+  const PairInfo* pairs;
+  const Tile* tiles;
+  const int32_t* ntiles;
+  const int32_t* active;
+};
+
+struct CheckArgs {
+  Planes A, B;        // ping-pong copies; current = A unless swap for the pair
+  int swap_active;    // 1: pairs still active hold their current iterate in B
+  int all_pairs;      // 1: evaluate inactive pairs too
+  const float* c;
+  const float* src;
+  const float* dst;
+  const PairInfo* pairs;
+  const Tile* tiles;
+  int32_t ntiles;
+  int32_t tile_rows;
+  const int32_t* active;
+  double* partial;    // [ntiles][NS]
+};
+
+struct SetupArgs {
+  const float* src;
+  const float* dst;
+  float* c;           // DIST only
+  Planes st;
+  int mode, resid, bc;
+  int warm;           // 1: keep the caller's state (only its structural zeros are written)
+  int write_state;    // 0: the state is only read
+  int write_c;        // DIST: write c = q - p into the workspace
+  const PairInfo* pairs;
+  const Tile* tiles;
+  int32_t ntiles;
+  int32_t tile_rows;
+  double* partial;
+};
+
+struct DecideArgs {
+  PairInfo* pairs;      // steps are rewritten when adaptive
+  const double* sums;   // [B][NS]
+  const double* xnorm;  // DIST: ||p|| + ||q|| per pair; other modes: unused
+  int32_t* active;
+  int32_t* iters;
+  int32_t* status;
+  double* rel_res;
+  int32_t* n_active;
+  int32_t B;
+  int32_t W;          // iterations since the last decision
+  int32_t max_iter;
+  int32_t check;      // 1: apply the stopping rule
+  int32_t final_pass; // 1: decide every still-active pair (MAX_ITER if not converged)
+  int32_t mode;
+  int32_t nid;        // identity blocks in K
+  double tol;
+  int32_t adaptive;   // residual balancing of tau1/tau2
+  double* alpha;      // per-pair adaptation factor
+  double mu, rho;
+};
+
+struct DualArgs {
+  const float* a;
+  const float* x_src;
+  const float* x_dst;
+  const float* inv_s;  // per pair
+  const PairInfo* pairs;
+  const Tile* tiles;
+  int32_t ntiles, tile_rows, mode, resid;
+  float rho, mu;
+  double* partial;
+};
+
+hipError_t launch_iter(int mode, int resid, int bc, int ty, int grid, const IterArgs& a,
+                       hipStream_t s);
+hipError_t launch_check(int mode, int resid, int bc, int grid, const CheckArgs& a, hipStream_t s);
+hipError_t launch_setup(int grid, const SetupArgs& a, hipStream_t s);
+hipError_t launch_pair_reduce(const PairInfo* pairs, int B, const double* partial, uint32_t max_mask,
+                              double* sums, hipStream_t s);
+hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
+hipError_t launch_copy_active(const Planes& dst, const Planes& src, const PairInfo* pairs,
+                              const Tile* tiles, int ntiles, int tile_rows, const int32_t* active,
+                              int grid, hipStream_t s);
+hipError_t launch_dual(int grid, const DualArgs& a, hipStream_t s);
+hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* blocks_per_cu);
+
+}  // namespace uot

@@ -1,0 +1,648 @@
+// HIP kernels (gfx950) of the unbalanced Beckmann OT prox solver.
+//
+// cp_iter: one fused pass of Algorithm 1 (Sec. III-B) per launch:
+//   M  <- group-shrink_{tau1}(M - tau1 D* a)          (eq. Prox_UOT_M_prox)
+//   x  <- max(theta p + (1-theta)(x - tau1 A^T a), 0)   (PROX modes)
+//   r  <- shrink_{mu tau1}(r + tau1 a)  |  (r + tau1 a)/(1 + 2 mu tau1)
+//   a  <- a + tau2 (2 K(z_new) - K(z_old)),   K(z) = D M - x0 + x1 - r
+// A workgroup owns a 64 x TY tile.  a^k is staged in LDS with a one-pixel
+// halo on every side, the old flux with a halo on the low sides; the new
+// flux is computed for the tile plus its low-side halo (so D M_new needs no
+// second launch), then each pixel forms K_old, K_new and the dual step.
+// Input and output states are different buffers (ping-pong), so no pixel
+// reads a value another workgroup may already have overwritten.
+//
+// The tile list is walked by a fixed grid; blocks are mapped so that each
+// of the 8 XCDs (which own separate L2 caches and receive workgroups
+// round-robin) walks one contiguous eighth of the list, keeping vertically
+// neighbouring tiles, which share halo rows, in one L2.
+#include "uot_internal.hpp"
+
+#include <cmath>
+
+namespace uot {
+
+namespace {
+
+__device__ __forceinline__ float shrink1f(float v, float s) {
+  float m = fabsf(v) - s;
+  return m > 0.f ? copysignf(m, v) : 0.f;
+}
+
+template <int MODE>
+__device__ __forceinline__ constexpr int n_id_blocks(int resid) {
+  return (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (resid == R_BAL ? 1 : 0);
+}
+
+// Chunked, XCD-aware walk of the tile list: returns the range of list
+// indices this block visits as (first, stride, end).
+__device__ __forceinline__ void xcd_chunk(int ntiles, long& first, long& stride, long& end) {
+  const int G = gridDim.x;              // multiple of 8
+  const int xcd = blockIdx.x & 7;
+  const int slot = blockIdx.x >> 3;
+  const int per = (G - xcd + 7) >> 3;  // blocks on this XCD
+  const long cb = (long)ntiles * xcd / 8;
+  end = (long)ntiles * (xcd + 1) / 8;
+  first = cb + slot;
+  stride = per;
+}
+
+}  // namespace
+
+template <int MODE, int RES, int BC, int TY>
+__global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
+  constexpr int PPT = TY / 4;
+  __shared__ float sa[TY + 2][TX + 2];
+  __shared__ float smx[TY + 1][TX + 1];
+  __shared__ float smy[TY + 1][TX + 1];
+  __shared__ float snx[TY + 1][TX + 1];
+  __shared__ float sny[TY + 1][TX + 1];
+
+  const int tid = threadIdx.x;
+  const int lx = tid & 63;
+  const int wv = tid >> 6;
+  long t, stride, tend;
+  xcd_chunk(*A.ntiles, t, stride, tend);
+
+  for (; t < tend; t += stride) {
+    const Tile tl = A.tiles[t];
+    if (!A.active[tl.pair]) continue;  // uniform over the block
+    const PairInfo P = A.pairs[tl.pair];
+    const int nx = P.nx, ny = P.ny;
+    const int gx0 = tl.x0, gy0 = tl.y0;
+    const long off = P.off;
+    const float tau1 = P.tau1, tau2 = P.tau2;
+
+    __syncthreads();  // LDS of the previous tile is no longer read
+
+    // ---- stage a^k (rows -1..TY, cols -1..TX) and old M (low halo) ----
+    const float* __restrict__ a_in = A.in.a + off;
+    for (int idx = tid; idx < (TY + 2) * (TX + 2); idx += BLOCK) {
+      const int ry = idx / (TX + 2), rx = idx - ry * (TX + 2);
+      const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
+      float v = 0.f;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = a_in[(long)gy * nx + gx];
+      sa[ry][rx] = v;
+    }
+    const float* __restrict__ mx_in = A.in.Mx + off;
+    const float* __restrict__ my_in = A.in.My + off;
+    for (int idx = tid; idx < (TY + 1) * (TX + 1); idx += BLOCK) {
+      const int ry = idx / (TX + 1), rx = idx - ry * (TX + 1);
+      const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
+      float vx = 0.f, vy = 0.f;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+        const long o = (long)gy * nx + gx;
+        vx = mx_in[o];
+        vy = my_in[o];
+        if (BC == 0) {
+          if (gx == nx - 1) vx = 0.f;
+          if (gy == ny - 1) vy = 0.f;
+        }
+      }
+      smx[ry][rx] = vx;
+      smy[ry][rx] = vy;
+    }
+    // own pixels: element-wise planes straight to registers
+    float r_o[PPT], c0[PPT], c1[PPT], x0_o[PPT], x1_o[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int gx = gx0 + lx, gy = gy0 + wv + 4 * k;
+      r_o[k] = c0[k] = c1[k] = x0_o[k] = x1_o[k] = 0.f;
+      if (gx < nx && gy < ny) {
+        const long o = off + (long)gy * nx + gx;
+        if (RES != R_BAL) r_o[k] = A.in.r[o];
+        if (MODE == 0) {
+          c0[k] = A.c[o];
+        } else {
+          c0[k] = A.src[o];
+          c1[k] = A.dst[o];
+          if (MODE == 1) x0_o[k] = A.in.x0[o];
+          x1_o[k] = A.in.x1[o];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- new flux over the tile and its low-side halo ----
+    const float t2 = tau1 * tau1;
+    for (int idx = tid; idx < (TY + 1) * (TX + 1); idx += BLOCK) {
+      const int ry = idx / (TX + 1), rx = idx - ry * (TX + 1);
+      const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
+      float nxv = 0.f, nyv = 0.f;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+        const float ac = sa[ry][rx];
+        float gxx = ac - sa[ry][rx + 1];
+        float gyy = ac - sa[ry + 1][rx];
+        if (BC == 0) {
+          if (gx == nx - 1) gxx = 0.f;
+          if (gy == ny - 1) gyy = 0.f;
+        }
+        const float vx = smx[ry][rx] - tau1 * gxx;
+        const float vy = smy[ry][rx] - tau1 * gyy;
+        const float n2 = vx * vx + vy * vy;
+        const float s = n2 > t2 ? 1.f - tau1 * rsqrtf(n2) : 0.f;
+        nxv = s * vx;
+        nyv = s * vy;
+      }
+      snx[ry][rx] = nxv;
+      sny[ry][rx] = nyv;
+    }
+    __syncthreads();
+
+    // ---- element-wise steps and the dual update ----
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int ly = wv + 4 * k;
+      const int gx = gx0 + lx, gy = gy0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const int ry = ly + 1, rx = lx + 1;
+      const float dmn = snx[ry][rx] - snx[ry][rx - 1] + sny[ry][rx] - sny[ry - 1][rx];
+      const float dmo = smx[ry][rx] - smx[ry][rx - 1] + smy[ry][rx] - smy[ry - 1][rx];
+      const float a = sa[ry][rx];
+      float kold, knew;
+      float x0n = 0.f, x1n = 0.f, rn = 0.f;
+      if (RES == R_P1) rn = shrink1f(r_o[k] + tau1 * a, P.mutau);
+      if (RES == R_P2) rn = (r_o[k] + tau1 * a) * P.inv2mt;
+      if (MODE == 0) {
+        kold = dmo + c0[k];
+        knew = dmn + c0[k];
+      } else if (MODE == 1) {
+        const float th = P.theta;
+        x0n = fmaxf(th * c0[k] + (1.f - th) * (x0_o[k] + tau1 * a), 0.f);
+        x1n = fmaxf(th * c1[k] + (1.f - th) * (x1_o[k] - tau1 * a), 0.f);
+        kold = dmo - x0_o[k] + x1_o[k];
+        knew = dmn - x0n + x1n;
+      } else {
+        const float th = P.theta;
+        x1n = fmaxf(th * c1[k] + (1.f - th) * (x1_o[k] - tau1 * a), 0.f);
+        kold = dmo - c0[k] + x1_o[k];
+        knew = dmn - c0[k] + x1n;
+      }
+      if (RES != R_BAL) {
+        kold -= r_o[k];
+        knew -= rn;
+      }
+      const float an = a + tau2 * (2.f * knew - kold);
+      const long o = off + (long)gy * nx + gx;
+      A.out.Mx[o] = snx[ry][rx];
+      A.out.My[o] = sny[ry][rx];
+      A.out.a[o] = an;
+      if (RES != R_BAL) A.out.r[o] = rn;
+      if (MODE == 1) A.out.x0[o] = x0n;
+      if (MODE != 0) A.out.x1[o] = x1n;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of NS double slots into one partial row.
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst) {
+  __shared__ double red[BLOCK / 64][NS];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double v = acc[s];
+    const bool mx = (max_mask >> s) & 1u;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double w = __shfl_xor(v, o, 64);
+      v = mx ? fmax(v, w) : v + w;
+    }
+    if (lane == 0) red[wv][s] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    const int s = threadIdx.x;
+    const bool mx = (max_mask >> s) & 1u;
+    double v = red[0][s];
+    for (int w = 1; w < BLOCK / 64; ++w) v = mx ? fmax(v, red[w][s]) : v + red[w][s];
+    dst[s] = v;
+  }
+  __syncthreads();
+}
+
+// Residuals and certificate terms of the current iterate (K2).  Direct
+// global loads; neighbours come from the L2.  Runs once per check window.
+template <int MODE, int RES, int BC>
+__global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
+  const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
+  for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+    const Tile tl = A.tiles[t];
+    const bool act = A.active[tl.pair] != 0;
+    if (!act && !A.all_pairs) continue;  // uniform
+    const PairInfo P = A.pairs[tl.pair];
+    const bool swap = A.swap_active && act;
+    const Planes C = swap ? A.B : A.A;
+    const Planes Q = swap ? A.A : A.B;  // previous iterate
+    const int nx = P.nx, ny = P.ny;
+    const float tau1 = P.tau1;
+    const double it1 = 1.0 / (double)tau1;
+    double acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int ly = wv; ly < A.tile_rows; ly += 4) {
+      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const long o = P.off + (long)gy * nx + gx;
+      const bool hasR = gx + 1 < nx, hasU = gy + 1 < ny;
+      const bool hasL = gx > 0, hasD = gy > 0;
+      const double a = C.a[o], ap = Q.a[o];
+      const double aR = hasR ? (double)C.a[o + 1] : 0.0, apR = hasR ? (double)Q.a[o + 1] : 0.0;
+      const double aU = hasU ? (double)C.a[o + nx] : 0.0, apU = hasU ? (double)Q.a[o + nx] : 0.0;
+      double gxx = a - aR, gyy = a - aU;
+      double dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
+      const bool zx = (BC == 0 && gx == nx - 1), zy = (BC == 0 && gy == ny - 1);
+      if (zx) gxx = dgx = 0.0;
+      if (zy) gyy = dgy = 0.0;
+      const double mx = zx ? 0.0 : (double)C.Mx[o], my = zy ? 0.0 : (double)C.My[o];
+      const double mxp = zx ? 0.0 : (double)Q.Mx[o], myp = zy ? 0.0 : (double)Q.My[o];
+      const double mxl = hasL ? (double)C.Mx[o - 1] : 0.0;
+      const double myd = hasD ? (double)C.My[o - nx] : 0.0;
+      const double dm = mx - mxl + my - myd;
+      double x0 = 0.0, x1 = 0.0, e;
+      if (MODE == 0) {
+        e = dm + (double)A.c[o];
+      } else if (MODE == 1) {
+        x0 = C.x0[o];
+        x1 = C.x1[o];
+        e = dm - x0 + x1;
+      } else {
+        x1 = C.x1[o];
+        e = dm - (double)A.src[o] + x1;
+      }
+      double r = 0.0, rp = 0.0;
+      if (RES != R_BAL) {
+        r = C.r[o];
+        rp = Q.r[o];
+      }
+      const double kz = e - r;
+      const double da = ap - a;
+      const double sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
+      double st2 = sx * sx + sy * sy;
+      if (RES != R_BAL) {
+        const double sr = (rp - r) * it1 + da;
+        st2 += sr * sr;
+      }
+      if (MODE == 1) {
+        const double s0 = ((double)Q.x0[o] - x0) * it1 + da;
+        st2 += s0 * s0;
+      }
+      if (MODE != 0) {
+        const double s1 = ((double)Q.x1[o] - x1) * it1 - da;
+        st2 += s1 * s1;
+      }
+      acc[S_PRES2] += kz * kz;
+      acc[S_STAT2] += st2;
+      acc[S_KA2] += gxx * gxx + gyy * gyy + nid * a * a;
+      acc[S_X0SQ] += x0 * x0;
+      acc[S_X1SQ] += x1 * x1;
+      acc[S_MNORM] += sqrt(mx * mx + my * my);
+      if (RES == R_P1) {
+        acc[S_RPEN] += fabs(r);
+        acc[S_EPEN] += fabs(e);
+      } else if (RES == R_P2) {
+        acc[S_RPEN] += r * r;
+        acc[S_EPEN] += e * e;
+      }
+      if (MODE == 0) acc[S_LIN] += a * (double)A.c[o];
+      if (MODE == 2) acc[S_LIN] -= a * (double)A.src[o];
+      if (MODE == 1) {
+        const double d0 = x0 - (double)A.src[o], d1 = x1 - (double)A.dst[o];
+        acc[S_QUAD] += d0 * d0 + d1 * d1;
+      }
+      if (MODE == 2) {
+        const double d1 = x1 - (double)A.dst[o];
+        acc[S_QUAD] += d1 * d1;
+      }
+      acc[S_MAXG] = fmax(acc[S_MAXG], sqrt(gxx * gxx + gyy * gyy));
+      acc[S_MAXA] = fmax(acc[S_MAXA], fabs(a));
+      const bool fin = isfinite(a) && isfinite(mx) && isfinite(my) && isfinite(r) && isfinite(x0) &&
+                       isfinite(x1);
+      acc[S_NONFIN] += fin ? 0.0 : 1.0;
+      acc[S_A2] += a * a;
+      acc[S_SUMA] += a;
+    }
+    block_reduce_store(acc, kMaxSlotsCheck, A.partial + (long)t * NS);
+  }
+}
+
+// Input validation, c = q - p, and state initialisation (K8).
+__global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
+  const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+    const Tile tl = A.tiles[t];
+    const PairInfo P = A.pairs[tl.pair];
+    const int nx = P.nx, ny = P.ny;
+    double acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int ly = wv; ly < A.tile_rows; ly += 4) {
+      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const long o = P.off + (long)gy * nx + gx;
+      const float s = A.src[o], d = A.dst[o];
+      acc[U_NONFIN_IN] += (isfinite(s) ? 0.0 : 1.0) + (isfinite(d) ? 0.0 : 1.0);
+      acc[U_NEG] += (s < 0.f ? 1.0 : 0.0) + (d < 0.f ? 1.0 : 0.0);
+      acc[U_SUMS] += s;
+      acc[U_SUMD] += d;
+      acc[U_SQS] += (double)s * s;
+      acc[U_SQD] += (double)d * d;
+      if (A.mode == 0 && A.write_c) A.c[o] = d - s;
+      const bool zx = (A.bc == 0 && gx == nx - 1), zy = (A.bc == 0 && gy == ny - 1);
+      if (!A.warm) {
+        if (A.write_state) {
+          A.st.Mx[o] = 0.f;
+          A.st.My[o] = 0.f;
+          A.st.a[o] = 0.f;
+          if (A.resid != R_BAL) A.st.r[o] = 0.f;
+          if (A.mode == 1) A.st.x0[o] = 0.f;
+          if (A.mode != 0) A.st.x1[o] = 0.f;
+        }
+      } else {
+        const float mx = A.st.Mx[o], my = A.st.My[o], a = A.st.a[o];
+        bool fin = isfinite(mx) && isfinite(my) && isfinite(a);
+        if (A.resid != R_BAL) fin = fin && isfinite(A.st.r[o]);
+        if (A.mode == 1) fin = fin && isfinite(A.st.x0[o]);
+        if (A.mode != 0) fin = fin && isfinite(A.st.x1[o]);
+        acc[U_NONFIN_ST] += fin ? 0.0 : 1.0;
+        if (A.write_state) {
+          if (zx) A.st.Mx[o] = 0.f;
+          if (zy) A.st.My[o] = 0.f;
+        }
+      }
+    }
+    block_reduce_store(acc, 0u, A.partial + (long)t * NS);
+  }
+}
+
+// Per-pair sums of tile partials in a fixed order (deterministic).
+__global__ __launch_bounds__(BLOCK) void pair_reduce_kernel(const PairInfo* pairs, const double* partial,
+                                                            uint32_t max_mask, double* sums) {
+  const int b = blockIdx.x;
+  const PairInfo P = pairs[b];
+  double acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+  for (int t = threadIdx.x; t < P.tile_count; t += BLOCK) {
+    const double* row = partial + (long)(P.tile_begin + t) * NS;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bool mx = (max_mask >> s) & 1u;
+      acc[s] = mx ? fmax(acc[s], row[s]) : acc[s] + row[s];
+    }
+  }
+  block_reduce_store(acc, max_mask, sums + (long)b * NS);
+}
+
+// Device-side stopping decision after a window of W iterations.
+__global__ __launch_bounds__(BLOCK) void decide_kernel(DecideArgs A) {
+  __shared__ int cnt[BLOCK];
+  int mine = 0;
+  for (int b = threadIdx.x; b < A.B; b += BLOCK) {
+    if (A.active[b]) {
+      A.iters[b] += A.W;
+      const double* S = A.sums + (long)b * NS;
+      bool done = false;
+      if (A.check) {
+        const double xn = A.mode == 0 ? A.xnorm[b] : sqrt(S[S_X0SQ]) + sqrt(S[S_X1SQ]);
+        const double p = sqrt(S[S_PRES2]) / fmax(xn, 1e-30);
+        const double d = sqrt(S[S_STAT2]) / fmax(sqrt(S[S_KA2]), 1e-30);
+        const double rel = fmax(p, d);
+        A.rel_res[b] = rel;
+        if (S[S_NONFIN] > 0.0 || !isfinite(rel)) {
+          A.status[b] = 2;
+          done = true;
+        } else if (A.tol > 0.0 && rel <= A.tol) {
+          A.status[b] = 0;
+          done = true;
+        }
+        if (!done && A.adaptive && !A.final_pass) {
+          // residual balancing: keep tau1*tau2, move the ratio toward the
+          // side whose relative residual lags
+          PairInfo& P = A.pairs[b];
+          const double al = A.alpha[b];
+          double t1 = P.tau1, t2 = P.tau2;
+          bool ch = false;
+          if (d > 1.5 * p) {
+            t1 /= (1.0 - al);
+            t2 *= (1.0 - al);
+            ch = true;
+          } else if (p > 1.5 * d) {
+            t1 *= (1.0 - al);
+            t2 /= (1.0 - al);
+            ch = true;
+          }
+          if (ch) {
+            A.alpha[b] = al * 0.95;
+            P.tau1 = (float)t1;
+            P.tau2 = (float)t2;
+            P.theta = A.mode == 0 ? 0.f : (float)(t1 / (A.rho + t1));
+            P.mutau = (float)(A.mu * t1);
+            P.inv2mt = (float)(1.0 / (1.0 + 2.0 * A.mu * t1));
+          }
+        }
+      }
+      if (!done && (A.final_pass || A.iters[b] >= A.max_iter)) {
+        A.status[b] = 1;
+        done = true;
+      }
+      if (done) A.active[b] = 0;
+      else ++mine;
+    }
+  }
+  cnt[threadIdx.x] = mine;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *A.n_active = cnt[0];
+}
+
+// Copies the current iterate from src to dst for pairs still active.
+__global__ __launch_bounds__(BLOCK) void copy_active_kernel(Planes dst, Planes src, const PairInfo* pairs,
+                                                            const Tile* tiles, int ntiles, int tile_rows,
+                                                            const int32_t* active) {
+  const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    if (!active[tl.pair]) continue;
+    const PairInfo P = pairs[tl.pair];
+    for (int ly = wv; ly < tile_rows; ly += 4) {
+      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
+      if (gx >= P.nx || gy >= P.ny) continue;
+      const long o = P.off + (long)gy * P.nx + gx;
+      dst.Mx[o] = src.Mx[o];
+      dst.My[o] = src.My[o];
+      dst.a[o] = src.a[o];
+      if (dst.r) dst.r[o] = src.r[o];
+      if (dst.x0) dst.x0[o] = src.x0[o];
+      if (dst.x1) dst.x1[o] = src.x1[o];
+    }
+  }
+}
+
+// Dual value of the scaled multiplier a/s for the PROX modes: the infimum
+// over x >= 0 of the Lagrangian's x terms has the closed-form minimisers
+// max(p0 + rho a, 0) and max(p1 - rho a, 0).
+__global__ __launch_bounds__(BLOCK) void dual_kernel(DualArgs A) {
+  const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+    const Tile tl = A.tiles[t];
+    const PairInfo P = A.pairs[tl.pair];
+    const double is = A.inv_s[tl.pair];
+    const double rho = A.rho;
+    double acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int ly = wv; ly < A.tile_rows; ly += 4) {
+      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
+      if (gx >= P.nx || gy >= P.ny) continue;
+      const long o = P.off + (long)gy * P.nx + gx;
+      const double ah = (double)A.a[o] * is;
+      double v = 0.0;
+      const double p1 = A.x_dst[o];
+      const double x1s = fmax(p1 - rho * ah, 0.0);
+      v += (x1s - p1) * (x1s - p1) / (2.0 * rho) + ah * x1s;
+      if (A.mode == 1) {
+        const double p0 = A.x_src[o];
+        const double x0s = fmax(p0 + rho * ah, 0.0);
+        v += (x0s - p0) * (x0s - p0) / (2.0 * rho) - ah * x0s;
+      } else {
+        v -= ah * (double)A.x_src[o];
+      }
+      if (A.resid == R_P2) v -= ah * ah / (4.0 * (double)A.mu);
+      acc[0] += v;
+    }
+    block_reduce_store(acc, 0u, A.partial + (long)t * NS);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+namespace {
+template <int MODE, int RES, int BC>
+hipError_t iter_by_ty(int ty, int grid, const IterArgs& a, hipStream_t s) {
+  switch (ty) {
+    case 4: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 16>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 32>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE, int RES, int BC>
+hipError_t occ_by_ty(int ty, int* n) {
+  switch (ty) {
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 4>, BLOCK, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 8>, BLOCK, 0);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 16>, BLOCK, 0);
+    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 32>, BLOCK, 0);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE, int RES>
+hipError_t iter_bc(int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
+  return bc == 0 ? iter_by_ty<MODE, RES, 0>(ty, grid, a, s) : iter_by_ty<MODE, RES, 1>(ty, grid, a, s);
+}
+template <int MODE>
+hipError_t iter_res(int res, int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
+  switch (res) {
+    case R_BAL: return iter_bc<MODE, R_BAL>(bc, ty, grid, a, s);
+    case R_P1: return iter_bc<MODE, R_P1>(bc, ty, grid, a, s);
+    case R_P2: return iter_bc<MODE, R_P2>(bc, ty, grid, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int MODE, int RES>
+hipError_t occ_bc(int bc, int ty, int* n) {
+  return bc == 0 ? occ_by_ty<MODE, RES, 0>(ty, n) : occ_by_ty<MODE, RES, 1>(ty, n);
+}
+template <int MODE>
+hipError_t occ_res(int res, int bc, int ty, int* n) {
+  switch (res) {
+    case R_BAL: return occ_bc<MODE, R_BAL>(bc, ty, n);
+    case R_P1: return occ_bc<MODE, R_P1>(bc, ty, n);
+    case R_P2: return occ_bc<MODE, R_P2>(bc, ty, n);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int MODE, int RES>
+hipError_t check_bc(int bc, int grid, const CheckArgs& a, hipStream_t s) {
+  if (bc == 0) hipLaunchKernelGGL((check_kernel<MODE, RES, 0>), dim3(grid), dim3(BLOCK), 0, s, a);
+  else hipLaunchKernelGGL((check_kernel<MODE, RES, 1>), dim3(grid), dim3(BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+template <int MODE>
+hipError_t check_res(int res, int bc, int grid, const CheckArgs& a, hipStream_t s) {
+  switch (res) {
+    case R_BAL: return check_bc<MODE, R_BAL>(bc, grid, a, s);
+    case R_P1: return check_bc<MODE, R_P1>(bc, grid, a, s);
+    case R_P2: return check_bc<MODE, R_P2>(bc, grid, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_iter(int mode, int resid, int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
+  switch (mode) {
+    case 0: return iter_res<0>(resid, bc, ty, grid, a, s);
+    case 1: return iter_res<1>(resid, bc, ty, grid, a, s);
+    case 2: return iter_res<2>(resid, bc, ty, grid, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* n) {
+  switch (mode) {
+    case 0: return occ_res<0>(resid, bc, ty, n);
+    case 1: return occ_res<1>(resid, bc, ty, n);
+    case 2: return occ_res<2>(resid, bc, ty, n);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_check(int mode, int resid, int bc, int grid, const CheckArgs& a, hipStream_t s) {
+  switch (mode) {
+    case 0: return check_res<0>(resid, bc, grid, a, s);
+    case 1: return check_res<1>(resid, bc, grid, a, s);
+    case 2: return check_res<2>(resid, bc, grid, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_setup(int grid, const SetupArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(setup_kernel, dim3(grid), dim3(BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_reduce(const PairInfo* pairs, int B, const double* partial, uint32_t max_mask,
+                              double* sums, hipStream_t s) {
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3(B), dim3(BLOCK), 0, s, pairs, partial, max_mask, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_active(const Planes& dst, const Planes& src, const PairInfo* pairs, const Tile* tiles,
+                              int ntiles, int tile_rows, const int32_t* active, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(copy_active_kernel, dim3(grid), dim3(BLOCK), 0, s, dst, src, pairs, tiles, ntiles,
+                     tile_rows, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual(int grid, const DualArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(dual_kernel, dim3(grid), dim3(BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace uot

@@ -1,0 +1,179 @@
+"""Python binding of libuot (torch tensors in, argument marshalling only).
+
+Every step of the solve runs in the HIP kernels behind the C ABI of
+include/uot.h; PyTorch supplies device memory and the stream.  There is no
+CPU fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, fields
+
+import torch
+
+from . import _lib
+from ._lib import (UOT_WARM_START, UOT_ALLOW_SIGNED, UOT_UNSAFE_STEPS, UOT_NO_GRAPH,  # noqa: F401
+                   UOT_AUTOTUNE, UOT_ADAPTIVE_STEPS)
+
+DIST, PROX, PROX_FIXED = 0, 1, 2
+PLANES = ("Mx", "My", "r", "a", "x0", "x1")
+
+
+class UOTError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = int(code)
+        msg = _lib.load().uot_status_string(self.code).decode()
+        super().__init__(f"{where}: {msg} (status {self.code})")
+
+
+@dataclass
+class Params:
+    """Fields of uot_params (include/uot.h)."""
+    nx: int = 0
+    ny: int = 0
+    mode: int = DIST
+    balanced: bool = False
+    residual_p: int = 1
+    bc: int = 0
+    mu: float = 1.0
+    rho: float = 1.0
+    tau1: float = 0.0
+    tau2: float = 0.0
+    max_iter: int = 1000
+    check_every: int = 20
+    tol: float = 0.0
+    flags: int = 0
+    tile_rows: int = 0
+
+    def to_c(self):
+        return _lib.Params(**{f.name: (int(getattr(self, f.name)) if f.type in ("int", "bool")
+                                       else getattr(self, f.name)) for f in fields(self)})
+
+
+def check_params(p: Params) -> int:
+    """uot_check_params: validates without touching the GPU (0 = OK)."""
+    c = p.to_c()
+    return int(_lib.load().uot_check_params(ctypes.byref(c)))
+
+
+def knorm2(nx, ny, mode=DIST, balanced=False, bc=0) -> float:
+    return float(_lib.load().uot_knorm2(nx, ny, mode, int(balanced), bc))
+
+
+def required_planes(mode, balanced):
+    req = ["Mx", "My", "a"] + ([] if balanced else ["r"])
+    if mode == PROX:
+        req += ["x0", "x1"]
+    elif mode == PROX_FIXED:
+        req += ["x1"]
+    return req
+
+
+def new_state(mode, balanced, numel_or_shape, device="cuda"):
+    """Zeroed caller-owned state planes for a mode."""
+    return {k: torch.zeros(numel_or_shape, dtype=torch.float32, device=device)
+            for k in required_planes(mode, balanced)}
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("planes must be contiguous float32 device tensors")
+    return t.data_ptr()
+
+
+def _cstate(st):
+    return _lib.State(*[_ptr(st.get(k)) for k in PLANES])
+
+
+class Solver:
+    """One handle of the C ABI bound to the current device and stream."""
+
+    def __init__(self, params: Params, stream=None):
+        self.lib = _lib.load()
+        self.params = params
+        self._c = params.to_c()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.uot_create(ctypes.byref(self._c), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise UOTError(rc, "uot_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.uot_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, src, dst, state=None):
+        """uot_solve on images of shape (ny, nx); returns (state, report)."""
+        p = self.params
+        if state is None:
+            state = new_state(p.mode, p.balanced, src.shape, src.device)
+        cs = _cstate(state)
+        rep = _lib.Report()
+        rc = self.lib.uot_solve(self._h, _ptr(src), _ptr(dst), ctypes.byref(cs), ctypes.byref(rep))
+        if rc != 0:
+            raise UOTError(rc, "uot_solve")
+        return state, rep.as_dict()
+
+    def solve_batched(self, src, dst, nx, ny, offset, state=None):
+        """uot_solve_batched on packed 1-D planes; returns (state, [reports])."""
+        p = self.params
+        B = len(nx)
+        if state is None:
+            state = new_state(p.mode, p.balanced, src.numel(), src.device)
+        ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
+        ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
+        ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+        reps = (_lib.Report * B)()
+        cs = _cstate(state)
+        rc = self.lib.uot_solve_batched(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs), reps)
+        if rc != 0:
+            raise UOTError(rc, "uot_solve_batched")
+        return state, [r.as_dict() for r in reps]
+
+    def time_iterations(self, src, dst, state, n):
+        """uot_time_iterations: average ms per fused-iteration launch."""
+        cs = _cstate(state)
+        ms = ctypes.c_double()
+        rc = self.lib.uot_time_iterations(self._h, _ptr(src), _ptr(dst), ctypes.byref(cs), int(n), ctypes.byref(ms))
+        if rc != 0:
+            raise UOTError(rc, "uot_time_iterations")
+        return ms.value
+
+    def objective(self, src, dst, state, prev=None):
+        cs = _cstate(state)
+        cp = _cstate(prev) if prev is not None else None
+        rep = _lib.Report()
+        rc = self.lib.uot_objective(self._h, _ptr(src), _ptr(dst), ctypes.byref(cs),
+                                    ctypes.byref(cp) if cp is not None else None, ctypes.byref(rep))
+        if rc != 0:
+            raise UOTError(rc, "uot_objective")
+        return rep.as_dict()
+
+
+def pack(images):
+    """Packs a list of (ny, nx) tensors into one flat plane; returns
+    (packed, nx list, ny list, offsets)."""
+    nx = [int(t.shape[1]) for t in images]
+    ny = [int(t.shape[0]) for t in images]
+    offs, o = [], 0
+    for a, b in zip(nx, ny):
+        offs.append(o)
+        o += a * b
+    flat = torch.cat([t.reshape(-1) for t in images]) if images else torch.zeros(0)
+    return flat.contiguous(), nx, ny, offs
+
+
+def unpack(flat, nx, ny, offsets):
+    return [flat[o:o + a * b].view(b, a) for a, b, o in zip(nx, ny, offsets)]
