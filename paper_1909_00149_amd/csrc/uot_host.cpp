@@ -283,7 +283,8 @@ uot_status validate_state(const uot_params& p, const uot_state* s) {
   return UOT_OK;
 }
 
-uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset, Job& J) {
+uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset, Job& J,
+                int force_ty = 0, bool* cached = nullptr) {
   const uot_params& p = h->prm;
   if (B < 1 || !nx || !ny || !offset) return UOT_ERR_ARG;
   J.B = B;
@@ -303,11 +304,13 @@ uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, cons
   J.total_px = total;
   const int resid = resid_of(p);
   // tile rows: explicit, autotuned, or heuristic
-  int ty = p.tile_rows;
+  int ty = force_ty > 0 ? force_ty : p.tile_rows;
+  if (cached) *cached = true;
   if (ty == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tune_cache.find(tune_key(p.mode, resid, p.bc, total));
+    if (cached) *cached = it != g_tune_cache.end();
     ty = it != g_tune_cache.end() ? it->second : heuristic_rows(total);
   }
   J.ty = ty;
@@ -514,8 +517,7 @@ uot_status enqueue_window(Launch& L, int W, bool check) {
     HIPCHK(launch_iter(p.mode, L.resid, p.bc, L.J->ty, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
   if (check) {
     HIPCHK(launch_check(p.mode, L.resid, p.bc, L.grid_aux, L.chk, h->stream));
-    HIPCHK(launch_pair_reduce(h->d_pairs, L.J->B, h->d_partial, kMaxSlotsCheck, h->d_sums, h->stream));
-    HIPCHK(launch_decide(L.dec, h->stream));
+    HIPCHK(launch_reduce_decide(L.dec, h->d_partial, h->stream));
   }
   return UOT_OK;
 }
@@ -563,6 +565,68 @@ uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
   return UOT_OK;
 }
 
+// Autotuner: times every tile shape on this very workload (the caller's
+// state after setup is read, the shadow copy is written, nothing else
+// changes), keeps the fastest for the (mode, variant, boundary, size class)
+// key, persists the table to $UOT_AUTOTUNE_CACHE when set, and re-plans J.
+uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
+                    const float* src, const float* dst, uot_state* st, Job& J) {
+  const uot_params& p = h->prm;
+  const int resid = resid_of(p);
+  const int cand[4] = {4, 8, 16, 32};
+  Job J4;
+  uot_status s = plan(h, B, nx, ny, offset, J4, 4);
+  if (s != UOT_OK) return s;
+  s = ensure_workspace(h, J4);  // the 4-row list is the longest
+  if (s != UOT_OK) return s;
+  std::vector<int32_t> ones(B, 1);
+  HIPCHK(hipMemcpyAsync(h->d_i32, ones.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  const Planes A = planes_of(*st), Bp = shadow_planes(h);
+  const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_ty = J.ty;
+  for (int ty : cand) {
+    Job Jt;
+    s = plan(h, B, nx, ny, offset, Jt, ty);
+    if (s != UOT_OK) break;
+    HIPCHK(hipMemcpyAsync(h->d_pairs, Jt.pairs.data(), B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+    s = upload_live(h, Jt, ones.data());
+    if (s != UOT_OK) break;
+    const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
+    const int grid = iter_grid(h, p.mode, resid, p.bc, ty, (int)Jt.tiles.size());
+    for (int i = 0; i < 2; ++i) HIPCHK(launch_iter(p.mode, resid, p.bc, ty, grid, fwd, h->stream));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int i = 0; i < 10; ++i) HIPCHK(launch_iter(p.mode, resid, p.bc, ty, grid, fwd, h->stream));
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_ty = ty;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != UOT_OK) return s;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tune_key(p.mode, resid, p.bc, J.total_px)] = best_ty;
+    tune_store_locked();
+  }
+  s = plan(h, B, nx, ny, offset, J, best_ty);
+  if (s != UOT_OK) return s;
+  s = ensure_workspace(h, J);
+  if (s != UOT_OK) return s;
+  HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return UOT_OK;
+}
+
 uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
                       const float* src, const float* dst, uot_state* st, uot_report* reps) {
   Timer timer;
@@ -571,7 +635,8 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   uot_status s = validate_state(p, st);
   if (s != UOT_OK) return s;
   Job J;
-  s = plan(h, B, nx, ny, offset, J);
+  bool cached = true;
+  s = plan(h, B, nx, ny, offset, J, 0, &cached);
   if (s != UOT_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
   s = ensure_workspace(h, J);
@@ -585,6 +650,10 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   if (s != UOT_OK) return s;
   s = check_setup_sums(h, J, warm);
   if (s != UOT_OK) return s;
+  if ((p.flags & UOT_AUTOTUNE) && p.tile_rows == 0 && !cached) {
+    s = autotune(h, B, nx, ny, offset, src, dst, st, J);
+    if (s != UOT_OK) return s;
+  }
 
   // per-pair host bookkeeping
   int32_t* h_active = h->h_i32;
@@ -607,7 +676,6 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   int32_t* d_active = h->d_i32;
   int32_t* d_iters = h->d_i32 + B;
   int32_t* d_status = h->d_i32 + 2 * B;
-  int32_t* d_nact = h->d_i32 + 3 * B;
   double* d_rel = h->d_f64;
   double* d_xn = h->d_f64 + B;
   double* d_alpha = h->d_f64 + 2 * B;
@@ -635,7 +703,7 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   int W = std::max(2, p.check_every > 0 ? p.check_every : 20);
   W += W & 1;
   const bool adaptive = check && (p.flags & UOT_ADAPTIVE_STEPS);
-  L.dec = DecideArgs{h->d_pairs, h->d_sums, d_xn, d_active, d_iters, d_status, d_rel, d_nact, B, W,
+  L.dec = DecideArgs{h->d_pairs, h->d_sums, d_xn, d_active, d_iters, d_status, d_rel, B, W,
                      p.max_iter, check ? 1 : 0, 0, p.mode, n_identity(p.mode, p.balanced), p.tol,
                      adaptive ? 1 : 0, d_alpha, p.mu, p.rho};
 
@@ -665,11 +733,11 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
     w += burst;
     done_iters += burst * W;
     if (check) {
-      HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t) + sizeof(int32_t) * 0,
-                            hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(hipMemcpyAsync(&h->h_i32[(size_t)B * 3], d_nact, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
-      const int now = h->h_i32[(size_t)B * 3];
+      int now = 0;
+      for (int b = 0; b < B; ++b) now += h_active[b] ? 1 : 0;
       if (now == 0) {
         n_active = 0;
         break;
@@ -698,7 +766,6 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   fin.swap_active = odd ? 1 : 0;
   fin.all_pairs = 1;
   HIPCHK(launch_check(p.mode, resid, p.bc, L.grid_aux, fin, h->stream));
-  HIPCHK(launch_pair_reduce(h->d_pairs, B, h->d_partial, kMaxSlotsCheck, h->d_sums, h->stream));
   DecideArgs fd = L.dec;
   fd.W = check ? (run_tail ? tail : 0) : (done_iters + (run_tail ? tail : 0));
   fd.check = 1;
@@ -710,9 +777,9 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
     HIPCHK(launch_copy_active(A, Bp, h->d_pairs, h->d_tiles, (int)J.tiles.size(), J.ty, d_active, L.grid_aux,
                               h->stream));
   }
-  // Pairs that stopped in an earlier window keep their recorded rel_res; the
+  // Pairs that stopped in an earlier window keep their recorded status; the
   // final decision re-evaluates only still-active pairs.
-  HIPCHK(launch_decide(fd, h->stream));
+  HIPCHK(launch_reduce_decide(fd, h->d_partial, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, (size_t)B * NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(relres.data(), d_rel, B * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -105,13 +105,12 @@ struct SetupArgs {
 
 struct DecideArgs {
   PairInfo* pairs;      // steps are rewritten when adaptive
-  const double* sums;   // [B][NS]
+  double* sums;         // [B][NS], written by the fused reduction
   const double* xnorm;  // DIST: ||p|| + ||q|| per pair; other modes: unused
   int32_t* active;
   int32_t* iters;
   int32_t* status;
   double* rel_res;
-  int32_t* n_active;
   int32_t B;
   int32_t W;          // iterations since the last decision
   int32_t max_iter;
@@ -143,7 +142,8 @@ hipError_t launch_check(int mode, int resid, int bc, int grid, const CheckArgs& 
 hipError_t launch_setup(int grid, const SetupArgs& a, hipStream_t s);
 hipError_t launch_pair_reduce(const PairInfo* pairs, int B, const double* partial, uint32_t max_mask,
                               double* sums, hipStream_t s);
-hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
+// per-pair reduction of check partials fused with the stopping decision
+hipError_t launch_reduce_decide(const DecideArgs& a, const double* partial, hipStream_t s);
 hipError_t launch_copy_active(const Planes& dst, const Planes& src, const PairInfo* pairs,
                               const Tile* tiles, int ntiles, int tile_rows, const int32_t* active,
                               int grid, hipStream_t s);

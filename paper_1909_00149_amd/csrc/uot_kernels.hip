@@ -195,8 +195,10 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Block reduction of NS double slots into one partial row.
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst) {
+// Block reduction of NS double slots into one partial row (and, if fin is
+// given, into that LDS row too, visible to the whole block on return).
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst,
+                                                   double* fin = nullptr) {
   __shared__ double red[BLOCK / 64][NS];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -216,16 +218,18 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t m
     double v = red[0][s];
     for (int w = 1; w < BLOCK / 64; ++w) v = mx ? fmax(v, red[w][s]) : v + red[w][s];
     dst[s] = v;
+    if (fin) fin[s] = v;
   }
   __syncthreads();
 }
 
 // Residuals and certificate terms of the current iterate (K2).  Direct
-// global loads; neighbours come from the L2.  Runs once per check window.
+// global loads; neighbours come from the L2.  Per-pixel terms in FP32,
+// sums over pixels in FP64.  Runs once per check window.
 template <int MODE, int RES, int BC>
 __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
   const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
+  constexpr float nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
   for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
     const Tile tl = A.tiles[t];
     const bool act = A.active[tl.pair] != 0;
@@ -235,8 +239,7 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
     const Planes C = swap ? A.B : A.A;
     const Planes Q = swap ? A.A : A.B;  // previous iterate
     const int nx = P.nx, ny = P.ny;
-    const float tau1 = P.tau1;
-    const double it1 = 1.0 / (double)tau1;
+    const float it1 = 1.f / P.tau1;
     double acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = 0.0;
@@ -246,76 +249,77 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
       const long o = P.off + (long)gy * nx + gx;
       const bool hasR = gx + 1 < nx, hasU = gy + 1 < ny;
       const bool hasL = gx > 0, hasD = gy > 0;
-      const double a = C.a[o], ap = Q.a[o];
-      const double aR = hasR ? (double)C.a[o + 1] : 0.0, apR = hasR ? (double)Q.a[o + 1] : 0.0;
-      const double aU = hasU ? (double)C.a[o + nx] : 0.0, apU = hasU ? (double)Q.a[o + nx] : 0.0;
-      double gxx = a - aR, gyy = a - aU;
-      double dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
+      const float a = C.a[o], ap = Q.a[o];
+      const float aR = hasR ? C.a[o + 1] : 0.f, apR = hasR ? Q.a[o + 1] : 0.f;
+      const float aU = hasU ? C.a[o + nx] : 0.f, apU = hasU ? Q.a[o + nx] : 0.f;
+      float gxx = a - aR, gyy = a - aU;
+      float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
       const bool zx = (BC == 0 && gx == nx - 1), zy = (BC == 0 && gy == ny - 1);
-      if (zx) gxx = dgx = 0.0;
-      if (zy) gyy = dgy = 0.0;
-      const double mx = zx ? 0.0 : (double)C.Mx[o], my = zy ? 0.0 : (double)C.My[o];
-      const double mxp = zx ? 0.0 : (double)Q.Mx[o], myp = zy ? 0.0 : (double)Q.My[o];
-      const double mxl = hasL ? (double)C.Mx[o - 1] : 0.0;
-      const double myd = hasD ? (double)C.My[o - nx] : 0.0;
-      const double dm = mx - mxl + my - myd;
-      double x0 = 0.0, x1 = 0.0, e;
+      if (zx) gxx = dgx = 0.f;
+      if (zy) gyy = dgy = 0.f;
+      const float mx = zx ? 0.f : C.Mx[o], my = zy ? 0.f : C.My[o];
+      const float mxp = zx ? 0.f : Q.Mx[o], myp = zy ? 0.f : Q.My[o];
+      const float mxl = hasL ? C.Mx[o - 1] : 0.f;
+      const float myd = hasD ? C.My[o - nx] : 0.f;
+      const float dm = (mx - mxl) + (my - myd);
+      float x0 = 0.f, x1 = 0.f, e;
       if (MODE == 0) {
-        e = dm + (double)A.c[o];
+        e = dm + A.c[o];
       } else if (MODE == 1) {
         x0 = C.x0[o];
         x1 = C.x1[o];
         e = dm - x0 + x1;
       } else {
         x1 = C.x1[o];
-        e = dm - (double)A.src[o] + x1;
+        e = dm - A.src[o] + x1;
       }
-      double r = 0.0, rp = 0.0;
+      float r = 0.f, rp = 0.f;
       if (RES != R_BAL) {
         r = C.r[o];
         rp = Q.r[o];
       }
-      const double kz = e - r;
-      const double da = ap - a;
-      const double sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
-      double st2 = sx * sx + sy * sy;
+      const float kz = e - r;
+      const float da = ap - a;
+      const float sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
+      float st2 = sx * sx + sy * sy;
       if (RES != R_BAL) {
-        const double sr = (rp - r) * it1 + da;
+        const float sr = (rp - r) * it1 + da;
         st2 += sr * sr;
       }
       if (MODE == 1) {
-        const double s0 = ((double)Q.x0[o] - x0) * it1 + da;
+        const float s0 = (Q.x0[o] - x0) * it1 + da;
         st2 += s0 * s0;
       }
       if (MODE != 0) {
-        const double s1 = ((double)Q.x1[o] - x1) * it1 - da;
+        const float s1 = (Q.x1[o] - x1) * it1 - da;
         st2 += s1 * s1;
       }
+      const float g2 = gxx * gxx + gyy * gyy;
       acc[S_PRES2] += kz * kz;
       acc[S_STAT2] += st2;
-      acc[S_KA2] += gxx * gxx + gyy * gyy + nid * a * a;
+      acc[S_KA2] += g2 + nid * a * a;
       acc[S_X0SQ] += x0 * x0;
       acc[S_X1SQ] += x1 * x1;
-      acc[S_MNORM] += sqrt(mx * mx + my * my);
+      acc[S_MNORM] += sqrtf(mx * mx + my * my);
       if (RES == R_P1) {
-        acc[S_RPEN] += fabs(r);
-        acc[S_EPEN] += fabs(e);
+        acc[S_RPEN] += fabsf(r);
+        acc[S_EPEN] += fabsf(e);
       } else if (RES == R_P2) {
         acc[S_RPEN] += r * r;
         acc[S_EPEN] += e * e;
       }
-      if (MODE == 0) acc[S_LIN] += a * (double)A.c[o];
-      if (MODE == 2) acc[S_LIN] -= a * (double)A.src[o];
+      if (MODE == 0) acc[S_LIN] += a * A.c[o];
+      if (MODE == 2) acc[S_LIN] -= a * A.src[o];
       if (MODE == 1) {
-        const double d0 = x0 - (double)A.src[o], d1 = x1 - (double)A.dst[o];
+        const float d0 = x0 - A.src[o], d1 = x1 - A.dst[o];
         acc[S_QUAD] += d0 * d0 + d1 * d1;
       }
       if (MODE == 2) {
-        const double d1 = x1 - (double)A.dst[o];
+        const float d1 = x1 - A.dst[o];
         acc[S_QUAD] += d1 * d1;
       }
-      acc[S_MAXG] = fmax(acc[S_MAXG], sqrt(gxx * gxx + gyy * gyy));
-      acc[S_MAXA] = fmax(acc[S_MAXA], fabs(a));
+      acc[S_MAXG] = fmax(acc[S_MAXG], (double)sqrtf(g2));
+      acc[S_MAXA] = fmax(acc[S_MAXA], (double)fabsf(a));
       const bool fin = isfinite(a) && isfinite(mx) && isfinite(my) && isfinite(r) && isfinite(x0) &&
                        isfinite(x1);
       acc[S_NONFIN] += fin ? 0.0 : 1.0;
@@ -375,11 +379,67 @@ __global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
   }
 }
 
-// Per-pair sums of tile partials in a fixed order (deterministic).
+// Stopping decision for pair b after a window of W iterations (device side,
+// so that captured windows need no host round trip).
+__device__ void decide_pair(const DecideArgs& A, int b, const double* S) {
+  if (!A.active[b]) return;
+  A.iters[b] += A.W;
+  bool done = false;
+  if (A.check) {
+    const double xn = A.mode == 0 ? A.xnorm[b] : sqrt(S[S_X0SQ]) + sqrt(S[S_X1SQ]);
+    const double p = sqrt(S[S_PRES2]) / fmax(xn, 1e-30);
+    const double d = sqrt(S[S_STAT2]) / fmax(sqrt(S[S_KA2]), 1e-30);
+    const double rel = fmax(p, d);
+    A.rel_res[b] = rel;
+    if (S[S_NONFIN] > 0.0 || !isfinite(rel)) {
+      A.status[b] = 2;
+      done = true;
+    } else if (A.tol > 0.0 && rel <= A.tol) {
+      A.status[b] = 0;
+      done = true;
+    }
+    if (!done && A.adaptive && !A.final_pass) {
+      // residual balancing: keep tau1*tau2, move the ratio toward the side
+      // whose relative residual lags
+      PairInfo& P = A.pairs[b];
+      const double al = A.alpha[b];
+      double t1 = P.tau1, t2 = P.tau2;
+      bool ch = false;
+      if (d > 1.5 * p) {
+        t1 /= (1.0 - al);
+        t2 *= (1.0 - al);
+        ch = true;
+      } else if (p > 1.5 * d) {
+        t1 *= (1.0 - al);
+        t2 /= (1.0 - al);
+        ch = true;
+      }
+      if (ch) {
+        A.alpha[b] = al * 0.95;
+        P.tau1 = (float)t1;
+        P.tau2 = (float)t2;
+        P.theta = A.mode == 0 ? 0.f : (float)(t1 / (A.rho + t1));
+        P.mutau = (float)(A.mu * t1);
+        P.inv2mt = (float)(1.0 / (1.0 + 2.0 * A.mu * t1));
+      }
+    }
+  }
+  if (!done && (A.final_pass || A.iters[b] >= A.max_iter)) {
+    A.status[b] = 1;
+    done = true;
+  }
+  if (done) A.active[b] = 0;
+}
+
+// Per-pair sums of tile partials in a fixed order (deterministic); with
+// do_decide, thread 0 then takes the pair's stopping decision.
 __global__ __launch_bounds__(BLOCK) void pair_reduce_kernel(const PairInfo* pairs, const double* partial,
-                                                            uint32_t max_mask, double* sums) {
+                                                            uint32_t max_mask, double* sums, DecideArgs dec,
+                                                            int do_decide) {
   const int b = blockIdx.x;
   const PairInfo P = pairs[b];
+  // uniform: a stopped pair keeps its record; the final pass still sums it
+  if (do_decide && !dec.active[b] && !dec.final_pass) return;
   double acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = 0.0;
@@ -391,72 +451,9 @@ __global__ __launch_bounds__(BLOCK) void pair_reduce_kernel(const PairInfo* pair
       acc[s] = mx ? fmax(acc[s], row[s]) : acc[s] + row[s];
     }
   }
-  block_reduce_store(acc, max_mask, sums + (long)b * NS);
-}
-
-// Device-side stopping decision after a window of W iterations.
-__global__ __launch_bounds__(BLOCK) void decide_kernel(DecideArgs A) {
-  __shared__ int cnt[BLOCK];
-  int mine = 0;
-  for (int b = threadIdx.x; b < A.B; b += BLOCK) {
-    if (A.active[b]) {
-      A.iters[b] += A.W;
-      const double* S = A.sums + (long)b * NS;
-      bool done = false;
-      if (A.check) {
-        const double xn = A.mode == 0 ? A.xnorm[b] : sqrt(S[S_X0SQ]) + sqrt(S[S_X1SQ]);
-        const double p = sqrt(S[S_PRES2]) / fmax(xn, 1e-30);
-        const double d = sqrt(S[S_STAT2]) / fmax(sqrt(S[S_KA2]), 1e-30);
-        const double rel = fmax(p, d);
-        A.rel_res[b] = rel;
-        if (S[S_NONFIN] > 0.0 || !isfinite(rel)) {
-          A.status[b] = 2;
-          done = true;
-        } else if (A.tol > 0.0 && rel <= A.tol) {
-          A.status[b] = 0;
-          done = true;
-        }
-        if (!done && A.adaptive && !A.final_pass) {
-          // residual balancing: keep tau1*tau2, move the ratio toward the
-          // side whose relative residual lags
-          PairInfo& P = A.pairs[b];
-          const double al = A.alpha[b];
-          double t1 = P.tau1, t2 = P.tau2;
-          bool ch = false;
-          if (d > 1.5 * p) {
-            t1 /= (1.0 - al);
-            t2 *= (1.0 - al);
-            ch = true;
-          } else if (p > 1.5 * d) {
-            t1 *= (1.0 - al);
-            t2 /= (1.0 - al);
-            ch = true;
-          }
-          if (ch) {
-            A.alpha[b] = al * 0.95;
-            P.tau1 = (float)t1;
-            P.tau2 = (float)t2;
-            P.theta = A.mode == 0 ? 0.f : (float)(t1 / (A.rho + t1));
-            P.mutau = (float)(A.mu * t1);
-            P.inv2mt = (float)(1.0 / (1.0 + 2.0 * A.mu * t1));
-          }
-        }
-      }
-      if (!done && (A.final_pass || A.iters[b] >= A.max_iter)) {
-        A.status[b] = 1;
-        done = true;
-      }
-      if (done) A.active[b] = 0;
-      else ++mine;
-    }
-  }
-  cnt[threadIdx.x] = mine;
-  __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *A.n_active = cnt[0];
+  __shared__ double fin[NS];
+  block_reduce_store(acc, max_mask, sums + (long)b * NS, fin);
+  if (do_decide && threadIdx.x == 0) decide_pair(dec, b, fin);
 }
 
 // Copies the current iterate from src to dst for pairs still active.
@@ -624,12 +621,14 @@ hipError_t launch_setup(int grid, const SetupArgs& a, hipStream_t s) {
 
 hipError_t launch_pair_reduce(const PairInfo* pairs, int B, const double* partial, uint32_t max_mask,
                               double* sums, hipStream_t s) {
-  hipLaunchKernelGGL(pair_reduce_kernel, dim3(B), dim3(BLOCK), 0, s, pairs, partial, max_mask, sums);
+  DecideArgs none{};
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3(B), dim3(BLOCK), 0, s, pairs, partial, max_mask, sums, none, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(BLOCK), 0, s, a);
+hipError_t launch_reduce_decide(const DecideArgs& a, const double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3(a.B), dim3(BLOCK), 0, s, a.pairs, partial, kMaxSlotsCheck,
+                     a.sums, a, 1);
   return hipGetLastError();
 }
 
