@@ -160,6 +160,23 @@ uot_status uot_solve_batched(uot_handle *h, int32_t B, const int32_t *nx, const 
 uot_status uot_objective(uot_handle *h, const float *src, const float *dst, const uot_state *st,
                          const uot_state *prev, uot_report *out);
 
+/* Neumann-Poisson solve (alpha I + D D*) phi = rhs on an nx x ny grid with
+ * the zero-flux boundary (D D* is the grid Laplacian with Neumann ends; the
+ * orthonormal DCT-II diagonalises it, eigenvalues 4 sin^2(pi kx/(2 nx)) +
+ * 4 sin^2(pi ky/(2 ny))).  alpha >= 0; at alpha = 0 the constant mode is
+ * dropped (phi has zero mean, rhs is projected to zero mean).  rhs, phi:
+ * device planes of nx*ny floats (may not alias).  Synchronous. */
+uot_status uot_poisson(uot_handle *h, int32_t nx, int32_t ny, double alpha, const float *rhs, float *phi);
+
+/* Poisson-flux start for B pairs (layout as uot_solve_batched): for each pair
+ * M0 = -D* phi with D D* phi = c - mean(c), c = dst - src, which is the
+ * least-squares flux carrying the mass difference; r0 = D M0 + c, so the
+ * start satisfies the constraint; a0 = 0; the free prox arguments start at
+ * src / dst.  Pass the state to uot_solve* with UOT_WARM_START.  Needs the
+ * zero-flux boundary (bc = 0). */
+uot_status uot_init_poisson(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
+                            const int64_t *offset, const float *src, const float *dst, uot_state *packed);
+
 /* Profiling aid: runs n (rounded up to even) back-to-back launches of the
  * fused iteration kernel on the handle's grid and stream, bracketed by HIP
  * events, starting from the caller's state *st (advanced by those

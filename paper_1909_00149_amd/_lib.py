@@ -64,6 +64,12 @@ SIGNATURES = {
     "uot_time_iterations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.POINTER(State), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_double)]),
+    "uot_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "uot_init_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(State)]),
     "uot_destroy": (None, [ctypes.c_void_p]),
     "uot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }

@@ -145,6 +145,14 @@ struct uot_handle {
 
   std::vector<Tile> h_live;     // kept alive across async uploads
 
+  // Poisson solve: DCT-II matrices by size, scratch planes, partial sums
+  std::map<int, float*> dct;
+  float* pw[4] = {nullptr, nullptr, nullptr, nullptr};  // t1 | t2 | phi | rhs
+  size_t cap_pw[4] = {0, 0, 0, 0};
+  double* d_pp = nullptr;
+  size_t cap_pp = 0;
+  double* h_pp = nullptr;       // pinned
+
   // cached graph of one check window
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
@@ -158,6 +166,11 @@ struct uot_handle {
       if (p) (void)hipFree(p);
     if (h_sums) (void)hipHostFree(h_sums);
     if (h_i32) (void)hipHostFree(h_i32);
+    for (auto& kv : dct) (void)hipFree(kv.second);
+    for (auto& p : pw)
+      if (p) (void)hipFree(p);
+    if (d_pp) (void)hipFree(d_pp);
+    if (h_pp) (void)hipHostFree(h_pp);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -435,7 +448,7 @@ uot_status check_setup_sums(uot_handle* h, const Job& J, bool warm) {
 struct Reporter {
   // per-pair final fields computed on the host from the final check sums
   static void fill(const uot_params& p, const PairInfo& P, const double* S, double xnorm_dist, uot_report* r,
-                   double dual_prox, bool have_dual_prox) {
+                   double dual_prox, bool have_dual_prox, double bal_primal = std::nan("")) {
     const int resid = resid_of(p);
     const double mu = p.mu, rho = p.rho;
     const double quad = p.mode == UOT_DIST ? 0.0 : S[S_QUAD] / (2.0 * rho);
@@ -450,7 +463,16 @@ struct Reporter {
     r->tau1 = P.tau1;
     r->tau2 = P.tau2;
     r->primal = r->dual = r->rel_gap = std::nan("");
-    if (resid == R_BAL) return;  // needs the feasibility projection
+    if (resid == R_BAL) {
+      // DIST with the zero-flux boundary: the primal bound comes from the
+      // Poisson feasibility repair; the dual needs only ||(D* a)_i|| <= 1
+      if (p.mode == UOT_DIST && std::isfinite(bal_primal)) {
+        r->primal = bal_primal;
+        r->dual = S[S_LIN] / std::max(1.0, S[S_MAXG]);
+        r->rel_gap = (r->primal - r->dual) / std::max(std::fabs(r->primal), 1e-30);
+      }
+      return;
+    }
     r->primal = S[S_MNORM] + mu * S[S_EPEN] + quad;
     double s = std::max(1.0, S[S_MAXG]);
     if (resid == R_P1) s = std::max(s, S[S_MAXA] / mu);
@@ -562,6 +584,76 @@ uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
   h->gexec = ex;
   h->gkey = key;
   *out = ex;
+  return UOT_OK;
+}
+
+// Orthonormal DCT-II matrix of size n, C[k][i] = s_k cos(pi (2i+1) k / (2n)),
+// cached on the device per size.
+uot_status get_dct(uot_handle* h, int n, const float** out) {
+  auto it = h->dct.find(n);
+  if (it != h->dct.end()) {
+    *out = it->second;
+    return UOT_OK;
+  }
+  std::vector<float> m((size_t)n * n);
+  for (int k = 0; k < n; ++k) {
+    const double s = k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+    for (int i = 0; i < n; ++i) m[(size_t)k * n + i] = (float)(s * std::cos(kPi * (2.0 * i + 1) * k / (2.0 * n)));
+  }
+  float* d = nullptr;
+  HIPCHK(hipMalloc((void**)&d, m.size() * sizeof(float)));
+  hipError_t e = hipMemcpy(d, m.data(), m.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return UOT_ERR_DEVICE;
+  }
+  h->dct[n] = d;
+  *out = d;
+  return UOT_OK;
+}
+
+uot_status ensure_poisson(uot_handle* h, size_t px) {
+  for (int i = 0; i < 4; ++i) HIPCHK(grow(&h->pw[i], &h->cap_pw[i], px));
+  HIPCHK(grow(&h->d_pp, &h->cap_pp, 1024));
+  if (!h->h_pp) HIPCHK(hipHostMalloc((void**)&h->h_pp, 1024 * sizeof(double), hipHostMallocDefault));
+  return UOT_OK;
+}
+
+// phi = (alpha I + D D*)^{-1} rhs on one grid (scratch planes pw[0], pw[1]).
+uot_status poisson_grid(uot_handle* h, int nx, int ny, double alpha, const float* rhs, float* phi) {
+  const float *cx = nullptr, *cy = nullptr;
+  uot_status s = get_dct(h, nx, &cx);
+  if (s != UOT_OK) return s;
+  s = get_dct(h, ny, &cy);
+  if (s != UOT_OK) return s;
+  HIPCHK(poisson_solve(cx, cy, nx, ny, (float)alpha, rhs, phi, h->pw[0], h->pw[1], h->stream));
+  return UOT_OK;
+}
+
+// Feasibility repair of a balanced DIST state (zero-flux boundary): with
+// e = D M + c and phi = (D D*)^+ e, the flux M - D* phi satisfies the
+// constraint; its l2,1 norm is a certified upper bound on the value.
+uot_status balanced_primal(uot_handle* h, const Job& J, const float* src, const float* dst, const uot_state* st,
+                           std::vector<double>& out) {
+  out.assign(J.B, std::nan(""));
+  size_t maxpx = 0;
+  for (const PairInfo& P : J.pairs) maxpx = std::max<size_t>(maxpx, (size_t)P.nx * P.ny);
+  uot_status s = ensure_poisson(h, maxpx);
+  if (s != UOT_OK) return s;
+  for (int b = 0; b < J.B; ++b) {
+    const PairInfo& P = J.pairs[b];
+    const long o = P.off;
+    HIPCHK(launch_infeasibility(st->Mx + o, st->My + o, src + o, dst + o, h->pw[3], P.nx, P.ny, h->stream));
+    s = poisson_grid(h, P.nx, P.ny, 0.0, h->pw[3], h->pw[2]);
+    if (s != UOT_OK) return s;
+    const int nb = repaired_norm_blocks(P.nx, P.ny);
+    HIPCHK(launch_repaired_norm(st->Mx + o, st->My + o, h->pw[2], P.nx, P.ny, h->d_pp, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_pp, h->d_pp, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += h->h_pp[i];
+    out[b] = acc;
+  }
   return UOT_OK;
 }
 
@@ -793,12 +885,17 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
     s = prox_duals(h, J, src, dst, st->a, sums.data(), duals);
     if (s != UOT_OK) return s;
   }
+  std::vector<double> bal(B, std::nan(""));
+  if (p.mode == UOT_DIST && resid == R_BAL && p.bc == 0) {
+    s = balanced_primal(h, J, src, dst, st, bal);
+    if (s != UOT_OK) return s;
+  }
   const double secs = timer.seconds();
   for (int b = 0; b < B; ++b) {
     uot_report& r = reps[b];
     std::memset(&r, 0, sizeof(r));
     Reporter::fill(p, J.pairs[b], sums.data() + (size_t)b * NS, xnorm[b], &r, need_dual ? duals[b] : 0.0,
-                   need_dual);
+                   need_dual, bal[b]);
     r.iters = h->h_i32[B + b];
     r.status = h->h_i32[2 * B + b];
     r.seconds = secs;
@@ -959,10 +1056,68 @@ uot_status uot_objective(uot_handle* h, const float* src, const float* dst, cons
       s = prox_duals(h, J, src, dst, st->a, sums.data(), duals);
       if (s != UOT_OK) return s;
     }
+    std::vector<double> bal(1, std::nan(""));
+    if (p.mode == UOT_DIST && p.balanced && p.bc == 0) {
+      s = balanced_primal(h, J, src, dst, st, bal);
+      if (s != UOT_OK) return s;
+    }
     std::memset(out, 0, sizeof(*out));
-    Reporter::fill(p, J.pairs[0], sums.data(), xn, out, need_dual ? duals[0] : 0.0, need_dual);
+    Reporter::fill(p, J.pairs[0], sums.data(), xn, out, need_dual ? duals[0] : 0.0, need_dual, bal[0]);
     out->status = (sums[S_NONFIN] > 0) ? UOT_DIVERGED : UOT_MAX_ITER;
     out->seconds = timer.seconds();
+    return UOT_OK;
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_poisson(uot_handle* h, int32_t nx, int32_t ny, double alpha, const float* rhs, float* phi) {
+  if (!h || !rhs || !phi || !(alpha >= 0.0) || !std::isfinite(alpha)) return UOT_ERR_ARG;
+  if (nx < 1 || ny < 1) return UOT_ERR_SHAPE;
+  if (rhs == phi) return UOT_ERR_ARG;
+  try {
+    if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+    uot_status s = ensure_poisson(h, (size_t)nx * ny);
+    if (s != UOT_OK) return s;
+    s = poisson_grid(h, nx, ny, alpha, rhs, phi);
+    if (s != UOT_OK) return s;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return UOT_OK;
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_init_poisson(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
+                            const float* src, const float* dst, uot_state* packed) {
+  if (!h || !src || !dst) return UOT_ERR_ARG;
+  const uot_params& p = h->prm;
+  if (p.bc != 0) return UOT_ERR_ARG;
+  uot_status s = validate_state(p, packed);
+  if (s != UOT_OK) return s;
+  try {
+    Job J;
+    s = plan(h, B, nx, ny, offset, J, 8);
+    if (s != UOT_OK) return s;
+    if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+    size_t maxpx = 0;
+    for (const PairInfo& P : J.pairs) maxpx = std::max<size_t>(maxpx, (size_t)P.nx * P.ny);
+    s = ensure_poisson(h, maxpx);
+    if (s != UOT_OK) return s;
+    for (int b = 0; b < B; ++b) {
+      const PairInfo& P = J.pairs[b];
+      const long o = P.off;
+      // rhs = c = dst - src: the infeasibility of the zero flux
+      HIPCHK(hipMemsetAsync(h->pw[2], 0, (size_t)P.nx * P.ny * sizeof(float), h->stream));
+      HIPCHK(launch_infeasibility(h->pw[2], h->pw[2], src + o, dst + o, h->pw[3], P.nx, P.ny, h->stream));
+      s = poisson_grid(h, P.nx, P.ny, 0.0, h->pw[3], h->pw[2]);
+      if (s != UOT_OK) return s;
+      Planes st = planes_of(*packed);
+      Planes at{st.Mx + o, st.My + o, st.r ? st.r + o : nullptr, st.a + o, st.x0 ? st.x0 + o : nullptr,
+                st.x1 ? st.x1 + o : nullptr};
+      HIPCHK(launch_poisson_start(h->pw[2], src + o, dst + o, at, P.nx, P.ny, p.mode, p.balanced, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
     return UOT_OK;
   } catch (...) {
     return UOT_ERR_OOM;

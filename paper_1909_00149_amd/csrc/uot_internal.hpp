@@ -151,3 +151,19 @@ hipError_t launch_dual(int grid, const DualArgs& a, hipStream_t s);
 hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* blocks_per_cu);
 
 }  // namespace uot
+
+namespace uot {
+// Neumann-Poisson solve via the orthonormal DCT-II matrices Cx (nx x nx),
+// Cy (ny x ny); t1, t2 are nx*ny scratch planes.
+hipError_t poisson_solve(const float* Cx, const float* Cy, int nx, int ny, float alpha, const float* rhs,
+                         float* phi, float* t1, float* t2, hipStream_t s);
+hipError_t launch_sgemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+                        float* C, int ldc, hipStream_t s);
+hipError_t launch_poisson_start(const float* phi, const float* src, const float* dst, const Planes& st, int nx,
+                                int ny, int mode, int balanced, hipStream_t s);
+hipError_t launch_infeasibility(const float* Mx, const float* My, const float* src, const float* dst, float* e,
+                                int nx, int ny, hipStream_t s);
+int repaired_norm_blocks(int nx, int ny);
+hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, double* partial,
+                                hipStream_t s);
+}  // namespace uot

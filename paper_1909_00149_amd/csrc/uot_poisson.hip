@@ -1,0 +1,216 @@
+// Neumann-Poisson solve (alpha I + D D*) phi = c on one grid, for the
+// zero-flux boundary, where D D* is the grid Laplacian with Neumann ends and
+// the orthonormal DCT-II diagonalises it with eigenvalues
+//     4 sin^2(pi kx / (2 nx)) + 4 sin^2(pi ky / (2 ny)).
+// The 2-D transform is separable: T = Cy c Cx^T, divide by the eigenvalues,
+// phi = Cy^T T Cx, i.e. four dense products with the DCT matrices, done by
+// an LDS-tiled FP32 GEMM.  Also the kernels that use phi: the Poisson-flux
+// warm start and the feasibility repair of the balanced certificate.
+#include "uot_internal.hpp"
+
+#include <algorithm>
+
+namespace uot {
+
+namespace {
+constexpr int GT = 64;   // output tile
+constexpr int GK = 16;   // k step
+}  // namespace
+
+// C[M x N] = op(A) op(B), row-major FP32.  op(A) is M x K: A[m*lda+k], or
+// A[k*lda+m] when TA.  op(B) is K x N: B[k*ldb+n], or B[n*ldb+k] when TB.
+// 256 threads, each owning a 4 x 4 block of the 64 x 64 output tile.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void sgemm_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                    const float* __restrict__ B, int ldb, float* __restrict__ C,
+                                                    int ldc) {
+  __shared__ float As[GK][GT + 4];
+  __shared__ float Bs[GK][GT + 4];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int idx = tid; idx < GT * GK; idx += 256) {
+      int mm, kk;
+      if (TA) {
+        kk = idx / GT;
+        mm = idx - kk * GT;
+      } else {
+        mm = idx / GK;
+        kk = idx - mm * GK;
+      }
+      const int m = m0 + mm, k = k0 + kk;
+      float v = 0.f;
+      if (m < M && k < K) v = TA ? A[(long)k * lda + m] : A[(long)m * lda + k];
+      As[kk][mm] = v;
+    }
+    for (int idx = tid; idx < GT * GK; idx += 256) {
+      int nn, kk;
+      if (TB) {
+        nn = idx / GK;
+        kk = idx - nn * GK;
+      } else {
+        kk = idx / GT;
+        nn = idx - kk * GT;
+      }
+      const int n = n0 + nn, k = k0 + kk;
+      float v = 0.f;
+      if (n < N && k < K) v = TB ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty + 16 * i;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx + 16 * j;
+      if (n < N) C[(long)m * ldc + n] = acc[i][j];
+    }
+  }
+}
+
+// Divide the spectrum by alpha + lambda_y[j] + lambda_x[i]; the constant
+// mode is dropped when its eigenvalue is zero.
+__global__ void spectrum_divide_kernel(float* T, int nx, int ny, float alpha) {
+  const long n = (long)nx * ny;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
+    const double sx = sin(3.14159265358979323846 * i / (2.0 * nx));
+    const double sy = sin(3.14159265358979323846 * j / (2.0 * ny));
+    const double lam = (double)alpha + 4.0 * sx * sx + 4.0 * sy * sy;
+    T[e] = lam > 0.0 ? (float)(T[e] / lam) : 0.f;
+  }
+}
+
+// Poisson-flux start on one grid: M0 = -D* phi (zero-flux edges), r0 = D M0 +
+// c so that K z0 = 0, a0 = 0; the free arguments start at their prox centres.
+__global__ void poisson_start_kernel(const float* phi, const float* src, const float* dst, Planes st, int nx,
+                                     int ny, int mode, int balanced) {
+  const long n = (long)nx * ny;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
+    auto mx_at = [&](int ii, int jj) -> float {
+      if (ii < 0 || ii >= nx - 1) return 0.f;
+      const long o = (long)jj * nx + ii;
+      return -(phi[o] - phi[o + 1]);
+    };
+    auto my_at = [&](int ii, int jj) -> float {
+      if (jj < 0 || jj >= ny - 1) return 0.f;
+      const long o = (long)jj * nx + ii;
+      return -(phi[o] - phi[o + nx]);
+    };
+    const float mx = mx_at(i, j), my = my_at(i, j);
+    st.Mx[e] = mx;
+    st.My[e] = my;
+    st.a[e] = 0.f;
+    const float dm = mx - mx_at(i - 1, j) + my - my_at(i, j - 1);
+    const float c = dst[e] - src[e];
+    if (!balanced) st.r[e] = dm + c;
+    if (mode == 1) st.x0[e] = src[e];
+    if (mode != 0) st.x1[e] = dst[e];
+  }
+}
+
+// e = D M + c of a state (the infeasibility the balanced repair removes).
+__global__ void infeasibility_kernel(const float* Mx, const float* My, const float* src, const float* dst,
+                                     float* e_out, int nx, int ny) {
+  const long n = (long)nx * ny;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
+    const float mx = i < nx - 1 ? Mx[e] : 0.f;
+    const float my = j < ny - 1 ? My[e] : 0.f;
+    const float mxl = i > 0 ? Mx[e - 1] : 0.f;
+    const float myd = j > 0 ? My[e - nx] : 0.f;
+    e_out[e] = (mx - mxl) + (my - myd) + (dst[e] - src[e]);
+  }
+}
+
+// Partial sums of ||(M - D* phi)_i||: the flux norm of the repaired flux.
+__global__ __launch_bounds__(256) void repaired_norm_kernel(const float* Mx, const float* My, const float* phi,
+                                                            int nx, int ny, double* partial) {
+  __shared__ double red[256];
+  const long n = (long)nx * ny;
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
+    const float gx = i < nx - 1 ? phi[e] - phi[e + 1] : 0.f;
+    const float gy = j < ny - 1 ? phi[e] - phi[e + nx] : 0.f;
+    const float mx = (i < nx - 1 ? Mx[e] : 0.f) - gx;
+    const float my = (j < ny - 1 ? My[e] : 0.f) - gy;
+    acc += sqrtf(mx * mx + my * my);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_sgemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+                        float* C, int ldc, hipStream_t s) {
+  const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  if (!ta && !tb) hipLaunchKernelGGL((sgemm_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+  else if (!ta && tb) hipLaunchKernelGGL((sgemm_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+  else if (ta && !tb) hipLaunchKernelGGL((sgemm_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+  else hipLaunchKernelGGL((sgemm_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+static int elem_grid(long n) { return (int)std::min<long>(4096, std::max<long>(1, (n + 255) / 256)); }
+
+hipError_t poisson_solve(const float* Cx, const float* Cy, int nx, int ny, float alpha, const float* rhs, float* phi,
+                         float* t1, float* t2, hipStream_t s) {
+  hipError_t e;
+  // T1 = rhs Cx^T (transform along x), T2 = Cy T1 (along y)
+  if ((e = launch_sgemm(false, true, ny, nx, nx, rhs, nx, Cx, nx, t1, nx, s)) != hipSuccess) return e;
+  if ((e = launch_sgemm(false, false, ny, nx, ny, Cy, ny, t1, nx, t2, nx, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(spectrum_divide_kernel, dim3(elem_grid((long)nx * ny)), dim3(256), 0, s, t2, nx, ny, alpha);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // T1 = Cy^T T2, phi = T1 Cx
+  if ((e = launch_sgemm(true, false, ny, nx, ny, Cy, ny, t2, nx, t1, nx, s)) != hipSuccess) return e;
+  return launch_sgemm(false, false, ny, nx, nx, t1, nx, Cx, nx, phi, nx, s);
+}
+
+hipError_t launch_poisson_start(const float* phi, const float* src, const float* dst, const Planes& st, int nx,
+                                int ny, int mode, int balanced, hipStream_t s) {
+  hipLaunchKernelGGL(poisson_start_kernel, dim3(elem_grid((long)nx * ny)), dim3(256), 0, s, phi, src, dst, st, nx,
+                     ny, mode, balanced);
+  return hipGetLastError();
+}
+
+hipError_t launch_infeasibility(const float* Mx, const float* My, const float* src, const float* dst, float* e,
+                                int nx, int ny, hipStream_t s) {
+  hipLaunchKernelGGL(infeasibility_kernel, dim3(elem_grid((long)nx * ny)), dim3(256), 0, s, Mx, My, src, dst, e,
+                     nx, ny);
+  return hipGetLastError();
+}
+
+int repaired_norm_blocks(int nx, int ny) { return std::min(1024, elem_grid((long)nx * ny)); }
+
+hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, double* partial,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(repaired_norm_kernel, dim3(repaired_norm_blocks(nx, ny)), dim3(256), 0, s, Mx, My, phi, nx,
+                     ny, partial);
+  return hipGetLastError();
+}
+
+}  // namespace uot

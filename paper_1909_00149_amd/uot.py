@@ -142,6 +142,34 @@ class Solver:
             raise UOTError(rc, "uot_solve_batched")
         return state, [r.as_dict() for r in reps]
 
+    def poisson(self, rhs, alpha=0.0, out=None):
+        """uot_poisson: phi = (alpha I + D D*)^{-1} rhs (zero-flux boundary)."""
+        ny, nx = rhs.shape
+        phi = torch.empty_like(rhs) if out is None else out
+        rc = self.lib.uot_poisson(self._h, nx, ny, float(alpha), _ptr(rhs), _ptr(phi))
+        if rc != 0:
+            raise UOTError(rc, "uot_poisson")
+        return phi
+
+    def init_poisson(self, src, dst, state=None, nx=None, ny=None, offset=None):
+        """uot_init_poisson: Poisson-flux start (single grid, or packed pairs
+        when nx/ny/offset are given)."""
+        p = self.params
+        if nx is None:
+            ny_, nx_ = src.shape
+            nx, ny, offset = [nx_], [ny_], [0]
+        B = len(nx)
+        if state is None:
+            state = new_state(p.mode, p.balanced, src.shape, src.device)
+        ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
+        ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
+        ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+        cs = _cstate(state)
+        rc = self.lib.uot_init_poisson(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs))
+        if rc != 0:
+            raise UOTError(rc, "uot_init_poisson")
+        return state
+
     def time_iterations(self, src, dst, state, n):
         """uot_time_iterations: average ms per fused-iteration launch."""
         cs = _cstate(state)
