@@ -22,6 +22,8 @@ Workloads (seeded synthetic inputs):
   video63   the 63 consecutive frame pairs of a 64-frame 256x256 video,
             prox mode (rho = 1, mu = 2), one batched solve
   sweepN    one NxN pair, exactly 200 iterations (the size sweep)
+  copy      a plain 1 GiB device-to-device copy (calibrates the HBM byte
+            counters of the profiler and shows the attainable copy rate)
 """
 from __future__ import annotations
 
@@ -108,6 +110,8 @@ def main():
     ap.add_argument("--workload", default="pair512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=400)
+    ap.add_argument("--warm-pairs", type=int, default=64,
+                    help="held-out 256x256 pairs for the warm-vs-cold time to 1e-4 (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"this benchmark runs on one GPU only (asked for {args.gpus}); the batched solver "
@@ -118,6 +122,26 @@ def main():
     from paper_1909_00149_amd import uot as G
 
     dev = torch.device("cuda:0")
+    if args.workload == "copy":
+        n = (1 << 30) // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(args.warmup):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+        print(json.dumps({"metric": "copy GB/s (read + write)", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                          "higher_is_better": True, "bytes_read_per_copy": n * 4,
+                          "bytes_written_per_copy": n * 4}), flush=True)
+        return
     W = workload(args.workload)
     pairs = W["pairs"]
     imgs_p = [torch.from_numpy(np.ascontiguousarray(p)).to(dev) for p, _ in pairs]
@@ -203,9 +227,31 @@ def main():
         "max_rel_res": max(float(r["rel_res"]) for r in reps),
         "roofline": roofline,
     }
+    if args.warm_pairs > 0:
+        out["warm_start"] = warm_vs_cold(dev, args.warm_pairs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
+
+
+def warm_vs_cold(dev, n):
+    """Time to rel_res <= 1e-4 on n held-out 256x256 pairs, one batched solve
+    per arm (best of 3): cold start vs the trained network's start
+    (inference included)."""
+    from paper_1909_00149_amd import warmstart as WS
+    path = os.path.join(ROOT, "paper_1909_00149_amd", "data", "warmstart_256.npz")
+    pairs = [WS._pair(s) for s in range(WS.EVAL_SEED0, WS.EVAL_SEED0 + n)]
+    src = np.stack([p for p, _ in pairs])
+    dst = np.stack([q for _, q in pairs])
+    net = WS.load_net(path, dev, batch_max=16)
+    res = WS.evaluate(net, src, dst, dev, arms=("cold", "learned"), repeats=3)
+    c, l = res["cold"], res["learned"]
+    return {"pairs": n, "side": WS.SIDE, "tol": 1e-4,
+            "cold_ms": round(1e3 * c["wall_s"], 3), "learned_ms": round(1e3 * l["wall_s"], 3),
+            "learned_start_ms": round(1e3 * l["start_s"], 3),
+            "cold_iters_median": c["iters_median"], "learned_iters_median": l["iters_median"],
+            "converged": [c["converged"], l["converged"]],
+            "speedup": round(c["wall_s"] / l["wall_s"], 3)}
 
 
 if __name__ == "__main__":

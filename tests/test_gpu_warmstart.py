@@ -1,0 +1,58 @@
+"""What the trained warm-start network gains over the method without it, on
+held-out pairs (seeds never used in training), and the fallback path."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1909_00149_amd import net as N
+from paper_1909_00149_amd import uot as G
+from paper_1909_00149_amd import warmstart as WS
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(WS.__file__), "data", "warmstart_256.npz")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch.device("cuda:0")
+
+
+def heldout(n, first=WS.EVAL_SEED0 + 5000):
+    pairs = [WS._pair(s) for s in range(first, first + n)]
+    return np.stack([p for p, _ in pairs]), np.stack([q for _, q in pairs])
+
+
+def test_learned_start_beats_cold_start(dev):
+    net = WS.load_net(WEIGHTS, dev, batch_max=16)
+    src, dst = heldout(32)
+    res = WS.evaluate(net, src, dst, dev, arms=("cold", "learned"))
+    cold, learned = res["cold"], res["learned"]
+    assert cold["converged"] == 32 and learned["converged"] == 32, res
+    assert learned["iters_median"] <= 0.8 * cold["iters_median"], res
+    # both arms reach the same optimal values (the stopping rule decides)
+    assert abs(learned["primal_mean"] - cold["primal_mean"]) <= 1e-3 * cold["primal_mean"], res
+
+
+def test_rejected_start_falls_back_to_cold(dev):
+    """A network producing non-finite values gives a start the solver
+    rejects; the evaluation falls back to the cold start and converges."""
+    net = WS.load_net(WEIGHTS, dev, batch_max=16)
+    bad = net.get_params()
+    bad[:] = np.nan
+    net.set_params(bad)
+    src, dst = heldout(4, first=WS.EVAL_SEED0 + 9000)
+    res = WS.evaluate(net, src, dst, dev, arms=("learned",))
+    assert res["learned"]["converged"] == 4
+    # and the warm solve by itself reports the rejection
+    S = torch.from_numpy(src.reshape(-1)).to(dev)
+    D = torch.from_numpy(dst.reshape(-1)).to(dev)
+    st = G.new_state(G.DIST, False, S.numel(), dev)
+    net.warm_state(S, D, st, WS.IN_SCALE, WS.S_FLUX, WS.S_DUAL)
+    s = G.Solver(G.Params(mu=WS.MU, tol=1e-4, max_iter=100, flags=G.UOT_WARM_START))
+    with pytest.raises(G.UOTError) as e:
+        s.solve_batched(S, D, [WS.SIDE] * 4, [WS.SIDE] * 4, [b * WS.NPX for b in range(4)], st)
+    assert e.value.code == 4
