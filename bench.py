@@ -8,8 +8,15 @@ already resident in HBM.  The printed JSON line carries:
   value      pixel-iterations per second over the K timed steps
              (sum over pairs of pixels x iterations actually run)
   roofline   the fused iteration kernel against the 8 TB/s HBM peak:
-             algorithmic bytes per pixel-iteration x pixels / the kernel's
-             average launch time (HIP events on the solver's stream)
+             algorithmic bytes per pixel-iteration x pixels per launch / the
+             kernel's average launch time, from HIP events on the solver's
+             stream around graph-replayed back-to-back launches of the launch
+             the step runs (a batch: every pair live).  `traffic` is the HBM
+             bytes per launch from the profiler's FETCH_SIZE / WRITE_SIZE
+             counters (calibrated on a device copy), or null when they were
+             not taken for this workload and the current kernel sources
+  warm_start time to rel_res <= 1e-4 on held-out 256x256 pairs, cold start
+             against the trained network's start (inference included)
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of
              the same workload (a fixed number of iterations of one pair)
 
@@ -43,6 +50,45 @@ HBM_PEAK_GBS = 8000.0
 # read once and written once, constants read once (FP32)
 BYTES = {(0, False): 36, (0, True): 28, (1, False): 56, (1, True): 48, (2, False): 48, (2, True): 40}
 
+
+# HBM traffic of one launch of the fused kernel, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, averaged over the
+# dispatches of the timing launches) scaled by what the same counters read
+# for a 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid
+# only for the kernel sources they were taken on: any change to them makes
+# the figure unknown (null) until the counters are taken again.
+TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_kernels.hip", "paper_1909_00149_amd/csrc/uot_internal.hpp")
+TRAFFIC_SHA256 = "25f6f58ee4dac98fe2848792da5c75e79ab8baf27c0f88f8bd7dfb212a48b411"
+FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
+# workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
+TRAFFIC_KIB = {
+    "pair512": (116, 2612.620, 4096.000),
+    "sweep4096": (316, 171642.301, 262153.792),
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name, shape):
+    rec = TRAFFIC_KIB.get(name)
+    if rec is None or rec[0] != shape or kernel_sources_sha256() != TRAFFIC_SHA256:
+        return None
+    return int(round((rec[1] * FETCH_SCALE + rec[2] * WRITE_SCALE) * 1024))
+
+
+def kernel_name(mode, balanced, shape):
+    """Instantiated name of the fused kernel for a tile_rows code."""
+    resid = 0 if balanced else 1
+    if shape >= 100:
+        return f"cp_iter_vec_kernel<{mode}, {resid}, 0, {shape % 100}, {'true' if shape >= 300 else 'false'}>"
+    return f"cp_iter_kernel<{mode}, {resid}, 0, {shape}>"
 
 def workload(name):
     from paper_1909_00149_amd import synth
@@ -184,26 +230,27 @@ def main():
     secs = time.perf_counter() - t0
     value = pix_iters / secs
 
-    # fused-kernel timing on the solver's stream (single pair: the pair
-    # itself; batched: the largest pair of the batch)
-    big = int(np.argmax(npx))
-    kp, kq = imgs_p[big], imgs_q[big]
-    kny, knx = kp.shape
-    kprm = G.Params(nx=knx, ny=kny, mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"])
-    ksolver = G.Solver(kprm)
-    kstate = G.new_state(W["mode"], W["balanced"], kp.shape, dev)
-    ksolver.time_iterations(kp, kq, kstate, 20)
-    ms = ksolver.time_iterations(kp, kq, kstate, args.kernel_iters)
-    bpp = BYTES[(W["mode"], W["balanced"])]
+    # fused-kernel timing on the solver's stream, on the launch the step runs
+    # (a batch: every pair live; one pair: the pair itself)
+    kstate = G.new_state(W["mode"], W["balanced"], src.shape if not batched else src.numel(), dev)
+    ksolver = G.Solver(prm)
     if batched:
-        # the batched step runs the same kernel over all pairs: report the
-        # step-level effective bandwidth too
-        pass
-    achieved = bpp * kp.numel() / (ms * 1e-3) / 1e9
+        ksolver.time_iterations_batched(src, dst, nx, ny, offs, kstate, 20)
+        ms, shape = ksolver.time_iterations_batched(src, dst, nx, ny, offs, kstate, args.kernel_iters)
+    else:
+        ksolver.time_iterations(src, dst, kstate, 20)
+        ms, shape = ksolver.time_iterations(src, dst, kstate, args.kernel_iters)
+    bpp = BYTES[(W["mode"], W["balanced"])]
+    px_launch = int(sum(npx))
+    alg_bytes = bpp * px_launch
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, shape)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "cp_iter_kernel", "bytes_per_pixel_iter": bpp, "pixels_per_launch": int(kp.numel()),
-                "kernel_ms": round(ms, 5)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_vs_algorithmic": round(traffic / alg_bytes, 4) if traffic else None,
+                "kernel": kernel_name(W["mode"], W["balanced"], shape), "tile_rows": shape,
+                "bytes_per_pixel_iter": bpp, "pixels_per_launch": px_launch,
+                "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5)}
     out = {
         "metric": "pixel-iters/s (%HBM peak); time-to-1e-4 residual, warm-start vs cold",
         "value": value,

@@ -100,7 +100,13 @@ typedef struct uot_params {
   int32_t check_every;  /* iterations between convergence checks (rounded up to even) */
   double tol;           /* stop when rel_res <= tol; <= 0 runs exactly max_iter       */
   uint32_t flags;       /* UOT_* flags above                                          */
-  int32_t tile_rows;    /* rows per 64-wide tile: 0 = autotuned/heuristic, else 4..32 */
+  int32_t tile_rows;    /* kernel shape: 0 = autotuned / heuristic; 4, 8, 16, 32 rows per
+                           64-wide tile; 116 / 132 = the 16- / 32-row vectorised kernel;
+                           316 / 332 = the same with non-temporal stores (for states
+                           larger than the last-level cache).  The vectorised shapes
+                           run when every row starts on a 16-byte boundary (nx and pair
+                           offsets multiples of 4, planes 16-byte aligned); otherwise
+                           the scalar kernel of the same rows runs                        */
 } uot_params;
 
 /* Device planes of one state.  Required planes by mode:
@@ -122,6 +128,8 @@ typedef struct uot_report {
   double objective;    /* objective of the raw iterate (no feasibility repair)         */
   double seconds;      /* wall time of the call                                        */
   double tau1, tau2;   /* steps actually used                                          */
+  int32_t tile_rows;   /* kernel shape that ran (a tile_rows code; 0 if no iteration)  */
+  int32_t reserved;
 } uot_report;
 
 typedef struct uot_handle uot_handle;
@@ -177,13 +185,22 @@ uot_status uot_poisson(uot_handle *h, int32_t nx, int32_t ny, double alpha, cons
 uot_status uot_init_poisson(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
                             const int64_t *offset, const float *src, const float *dst, uot_state *packed);
 
-/* Profiling aid: runs n (rounded up to even) back-to-back launches of the
- * fused iteration kernel on the handle's grid and stream, bracketed by HIP
- * events, starting from the caller's state *st (advanced by those
- * iterations; no setup, no checks, no zeroing).  *ms_per_iter receives the
- * average event-to-event time per launch.  src/dst as for uot_solve. */
+/* Profiling aid: captures n (rounded up to even) back-to-back launches of
+ * the fused iteration kernel on the handle's grid and stream into a graph,
+ * replays it once untimed and once bracketed by HIP events, starting from
+ * the caller's state *st (advanced by those 2n iterations; no checks, no
+ * zeroing; the state and images are validated first).  *ms_per_iter
+ * receives the average event-to-event time per launch; *tile_rows (may be
+ * NULL) the kernel shape that ran.  src/dst as for uot_solve. */
 uot_status uot_time_iterations(uot_handle *h, const float *src, const float *dst, uot_state *st,
-                               int32_t n, double *ms_per_iter);
+                               int32_t n, double *ms_per_iter, int32_t *tile_rows);
+
+/* The same over a batch layout (as uot_solve_batched), every pair live: the
+ * launch the batched solve runs until its first pair stops. */
+uot_status uot_time_iterations_batched(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
+                                       const int64_t *offset, const float *src, const float *dst,
+                                       uot_state *packed, int32_t n, double *ms_per_iter,
+                                       int32_t *tile_rows);
 
 /* Releases the handle's workspace.  NULL is a no-op. */
 void uot_destroy(uot_handle *h);

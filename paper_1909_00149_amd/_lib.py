@@ -39,7 +39,8 @@ class Report(ctypes.Structure):
                 ("primal", ctypes.c_double), ("dual", ctypes.c_double),
                 ("feas", ctypes.c_double), ("objective", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("tau1", ctypes.c_double),
-                ("tau2", ctypes.c_double)]
+                ("tau2", ctypes.c_double), ("tile_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,7 +64,12 @@ SIGNATURES = {
                                      ctypes.POINTER(State), ctypes.POINTER(State), ctypes.POINTER(Report)]),
     "uot_time_iterations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.POINTER(State), ctypes.c_int32,
-                                           ctypes.POINTER(ctypes.c_double)]),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
+    "uot_time_iterations_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State),
+                                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_int32)]),
     "uot_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "uot_init_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,

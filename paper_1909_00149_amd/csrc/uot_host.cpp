@@ -85,11 +85,17 @@ void tune_store_locked() {
   std::fclose(f);
 }
 
-int heuristic_rows(long total_px) {
+// Kernel shape codes: rows per tile for the scalar kernel (4, 8, 16, 32);
+// 100 + rows for the vectorised kernel (rows on 16-byte boundaries); 300 +
+// rows for the vectorised kernel with non-temporal stores, which pays once
+// the state no longer fits the 256 MB Infinity Cache.  Default by size:
+int heuristic_shape(long total_px) {
   if (total_px <= (1L << 16)) return 4;
-  if (total_px <= (1L << 20)) return 8;
-  return 16;
+  if (total_px <= (8L << 20)) return 116;
+  return 316;
 }
+
+bool aligned16(const void* p) { return p == nullptr || ((uintptr_t)p & 15u) == 0; }
 
 template <class T>
 hipError_t grow(T** p, size_t* cap, size_t n) {
@@ -209,8 +215,10 @@ uot_status uot_check_params(const uot_params* p) {
   if ((p->tau1 == 0.0) != (p->tau2 == 0.0)) return UOT_ERR_ARG;
   if (p->max_iter < 0 || p->check_every < 0) return UOT_ERR_ARG;
   if (!std::isfinite(p->tol)) return UOT_ERR_ARG;
-  if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16 && p->tile_rows != 32)
-    return UOT_ERR_ARG;
+  switch (p->tile_rows) {
+    case 0: case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332: break;
+    default: return UOT_ERR_ARG;
+  }
   if ((p->flags & UOT_ALLOW_SIGNED) && p->mode != UOT_DIST) return UOT_ERR_ARG;
   if (p->nx < 0 || p->ny < 0) return UOT_ERR_SHAPE;
   if (p->nx > 0 && p->ny > 0 && p->tau1 > 0.0 && !(p->flags & UOT_UNSAFE_STEPS)) {
@@ -269,7 +277,9 @@ struct Job {
   std::vector<Tile> tiles;
   std::vector<double> knorm2;
   long total_px = 0;
-  int ty = 8;
+  int ty = 8;        // rows per tile
+  int shape = 8;     // kernel shape code: rows, or 100 + rows for the vectorised kernel
+  bool vec_ok = false;
 };
 
 Planes planes_of(const uot_state& s) { return Planes{s.Mx, s.My, s.r, s.a, s.x0, s.x1}; }
@@ -297,7 +307,7 @@ uot_status validate_state(const uot_params& p, const uot_state* s) {
 }
 
 uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset, Job& J,
-                int force_ty = 0, bool* cached = nullptr) {
+                int force_ty = 0, bool* cached = nullptr, bool ptrs_aligned = false) {
   const uot_params& p = h->prm;
   if (B < 1 || !nx || !ny || !offset) return UOT_ERR_ARG;
   J.B = B;
@@ -315,6 +325,9 @@ uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, cons
   for (int b = 1; b < B; ++b)
     if (ranges[b].first < ranges[b - 1].second) return UOT_ERR_SHAPE;
   J.total_px = total;
+  J.vec_ok = ptrs_aligned;
+  for (int b = 0; b < B; ++b)
+    if (nx[b] % 4 != 0 || offset[b] % 4 != 0) J.vec_ok = false;
   const int resid = resid_of(p);
   // tile rows: explicit, autotuned, or heuristic
   int ty = force_ty > 0 ? force_ty : p.tile_rows;
@@ -324,8 +337,13 @@ uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, cons
     tune_load_locked();
     auto it = g_tune_cache.find(tune_key(p.mode, resid, p.bc, total));
     if (cached) *cached = it != g_tune_cache.end();
-    ty = it != g_tune_cache.end() ? it->second : heuristic_rows(total);
+    ty = it != g_tune_cache.end() ? it->second : heuristic_shape(total);
   }
+  // the vectorised kernels (100 * variant + rows) need 16-byte aligned rows;
+  // otherwise run the scalar kernel of the same rows
+  if (ty >= 100 && !J.vec_ok) ty %= 100;
+  J.shape = ty;
+  ty %= 100;
   J.ty = ty;
   J.tiles.clear();
   for (int b = 0; b < B; ++b) {
@@ -536,7 +554,7 @@ uot_status enqueue_window(Launch& L, int W, bool check) {
   uot_handle* h = L.h;
   const uot_params& p = h->prm;
   for (int i = 0; i < W; ++i)
-    HIPCHK(launch_iter(p.mode, L.resid, p.bc, L.J->ty, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
+    HIPCHK(launch_iter(p.mode, L.resid, p.bc, L.J->shape, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
   if (check) {
     HIPCHK(launch_check(p.mode, L.resid, p.bc, L.grid_aux, L.chk, h->stream));
     HIPCHK(launch_reduce_decide(L.dec, h->d_partial, h->stream));
@@ -558,7 +576,7 @@ uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
   int c = check;
   put(&c, sizeof(c));
   put(&L.grid_iter, sizeof(int));
-  put(&L.J->ty, sizeof(int));
+  put(&L.J->shape, sizeof(int));
   put(&h->prm, sizeof(h->prm));
   if (h->gexec && key == h->gkey) {
     *out = h->gexec;
@@ -665,7 +683,10 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
                     const float* src, const float* dst, uot_state* st, Job& J) {
   const uot_params& p = h->prm;
   const int resid = resid_of(p);
-  const int cand[4] = {4, 8, 16, 32};
+  std::vector<int> cand = {4, 8, 16, 32};
+  if (J.vec_ok) {
+    for (int c : {116, 132, 316, 332}) cand.push_back(c);
+  }
   Job J4;
   uot_status s = plan(h, B, nx, ny, offset, J4, 4);
   if (s != UOT_OK) return s;
@@ -679,10 +700,10 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_ty = J.ty;
+  int best_ty = J.shape;
   for (int ty : cand) {
     Job Jt;
-    s = plan(h, B, nx, ny, offset, Jt, ty);
+    s = plan(h, B, nx, ny, offset, Jt, ty, nullptr, J.vec_ok);
     if (s != UOT_OK) break;
     HIPCHK(hipMemcpyAsync(h->d_pairs, Jt.pairs.data(), B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
     s = upload_live(h, Jt, ones.data());
@@ -709,7 +730,7 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
     g_tune_cache[tune_key(p.mode, resid, p.bc, J.total_px)] = best_ty;
     tune_store_locked();
   }
-  s = plan(h, B, nx, ny, offset, J, best_ty);
+  s = plan(h, B, nx, ny, offset, J, best_ty, nullptr, J.vec_ok);
   if (s != UOT_OK) return s;
   s = ensure_workspace(h, J);
   if (s != UOT_OK) return s;
@@ -728,7 +749,9 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   if (s != UOT_OK) return s;
   Job J;
   bool cached = true;
-  s = plan(h, B, nx, ny, offset, J, 0, &cached);
+  const bool ptrs_aligned = aligned16(src) && aligned16(dst) && aligned16(st->Mx) && aligned16(st->My) &&
+                            aligned16(st->r) && aligned16(st->a) && aligned16(st->x0) && aligned16(st->x1);
+  s = plan(h, B, nx, ny, offset, J, 0, &cached, ptrs_aligned);
   if (s != UOT_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
   s = ensure_workspace(h, J);
@@ -783,7 +806,7 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   L.h = h;
   L.J = &J;
   L.resid = resid;
-  L.grid_iter = iter_grid(h, p.mode, resid, p.bc, J.ty, (int)J.tiles.size());
+  L.grid_iter = iter_grid(h, p.mode, resid, p.bc, J.shape, (int)J.tiles.size());
   L.grid_aux = aux_grid(h, (int)J.tiles.size());
   const Planes A = planes_of(*st), Bp = shadow_planes(h);
   const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
@@ -849,7 +872,7 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   const bool run_tail = n_active > 0 && tail > 0;
   if (run_tail) {
     for (int i = 0; i < tail; ++i)
-      HIPCHK(launch_iter(p.mode, resid, p.bc, J.ty, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
+      HIPCHK(launch_iter(p.mode, resid, p.bc, J.shape, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
   }
   const bool odd = run_tail && (tail & 1);
   // final evaluation of every pair, then the final decision
@@ -899,8 +922,75 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
     r.iters = h->h_i32[B + b];
     r.status = h->h_i32[2 * B + b];
     r.seconds = secs;
+    r.tile_rows = J.shape;
     if (r.status == UOT_CONVERGED && relres[b] == 0.0) r.rel_res = 0.0;
   }
+  return UOT_OK;
+}
+
+// Back-to-back fused-iteration launches over a batch layout, replayed from one
+// captured graph and bracketed by events (every pair live).
+uot_status time_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
+                     const float* src, const float* dst, uot_state* st, int32_t n, double* ms_per_iter,
+                     int32_t* tile_rows) {
+  const uot_params& p = h->prm;
+  if (!src || !dst || !ms_per_iter || n < 1) return UOT_ERR_ARG;
+  uot_status s = validate_state(p, st);
+  if (s != UOT_OK) return s;
+  Job J;
+  const bool ptrs_aligned = aligned16(src) && aligned16(dst) && aligned16(st->Mx) && aligned16(st->My) &&
+                            aligned16(st->r) && aligned16(st->a) && aligned16(st->x0) && aligned16(st->x1);
+  s = plan(h, B, nx, ny, offset, J, 0, nullptr, ptrs_aligned);
+  if (s != UOT_OK) return s;
+  if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+  s = ensure_workspace(h, J);
+  if (s != UOT_OK) return s;
+  HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                        h->stream));
+  s = run_setup(h, J, src, dst, st, true, false);
+  if (s != UOT_OK) return s;
+  for (int b = 0; b < B; ++b) h->h_i32[b] = 1;
+  HIPCHK(hipMemcpyAsync(h->d_i32, h->h_i32, (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  s = upload_live(h, J, h->h_i32);
+  if (s != UOT_OK) return s;
+  const int resid = resid_of(p);
+  const int grid = iter_grid(h, p.mode, resid, p.bc, J.shape, (int)J.tiles.size());
+  const Planes A = planes_of(*st), Bp = shadow_planes(h);
+  const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
+  const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
+  const IterArgs bwd{Bp, A, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
+  const int nn = n + (n & 1);
+  // the launches are captured once and replayed, as the solver does
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < nn && le == hipSuccess; ++i)
+    le = launch_iter(p.mode, resid, p.bc, J.shape, grid, (i & 1) ? bwd : fwd, h->stream);
+  hipError_t ce = hipStreamEndCapture(h->stream, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return UOT_ERR_DEVICE;
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(ie);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipGraphLaunch(ex, h->stream));  // warm replay
+  HIPCHK(hipEventRecord(e0, h->stream));
+  HIPCHK(hipGraphLaunch(ex, h->stream));
+  HIPCHK(hipEventRecord(e1, h->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(ex);
+  *ms_per_iter = (double)ms / nn;
+  if (tile_rows) *tile_rows = J.shape;
   return UOT_OK;
 }
 
@@ -931,67 +1021,25 @@ uot_status uot_solve_batched(uot_handle* h, int32_t B, const int32_t* nx, const 
 }
 
 uot_status uot_time_iterations(uot_handle* h, const float* src, const float* dst, uot_state* st, int32_t n,
-                               double* ms_per_iter) {
-  if (!h || !src || !dst || !ms_per_iter || n < 1) return UOT_ERR_ARG;
+                               double* ms_per_iter, int32_t* tile_rows) {
+  if (!h) return UOT_ERR_ARG;
   const uot_params& p = h->prm;
   if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
-  uot_status s = validate_state(p, st);
-  if (s != UOT_OK) return s;
+  const int32_t nx = p.nx, ny = p.ny;
+  const int64_t off = 0;
   try {
-    const int32_t nx = p.nx, ny = p.ny;
-    const int64_t off = 0;
-    Job J;
-    s = plan(h, 1, &nx, &ny, &off, J);
-    if (s != UOT_OK) return s;
-    if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
-    s = ensure_workspace(h, J);
-    if (s != UOT_OK) return s;
-    HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
-                          h->stream));
-    s = run_setup(h, J, src, dst, st, true, false);
-    if (s != UOT_OK) return s;
-    h->h_i32[0] = 1;
-    HIPCHK(hipMemcpyAsync(h->d_i32, h->h_i32, sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-    s = upload_live(h, J, h->h_i32);
-    if (s != UOT_OK) return s;
-    const int resid = resid_of(p);
-    const int grid = iter_grid(h, p.mode, resid, p.bc, J.ty, (int)J.tiles.size());
-    const Planes A = planes_of(*st), Bp = shadow_planes(h);
-    const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
-    const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
-    const IterArgs bwd{Bp, A, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
-    const int nn = n + (n & 1);
-    // the launches are captured once and replayed, as the solver does
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hipSuccess;
-    for (int i = 0; i < nn && le == hipSuccess; ++i)
-      le = launch_iter(p.mode, resid, p.bc, J.ty, grid, (i & 1) ? bwd : fwd, h->stream);
-    hipError_t ce = hipStreamEndCapture(h->stream, &g);
-    if (le != hipSuccess || ce != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return UOT_ERR_DEVICE;
-    }
-    hipGraphExec_t ex = nullptr;
-    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HIPCHK(ie);
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipGraphLaunch(ex, h->stream));  // warm replay
-    HIPCHK(hipEventRecord(e0, h->stream));
-    HIPCHK(hipGraphLaunch(ex, h->stream));
-    HIPCHK(hipEventRecord(e1, h->stream));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipGraphExecDestroy(ex);
-    *ms_per_iter = (double)ms / nn;
-    return UOT_OK;
+    return time_core(h, 1, &nx, &ny, &off, src, dst, st, n, ms_per_iter, tile_rows);
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_time_iterations_batched(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny,
+                                       const int64_t* offset, const float* src, const float* dst,
+                                       uot_state* packed, int32_t n, double* ms_per_iter, int32_t* tile_rows) {
+  if (!h) return UOT_ERR_ARG;
+  try {
+    return time_core(h, B, nx, ny, offset, src, dst, packed, n, ms_per_iter, tile_rows);
   } catch (...) {
     return UOT_ERR_OOM;
   }

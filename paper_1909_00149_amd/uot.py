@@ -171,13 +171,32 @@ class Solver:
         return state
 
     def time_iterations(self, src, dst, state, n):
-        """uot_time_iterations: average ms per fused-iteration launch."""
+        """uot_time_iterations: (average ms per fused-iteration launch, the
+        kernel shape code that ran)."""
         cs = _cstate(state)
         ms = ctypes.c_double()
-        rc = self.lib.uot_time_iterations(self._h, _ptr(src), _ptr(dst), ctypes.byref(cs), int(n), ctypes.byref(ms))
+        shape = ctypes.c_int32()
+        rc = self.lib.uot_time_iterations(self._h, _ptr(src), _ptr(dst), ctypes.byref(cs), int(n), ctypes.byref(ms),
+                                          ctypes.byref(shape))
         if rc != 0:
             raise UOTError(rc, "uot_time_iterations")
-        return ms.value
+        return ms.value, shape.value
+
+    def time_iterations_batched(self, src, dst, nx, ny, offset, state, n):
+        """uot_time_iterations_batched on packed planes: (average ms per
+        launch with every pair live, the kernel shape code that ran)."""
+        B = len(nx)
+        ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
+        ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
+        ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+        cs = _cstate(state)
+        ms = ctypes.c_double()
+        shape = ctypes.c_int32()
+        rc = self.lib.uot_time_iterations_batched(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs),
+                                                  int(n), ctypes.byref(ms), ctypes.byref(shape))
+        if rc != 0:
+            raise UOTError(rc, "uot_time_iterations_batched")
+        return ms.value, shape.value
 
     def objective(self, src, dst, state, prev=None):
         cs = _cstate(state)

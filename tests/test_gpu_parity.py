@@ -114,12 +114,17 @@ def test_fixed_iterations_all_modes(dev, mode, balanced, resid, bc, shape):
         assert abs(rep["dual"] - g.dual) <= VAL_TOL * max(abs(g.dual), abs(g.primal))
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16, 32])
-@pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 1), (PROX_FIXED, True, 1)])
-def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid):
-    """Every tile shape computes each pixel with the same arithmetic: the
-    iterates are bitwise identical across tile shapes."""
-    p, q = pair_inputs((45, 133), 7, mode)
+@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332])
+@pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 1), (PROX_FIXED, True, 1),
+                                                 (DIST, True, 1), (PROX, False, 2)])
+@pytest.mark.parametrize("shape", [(45, 133), (45, 132), (70, 256)])
+def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):
+    """Every tile shape, scalar or vectorised (116/132; rows starting on
+    16-byte boundaries, else the scalar kernel), computes each pixel with
+    the same arithmetic: the iterates are bitwise identical."""
+    p, q = pair_inputs(shape, 7, mode)
+    if balanced and mode == DIST:
+        q = (q * (p.astype(np.float64).sum() / q.astype(np.float64).sum())).astype(np.float32)
     base, _ = run_pair(dev, p, q, mode, balanced, resid, iters=40, tile_rows=4)
     st, _ = run_pair(dev, p, q, mode, balanced, resid, iters=40, tile_rows=ty)
     for k in planes_for(mode, balanced):

@@ -1,0 +1,84 @@
+"""The profiling entry points uot_time_iterations(_batched) time the solver's
+own fused-iteration launches: from a zero state, n timed launches (plus the
+untimed replay before them, 2n in all) must leave bit for bit the state a
+cold solve of exactly 2n iterations leaves, and report the kernel shape that
+ran (the vectorised shapes fall back to the scalar kernel of the same rows
+on grids whose rows are not 16-byte aligned)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.ops import DIST, PROX
+from paper_1909_00149_amd import uot as G
+
+pytestmark = pytest.mark.gpu
+
+PLANES = {(DIST, False): ("Mx", "My", "r", "a"), (DIST, True): ("Mx", "My", "a"),
+          (PROX, False): ("Mx", "My", "r", "a", "x0", "x1")}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch.device("cuda:0")
+
+
+def pair(shape, seed, balanced):
+    rng = np.random.default_rng(seed)
+    p = (rng.uniform(0, 1, shape) * (rng.uniform(0, 1, shape) < 0.4)).astype(np.float32)
+    q = (rng.uniform(0, 1, shape) * (rng.uniform(0, 1, shape) < 0.4)).astype(np.float32)
+    p[0, 0] += 0.5
+    q[-1, -1] += 0.5
+    if balanced:
+        q = (q * np.float32(p.astype(np.float64).sum() / q.astype(np.float64).sum())).astype(np.float32)
+    return p, q
+
+
+@pytest.mark.parametrize("mode,balanced", [(DIST, False), (DIST, True), (PROX, False)])
+@pytest.mark.parametrize("shape", [(40, 128), (45, 133)])
+@pytest.mark.parametrize("ty", [4, 116, 316])
+def test_timed_launches_are_solver_iterations(dev, mode, balanced, shape, ty):
+    p, q = pair(shape, 3, balanced)
+    ny, nx = shape
+    src, dst = torch.from_numpy(p).to(dev), torch.from_numpy(q).to(dev)
+    n = 6
+    kw = dict(nx=nx, ny=ny, mode=mode, balanced=balanced, mu=2.0, rho=0.5, tile_rows=ty)
+    ref, rep = G.Solver(G.Params(max_iter=2 * n, tol=0.0, **kw)).solve(src, dst)
+    st = G.new_state(mode, balanced, shape, dev)
+    ms, ran = G.Solver(G.Params(**kw)).time_iterations(src, dst, st, n)
+    torch.cuda.synchronize()
+    vec_ok = nx % 4 == 0
+    assert ran == (ty if vec_ok or ty < 100 else ty % 100)
+    assert rep["tile_rows"] == ran
+    assert rep["iters"] == 2 * n
+    assert ms > 0.0
+    for k in PLANES[(mode, balanced)]:
+        assert torch.equal(st[k], ref[k]), k
+
+
+def test_batched_timing_matches_batched_solve(dev):
+    shapes = [(33, 64), (8, 200), (70, 12), (1, 4)]
+    pairs = [pair(s, 10 + i, False) for i, s in enumerate(shapes)]
+    src, nx, ny, offs = G.pack([torch.from_numpy(p).to(dev) for p, _ in pairs])
+    dst, _, _, _ = G.pack([torch.from_numpy(q).to(dev) for _, q in pairs])
+    n = 5  # rounded up to 6 launches per replay
+    kw = dict(mode=DIST, balanced=False, mu=2.0, tile_rows=116)
+    ref, reps = G.Solver(G.Params(max_iter=12, tol=0.0, **kw)).solve_batched(src, dst, nx, ny, offs)
+    st = G.new_state(DIST, False, src.numel(), dev)
+    ms, ran = G.Solver(G.Params(**kw)).time_iterations_batched(src, dst, nx, ny, offs, st, n)
+    torch.cuda.synchronize()
+    assert ran == 116 and all(r["tile_rows"] == 116 for r in reps)
+    assert ms > 0.0
+    for k in PLANES[(DIST, False)]:
+        assert torch.equal(st[k], ref[k]), k
+
+
+def test_timing_rejects_bad_arguments(dev):
+    p, q = pair((16, 16), 0, False)
+    src, dst = torch.from_numpy(p).to(dev), torch.from_numpy(q).to(dev)
+    s = G.Solver(G.Params(nx=16, ny=16, mode=DIST, mu=1.0))
+    st = G.new_state(DIST, False, (16, 16), dev)
+    with pytest.raises(G.UOTError):
+        s.time_iterations(src, dst, st, 0)
+    with pytest.raises(G.UOTError):
+        s.time_iterations_batched(src.reshape(-1), dst.reshape(-1), [16, 16], [16, 16], [0, 8], st, 4)
