@@ -25,7 +25,8 @@ Workloads (seeded synthetic inputs):
             rel_res <= 1e-4 or 2000 iterations, adaptive step balance
   balanced64  one balanced 64x64 pair, exactly 500 iterations
   ragged256 256 pairs with sides log-uniform in [32, 512] in one batched
-            solve, rel_res <= 1e-4 or 2000 iterations per pair
+            solve, rel_res <= 1e-4 or 2000 iterations per pair (batches are
+            packed with rows padded to 256-byte boundaries)
   video63   the 63 consecutive frame pairs of a 64-frame 256x256 video,
             prox mode (rho = 1, mu = 2), one batched solve
   sweepN    one NxN pair, exactly 200 iterations (the size sweep)
@@ -195,8 +196,11 @@ def main():
     flags = G.UOT_ADAPTIVE_STEPS if W["adaptive"] else 0
     batched = len(pairs) > 1
     if batched:
-        src, nx, ny, offs = G.pack(imgs_p)
-        dst, _, _, _ = G.pack(imgs_q)
+        # every row starts on a 256-byte boundary (one 64-pixel tile row), so
+        # no cache line or HBM burst is shared between tiles or pairs; the
+        # padding is never touched and not counted
+        src, nx, ny, pitch, offs = G.pack_pitched(imgs_p, align=64)
+        dst, _, _, _, _ = G.pack_pitched(imgs_q, align=64)
         prm = G.Params(mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"], tol=W["tol"],
                        max_iter=W["max_iter"], check_every=20, flags=flags)
         state = G.new_state(W["mode"], W["balanced"], src.numel(), dev)
@@ -211,7 +215,7 @@ def main():
 
     def step():
         if batched:
-            _, reps = solver.solve_batched(src, dst, nx, ny, offs, state)
+            _, reps = solver.solve_batched(src, dst, nx, ny, offs, state, pitch=pitch)
         else:
             _, rep = solver.solve(src, dst, state)
             reps = [rep]
@@ -235,8 +239,8 @@ def main():
     kstate = G.new_state(W["mode"], W["balanced"], src.shape if not batched else src.numel(), dev)
     ksolver = G.Solver(prm)
     if batched:
-        ksolver.time_iterations_batched(src, dst, nx, ny, offs, kstate, 20)
-        ms, shape = ksolver.time_iterations_batched(src, dst, nx, ny, offs, kstate, args.kernel_iters)
+        ksolver.time_iterations_batched(src, dst, nx, ny, offs, kstate, 20, pitch=pitch)
+        ms, shape = ksolver.time_iterations_batched(src, dst, nx, ny, offs, kstate, args.kernel_iters, pitch=pitch)
     else:
         ksolver.time_iterations(src, dst, kstate, 20)
         ms, shape = ksolver.time_iterations(src, dst, kstate, args.kernel_iters)

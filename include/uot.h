@@ -40,7 +40,7 @@
  *
  * Memory layout: every image and state plane is FP32, ny rows of nx pixels
  * with x fastest (element j*nx + i is pixel (i, j), the paper's column-major
- * vec with i first).
+ * vec with i first); a row stride (pitch) larger than nx may be given.
  *
  * Ownership: every image and state pointer is a DEVICE pointer owned by the
  * caller.  The library never frees, reallocates or keeps them past a call.
@@ -104,9 +104,11 @@ typedef struct uot_params {
                            64-wide tile; 116 / 132 = the 16- / 32-row vectorised kernel;
                            316 / 332 = the same with non-temporal stores (for states
                            larger than the last-level cache).  The vectorised shapes
-                           run when every row starts on a 16-byte boundary (nx and pair
-                           offsets multiples of 4, planes 16-byte aligned); otherwise
-                           the scalar kernel of the same rows runs                        */
+                           take any row layout; they run at full speed when every row
+                           starts on a 16-byte boundary (see pitch)                      */
+  int32_t pitch;        /* row stride of uot_solve's planes in elements; 0 = nx.  A
+                           pitch rounded up to a multiple of 4 puts every row on a
+                           16-byte boundary; the padding is never read or written   */
 } uot_params;
 
 /* Device planes of one state.  Required planes by mode:
@@ -153,14 +155,26 @@ uot_status uot_create(const uot_params *prm, void *hip_stream, uot_handle **out)
 uot_status uot_solve(uot_handle *h, const float *src, const float *dst, uot_state *st,
                      uot_report *rep);
 
-/* B independent pairs of uneven sizes, solved together.  nx, ny, offset are
- * HOST arrays of length B; pair b occupies elements [offset[b], offset[b] +
+/* B independent pairs of uneven sizes, solved together (the T-1 frame-pair
+ * problems of Sec. IV-B are one such batch).  nx, ny, offset are HOST
+ * arrays of length B; pair b occupies elements [offset[b], offset[b] +
  * nx[b]*ny[b]) of src, dst and of every plane of *packed (ranges must not
  * overlap).  reps: host array of B reports.  Each pair gets its own steps
  * (from its own ||K||) unless tau1/tau2 are given, and stops on its own. */
 uot_status uot_solve_batched(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
                              const int64_t *offset, const float *src, const float *dst,
                              uot_state *packed, uot_report *reps);
+
+/* uot_solve_batched with a row stride per pair: pixel (x, y) of pair b is
+ * element offset[b] + y * pitch[b] + x; pitch (HOST, length B, each >= nx[b])
+ * may be NULL (pitch = nx).  Pair b spans [offset[b], offset[b] + pitch[b] *
+ * (ny[b] - 1) + nx[b]); spans must not overlap.  The padding between rows is
+ * never read or written.  Rows starting on 16-byte boundaries (pitches and
+ * offsets multiples of 4) let the fused kernel move every pixel with 16-byte
+ * accesses; that is the layout to choose for batches of arbitrary widths. */
+uot_status uot_solve_batched_pitched(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
+                                     const int32_t *pitch, const int64_t *offset, const float *src,
+                                     const float *dst, uot_state *packed, uot_report *reps);
 
 /* Evaluates the report fields (rel_res against prev if prev != NULL, the
  * certified gap, feasibility, objective) of a given state without iterating.
@@ -185,6 +199,11 @@ uot_status uot_poisson(uot_handle *h, int32_t nx, int32_t ny, double alpha, cons
 uot_status uot_init_poisson(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
                             const int64_t *offset, const float *src, const float *dst, uot_state *packed);
 
+/* The same with row strides (layout as uot_solve_batched_pitched). */
+uot_status uot_init_poisson_pitched(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
+                                    const int32_t *pitch, const int64_t *offset, const float *src,
+                                    const float *dst, uot_state *packed);
+
 /* Profiling aid: captures n (rounded up to even) back-to-back launches of
  * the fused iteration kernel on the handle's grid and stream into a graph,
  * replays it once untimed and once bracketed by HIP events, starting from
@@ -195,12 +214,13 @@ uot_status uot_init_poisson(uot_handle *h, int32_t B, const int32_t *nx, const i
 uot_status uot_time_iterations(uot_handle *h, const float *src, const float *dst, uot_state *st,
                                int32_t n, double *ms_per_iter, int32_t *tile_rows);
 
-/* The same over a batch layout (as uot_solve_batched), every pair live: the
- * launch the batched solve runs until its first pair stops. */
+/* The same over a batch layout (as uot_solve_batched_pitched; pitch may be
+ * NULL), every pair live: the launch the batched solve runs until its first
+ * pair stops. */
 uot_status uot_time_iterations_batched(uot_handle *h, int32_t B, const int32_t *nx, const int32_t *ny,
-                                       const int64_t *offset, const float *src, const float *dst,
-                                       uot_state *packed, int32_t n, double *ms_per_iter,
-                                       int32_t *tile_rows);
+                                       const int32_t *pitch, const int64_t *offset, const float *src,
+                                       const float *dst, uot_state *packed, int32_t n,
+                                       double *ms_per_iter, int32_t *tile_rows);
 
 /* Releases the handle's workspace.  NULL is a no-op. */
 void uot_destroy(uot_handle *h);

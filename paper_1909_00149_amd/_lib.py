@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
                 ("tau1", ctypes.c_double), ("tau2", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("tile_rows", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("pitch", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -60,13 +60,19 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(State), ctypes.POINTER(Report)]),
+    "uot_solve_batched_pitched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                                 ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.POINTER(State), ctypes.POINTER(Report)]),
     "uot_objective": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.POINTER(State), ctypes.POINTER(State), ctypes.POINTER(Report)]),
     "uot_time_iterations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.POINTER(State), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "uot_time_iterations_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                                   ctypes.POINTER(ctypes.c_int64),
                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State),
                                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_int32)]),
@@ -76,6 +82,10 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(State)]),
+    "uot_init_poisson_pitched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State)]),
     "uot_destroy": (None, [ctypes.c_void_p]),
     "uot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }

@@ -5,6 +5,14 @@
 Every HIP source is compiled with packed-FP32 instruction generation turned
 off (-Xclang -target-feature -Xclang -packed-fp32-ops); hipcc's host pass
 warns that it does not know that feature, which is harmless.
+
+Multiply-adds are fused only where one source expression holds both
+(-ffp-contract=on).  hipcc's default lets the back end fuse across
+statements, and it does so differently in differently shaped code (the
+scalar kernel, and the full and partial quads of the vectorised kernel), so
+kernels written with the same per-pixel formulas would round differently;
+with expression-level fusion every tile shape computes every pixel
+identically.
 """
 from __future__ import annotations
 
@@ -21,7 +29,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libuot.so")
 
 ARCH = os.environ.get("UOT_OFFLOAD_ARCH", "gfx950")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -95,7 +95,7 @@ int heuristic_shape(long total_px) {
   return 316;
 }
 
-bool aligned16(const void* p) { return p == nullptr || ((uintptr_t)p & 15u) == 0; }
+bool aligned4(const void* p) { return p == nullptr || ((uintptr_t)p & 3u) == 0; }
 
 template <class T>
 hipError_t grow(T** p, size_t* cap, size_t n) {
@@ -221,6 +221,7 @@ uot_status uot_check_params(const uot_params* p) {
   }
   if ((p->flags & UOT_ALLOW_SIGNED) && p->mode != UOT_DIST) return UOT_ERR_ARG;
   if (p->nx < 0 || p->ny < 0) return UOT_ERR_SHAPE;
+  if (p->pitch != 0 && p->pitch < p->nx) return UOT_ERR_SHAPE;
   if (p->nx > 0 && p->ny > 0 && p->tau1 > 0.0 && !(p->flags & UOT_UNSAFE_STEPS)) {
     const double k2 = uot_knorm2(p->nx, p->ny, p->mode, p->balanced, p->bc);
     if (p->tau1 * p->tau2 * k2 >= 1.0) return UOT_ERR_STEP;
@@ -276,7 +277,8 @@ struct Job {
   std::vector<PairInfo> pairs;
   std::vector<Tile> tiles;
   std::vector<double> knorm2;
-  long total_px = 0;
+  long total_px = 0;  // extent of the packed planes (elements)
+  long npx = 0;       // pixels of all pairs
   int ty = 8;        // rows per tile
   int shape = 8;     // kernel shape code: rows, or 100 + rows for the vectorised kernel
   bool vec_ok = false;
@@ -306,28 +308,41 @@ uot_status validate_state(const uot_params& p, const uot_state* s) {
   return UOT_OK;
 }
 
-uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset, Job& J,
-                int force_ty = 0, bool* cached = nullptr, bool ptrs_aligned = false) {
+// Where the pairs of a call live in the packed planes (host arrays of B):
+// pixel (x, y) of pair b is element offset[b] + y * pitch[b] + x; pitch ==
+// nullptr means pitch[b] = nx[b] (rows packed back to back).
+struct Layout {
+  int B;
+  const int32_t *nx, *ny, *pitch;
+  const int64_t* offset;
+  int32_t pitch_of(int b) const { return pitch ? pitch[b] : nx[b]; }
+};
+
+uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* cached = nullptr,
+                bool ptrs_aligned = false) {
   const uot_params& p = h->prm;
+  const int B = L.B;
+  const int32_t *nx = L.nx, *ny = L.ny;
+  const int64_t* offset = L.offset;
   if (B < 1 || !nx || !ny || !offset) return UOT_ERR_ARG;
   J.B = B;
   J.pairs.resize(B);
   J.knorm2.resize(B);
   std::vector<std::pair<int64_t, int64_t>> ranges(B);
-  long total = 0;
+  long total = 0, npx = 0;
   for (int b = 0; b < B; ++b) {
-    if (nx[b] < 1 || ny[b] < 1 || offset[b] < 0) return UOT_ERR_SHAPE;
-    const int64_t n = (int64_t)nx[b] * ny[b];
-    ranges[b] = {offset[b], offset[b] + n};
-    total = std::max<long>(total, offset[b] + n);
+    if (nx[b] < 1 || ny[b] < 1 || offset[b] < 0 || L.pitch_of(b) < nx[b]) return UOT_ERR_SHAPE;
+    const int64_t extent = (int64_t)L.pitch_of(b) * (ny[b] - 1) + nx[b];
+    ranges[b] = {offset[b], offset[b] + extent};
+    total = std::max<long>(total, offset[b] + extent);
+    npx += (long)nx[b] * ny[b];
   }
   std::sort(ranges.begin(), ranges.end());
   for (int b = 1; b < B; ++b)
     if (ranges[b].first < ranges[b - 1].second) return UOT_ERR_SHAPE;
   J.total_px = total;
+  J.npx = npx;
   J.vec_ok = ptrs_aligned;
-  for (int b = 0; b < B; ++b)
-    if (nx[b] % 4 != 0 || offset[b] % 4 != 0) J.vec_ok = false;
   const int resid = resid_of(p);
   // tile rows: explicit, autotuned, or heuristic
   int ty = force_ty > 0 ? force_ty : p.tile_rows;
@@ -335,12 +350,13 @@ uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, cons
   if (ty == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
-    auto it = g_tune_cache.find(tune_key(p.mode, resid, p.bc, total));
+    auto it = g_tune_cache.find(tune_key(p.mode, resid, p.bc, npx));
     if (cached) *cached = it != g_tune_cache.end();
-    ty = it != g_tune_cache.end() ? it->second : heuristic_shape(total);
+    ty = it != g_tune_cache.end() ? it->second : heuristic_shape(npx);
   }
-  // the vectorised kernels (100 * variant + rows) need 16-byte aligned rows;
-  // otherwise run the scalar kernel of the same rows
+  // the vectorised kernels (100 * variant + rows) take any row layout but
+  // need every plane 4-byte aligned; otherwise the scalar kernel of the same
+  // rows runs
   if (ty >= 100 && !J.vec_ok) ty %= 100;
   J.shape = ty;
   ty %= 100;
@@ -365,7 +381,7 @@ uot_status plan(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, cons
     for (int y = 0; y < ny[b]; y += ty)
       for (int x = 0; x < nx[b]; x += TX) J.tiles.push_back(Tile{b, x, y, 0});
     P.tile_count = (int32_t)J.tiles.size() - P.tile_begin;
-    P.pad = 0;
+    P.pitch = L.pitch_of(b);
   }
   return UOT_OK;
 }
@@ -661,11 +677,11 @@ uot_status balanced_primal(uot_handle* h, const Job& J, const float* src, const 
   for (int b = 0; b < J.B; ++b) {
     const PairInfo& P = J.pairs[b];
     const long o = P.off;
-    HIPCHK(launch_infeasibility(st->Mx + o, st->My + o, src + o, dst + o, h->pw[3], P.nx, P.ny, h->stream));
+    HIPCHK(launch_infeasibility(st->Mx + o, st->My + o, src + o, dst + o, h->pw[3], P.nx, P.ny, P.pitch, h->stream));
     s = poisson_grid(h, P.nx, P.ny, 0.0, h->pw[3], h->pw[2]);
     if (s != UOT_OK) return s;
     const int nb = repaired_norm_blocks(P.nx, P.ny);
-    HIPCHK(launch_repaired_norm(st->Mx + o, st->My + o, h->pw[2], P.nx, P.ny, h->d_pp, h->stream));
+    HIPCHK(launch_repaired_norm(st->Mx + o, st->My + o, h->pw[2], P.nx, P.ny, P.pitch, h->d_pp, h->stream));
     HIPCHK(hipMemcpyAsync(h->h_pp, h->d_pp, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     double acc = 0.0;
@@ -679,8 +695,8 @@ uot_status balanced_primal(uot_handle* h, const Job& J, const float* src, const 
 // state after setup is read, the shadow copy is written, nothing else
 // changes), keeps the fastest for the (mode, variant, boundary, size class)
 // key, persists the table to $UOT_AUTOTUNE_CACHE when set, and re-plans J.
-uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
-                    const float* src, const float* dst, uot_state* st, Job& J) {
+uot_status autotune(uot_handle* h, const Layout& L, const float* src, const float* dst, uot_state* st, Job& J) {
+  const int B = L.B;
   const uot_params& p = h->prm;
   const int resid = resid_of(p);
   std::vector<int> cand = {4, 8, 16, 32};
@@ -688,7 +704,7 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
     for (int c : {116, 132, 316, 332}) cand.push_back(c);
   }
   Job J4;
-  uot_status s = plan(h, B, nx, ny, offset, J4, 4);
+  uot_status s = plan(h, L, J4, 4);
   if (s != UOT_OK) return s;
   s = ensure_workspace(h, J4);  // the 4-row list is the longest
   if (s != UOT_OK) return s;
@@ -703,7 +719,7 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
   int best_ty = J.shape;
   for (int ty : cand) {
     Job Jt;
-    s = plan(h, B, nx, ny, offset, Jt, ty, nullptr, J.vec_ok);
+    s = plan(h, L, Jt, ty, nullptr, J.vec_ok);
     if (s != UOT_OK) break;
     HIPCHK(hipMemcpyAsync(h->d_pairs, Jt.pairs.data(), B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
     s = upload_live(h, Jt, ones.data());
@@ -727,10 +743,10 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
   if (s != UOT_OK) return s;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(p.mode, resid, p.bc, J.total_px)] = best_ty;
+    g_tune_cache[tune_key(p.mode, resid, p.bc, J.npx)] = best_ty;
     tune_store_locked();
   }
-  s = plan(h, B, nx, ny, offset, J, best_ty, nullptr, J.vec_ok);
+  s = plan(h, L, J, best_ty, nullptr, J.vec_ok);
   if (s != UOT_OK) return s;
   s = ensure_workspace(h, J);
   if (s != UOT_OK) return s;
@@ -740,8 +756,9 @@ uot_status autotune(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, 
   return UOT_OK;
 }
 
-uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
-                      const float* src, const float* dst, uot_state* st, uot_report* reps) {
+uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const float* dst, uot_state* st,
+                      uot_report* reps) {
+  const int B = lay.B;
   Timer timer;
   const uot_params& p = h->prm;
   if (!src || !dst || !reps) return UOT_ERR_ARG;
@@ -749,9 +766,9 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   if (s != UOT_OK) return s;
   Job J;
   bool cached = true;
-  const bool ptrs_aligned = aligned16(src) && aligned16(dst) && aligned16(st->Mx) && aligned16(st->My) &&
-                            aligned16(st->r) && aligned16(st->a) && aligned16(st->x0) && aligned16(st->x1);
-  s = plan(h, B, nx, ny, offset, J, 0, &cached, ptrs_aligned);
+  const bool ptrs_aligned = aligned4(src) && aligned4(dst) && aligned4(st->Mx) && aligned4(st->My) &&
+                            aligned4(st->r) && aligned4(st->a) && aligned4(st->x0) && aligned4(st->x1);
+  s = plan(h, lay, J, 0, &cached, ptrs_aligned);
   if (s != UOT_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
   s = ensure_workspace(h, J);
@@ -766,7 +783,7 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
   s = check_setup_sums(h, J, warm);
   if (s != UOT_OK) return s;
   if ((p.flags & UOT_AUTOTUNE) && p.tile_rows == 0 && !cached) {
-    s = autotune(h, B, nx, ny, offset, src, dst, st, J);
+    s = autotune(h, lay, src, dst, st, J);
     if (s != UOT_OK) return s;
   }
 
@@ -930,17 +947,17 @@ uot_status solve_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny
 
 // Back-to-back fused-iteration launches over a batch layout, replayed from one
 // captured graph and bracketed by events (every pair live).
-uot_status time_core(uot_handle* h, int B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
-                     const float* src, const float* dst, uot_state* st, int32_t n, double* ms_per_iter,
-                     int32_t* tile_rows) {
+uot_status time_core(uot_handle* h, const Layout& L, const float* src, const float* dst, uot_state* st,
+                     int32_t n, double* ms_per_iter, int32_t* tile_rows) {
+  const int B = L.B;
   const uot_params& p = h->prm;
   if (!src || !dst || !ms_per_iter || n < 1) return UOT_ERR_ARG;
   uot_status s = validate_state(p, st);
   if (s != UOT_OK) return s;
   Job J;
-  const bool ptrs_aligned = aligned16(src) && aligned16(dst) && aligned16(st->Mx) && aligned16(st->My) &&
-                            aligned16(st->r) && aligned16(st->a) && aligned16(st->x0) && aligned16(st->x1);
-  s = plan(h, B, nx, ny, offset, J, 0, nullptr, ptrs_aligned);
+  const bool ptrs_aligned = aligned4(src) && aligned4(dst) && aligned4(st->Mx) && aligned4(st->My) &&
+                            aligned4(st->r) && aligned4(st->a) && aligned4(st->x0) && aligned4(st->x1);
+  s = plan(h, L, J, 0, nullptr, ptrs_aligned);
   if (s != UOT_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
   s = ensure_workspace(h, J);
@@ -1000,11 +1017,12 @@ extern "C" {
 
 uot_status uot_solve(uot_handle* h, const float* src, const float* dst, uot_state* st, uot_report* rep) {
   if (!h) return UOT_ERR_ARG;
-  if (h->prm.nx < 1 || h->prm.ny < 1) return UOT_ERR_SHAPE;
-  const int32_t nx = h->prm.nx, ny = h->prm.ny;
+  const uot_params& p = h->prm;
+  if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
+  const int32_t nx = p.nx, ny = p.ny, pitch = p.pitch > 0 ? p.pitch : p.nx;
   const int64_t off = 0;
   try {
-    return solve_core(h, 1, &nx, &ny, &off, src, dst, st, rep);
+    return solve_core(h, Layout{1, &nx, &ny, &pitch, &off}, src, dst, st, rep);
   } catch (...) {
     return UOT_ERR_OOM;
   }
@@ -1012,9 +1030,15 @@ uot_status uot_solve(uot_handle* h, const float* src, const float* dst, uot_stat
 
 uot_status uot_solve_batched(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
                              const float* src, const float* dst, uot_state* packed, uot_report* reps) {
+  return uot_solve_batched_pitched(h, B, nx, ny, nullptr, offset, src, dst, packed, reps);
+}
+
+uot_status uot_solve_batched_pitched(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny,
+                                     const int32_t* pitch, const int64_t* offset, const float* src,
+                                     const float* dst, uot_state* packed, uot_report* reps) {
   if (!h) return UOT_ERR_ARG;
   try {
-    return solve_core(h, B, nx, ny, offset, src, dst, packed, reps);
+    return solve_core(h, Layout{B, nx, ny, pitch, offset}, src, dst, packed, reps);
   } catch (...) {
     return UOT_ERR_OOM;
   }
@@ -1025,21 +1049,22 @@ uot_status uot_time_iterations(uot_handle* h, const float* src, const float* dst
   if (!h) return UOT_ERR_ARG;
   const uot_params& p = h->prm;
   if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
-  const int32_t nx = p.nx, ny = p.ny;
+  const int32_t nx = p.nx, ny = p.ny, pitch = p.pitch > 0 ? p.pitch : p.nx;
   const int64_t off = 0;
   try {
-    return time_core(h, 1, &nx, &ny, &off, src, dst, st, n, ms_per_iter, tile_rows);
+    return time_core(h, Layout{1, &nx, &ny, &pitch, &off}, src, dst, st, n, ms_per_iter, tile_rows);
   } catch (...) {
     return UOT_ERR_OOM;
   }
 }
 
 uot_status uot_time_iterations_batched(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny,
-                                       const int64_t* offset, const float* src, const float* dst,
-                                       uot_state* packed, int32_t n, double* ms_per_iter, int32_t* tile_rows) {
+                                       const int32_t* pitch, const int64_t* offset, const float* src,
+                                       const float* dst, uot_state* packed, int32_t n, double* ms_per_iter,
+                                       int32_t* tile_rows) {
   if (!h) return UOT_ERR_ARG;
   try {
-    return time_core(h, B, nx, ny, offset, src, dst, packed, n, ms_per_iter, tile_rows);
+    return time_core(h, Layout{B, nx, ny, pitch, offset}, src, dst, packed, n, ms_per_iter, tile_rows);
   } catch (...) {
     return UOT_ERR_OOM;
   }
@@ -1055,10 +1080,10 @@ uot_status uot_objective(uot_handle* h, const float* src, const float* dst, cons
   if (prev && validate_state(p, prev) != UOT_OK) return UOT_ERR_ARG;
   try {
     Timer timer;
-    const int32_t nx = p.nx, ny = p.ny;
+    const int32_t nx = p.nx, ny = p.ny, pitch = p.pitch > 0 ? p.pitch : p.nx;
     const int64_t off = 0;
     Job J;
-    s = plan(h, 1, &nx, &ny, &off, J);
+    s = plan(h, Layout{1, &nx, &ny, &pitch, &off}, J);
     if (s != UOT_OK) return s;
     if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
     s = ensure_workspace(h, J);
@@ -1138,6 +1163,12 @@ uot_status uot_poisson(uot_handle* h, int32_t nx, int32_t ny, double alpha, cons
 
 uot_status uot_init_poisson(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny, const int64_t* offset,
                             const float* src, const float* dst, uot_state* packed) {
+  return uot_init_poisson_pitched(h, B, nx, ny, nullptr, offset, src, dst, packed);
+}
+
+uot_status uot_init_poisson_pitched(uot_handle* h, int32_t B, const int32_t* nx, const int32_t* ny,
+                                    const int32_t* pitch, const int64_t* offset, const float* src,
+                                    const float* dst, uot_state* packed) {
   if (!h || !src || !dst) return UOT_ERR_ARG;
   const uot_params& p = h->prm;
   if (p.bc != 0) return UOT_ERR_ARG;
@@ -1145,7 +1176,7 @@ uot_status uot_init_poisson(uot_handle* h, int32_t B, const int32_t* nx, const i
   if (s != UOT_OK) return s;
   try {
     Job J;
-    s = plan(h, B, nx, ny, offset, J, 8);
+    s = plan(h, Layout{B, nx, ny, pitch, offset}, J, 8);
     if (s != UOT_OK) return s;
     if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
     size_t maxpx = 0;
@@ -1156,14 +1187,14 @@ uot_status uot_init_poisson(uot_handle* h, int32_t B, const int32_t* nx, const i
       const PairInfo& P = J.pairs[b];
       const long o = P.off;
       // rhs = c = dst - src: the infeasibility of the zero flux
-      HIPCHK(hipMemsetAsync(h->pw[2], 0, (size_t)P.nx * P.ny * sizeof(float), h->stream));
-      HIPCHK(launch_infeasibility(h->pw[2], h->pw[2], src + o, dst + o, h->pw[3], P.nx, P.ny, h->stream));
+      HIPCHK(launch_infeasibility(nullptr, nullptr, src + o, dst + o, h->pw[3], P.nx, P.ny, P.pitch, h->stream));
       s = poisson_grid(h, P.nx, P.ny, 0.0, h->pw[3], h->pw[2]);
       if (s != UOT_OK) return s;
       Planes st = planes_of(*packed);
       Planes at{st.Mx + o, st.My + o, st.r ? st.r + o : nullptr, st.a + o, st.x0 ? st.x0 + o : nullptr,
                 st.x1 ? st.x1 + o : nullptr};
-      HIPCHK(launch_poisson_start(h->pw[2], src + o, dst + o, at, P.nx, P.ny, p.mode, p.balanced, h->stream));
+      HIPCHK(launch_poisson_start(h->pw[2], src + o, dst + o, at, P.nx, P.ny, P.pitch, p.mode, p.balanced,
+                                  h->stream));
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     return UOT_OK;

@@ -43,14 +43,14 @@ inline constexpr uint32_t kMaxSlotsCheck = (1u << S_MAXG) | (1u << S_MAXA);
 
 struct PairInfo {
   int64_t off;         // first pixel of the pair in the packed planes
-  int32_t nx, ny;
+  int32_t nx, ny;      // pixel (x, y) is element off + y * pitch + x
   float tau1, tau2;
   float theta;         // tau1 / (rho + tau1)
   float mutau;         // mu * tau1
   float inv2mt;        // 1 / (1 + 2 mu tau1)
   int32_t tile_begin;  // first tile of the pair in the full tile list
   int32_t tile_count;
-  int32_t pad;
+  int32_t pitch;       // row stride in elements (>= nx)
 };
 
 struct Tile {
@@ -159,11 +159,14 @@ hipError_t poisson_solve(const float* Cx, const float* Cy, int nx, int ny, float
                          float* phi, float* t1, float* t2, hipStream_t s);
 hipError_t launch_sgemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
                         float* C, int ldc, hipStream_t s);
+// In the three helpers below the state and image planes have row stride
+// pitch (>= nx); phi and e are contiguous nx*ny planes.
 hipError_t launch_poisson_start(const float* phi, const float* src, const float* dst, const Planes& st, int nx,
-                                int ny, int mode, int balanced, hipStream_t s);
+                                int ny, int pitch, int mode, int balanced, hipStream_t s);
+// Mx = My = nullptr: the zero flux.
 hipError_t launch_infeasibility(const float* Mx, const float* My, const float* src, const float* dst, float* e,
-                                int nx, int ny, hipStream_t s);
+                                int nx, int ny, int pitch, hipStream_t s);
 int repaired_norm_blocks(int nx, int ny);
-hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, double* partial,
-                                hipStream_t s);
+hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, int pitch,
+                                double* partial, hipStream_t s);
 }  // namespace uot

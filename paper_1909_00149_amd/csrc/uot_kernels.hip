@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
     const Tile tl = A.tiles[t];
     if (!A.active[tl.pair]) continue;  // uniform over the block
     const PairInfo P = A.pairs[tl.pair];
-    const int nx = P.nx, ny = P.ny;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const int gx0 = tl.x0, gy0 = tl.y0;
     const long off = P.off;
     const float tau1 = P.tau1, tau2 = P.tau2;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
       const int ry = idx / (TX + 2), rx = idx - ry * (TX + 2);
       const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
       float v = 0.f;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = a_in[(long)gy * nx + gx];
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = a_in[(long)gy * pitch + gx];
       sa[ry][rx] = v;
     }
     const float* __restrict__ mx_in = A.in.Mx + off;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
       const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
       float vx = 0.f, vy = 0.f;
       if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        const long o = (long)gy * nx + gx;
+        const long o = (long)gy * pitch + gx;
         vx = mx_in[o];
         vy = my_in[o];
         if (BC == 0) {
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
       const int gx = gx0 + lx, gy = gy0 + wv + 4 * k;
       r_o[k] = c0[k] = c1[k] = x0_o[k] = x1_o[k] = 0.f;
       if (gx < nx && gy < ny) {
-        const long o = off + (long)gy * nx + gx;
+        const long o = off + (long)gy * pitch + gx;
         if (RES != R_BAL) r_o[k] = A.in.r[o];
         if (MODE == 0) {
           c0[k] = A.c[o];
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
         knew -= rn;
       }
       const float an = a + tau2 * (2.f * knew - kold);
-      const long o = off + (long)gy * nx + gx;
+      const long o = off + (long)gy * pitch + gx;
       A.out.Mx[o] = snx[ry][rx];
       A.out.My[o] = sny[ry][rx];
       A.out.a[o] = an;
@@ -194,18 +194,45 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
   }
 }
 
-// Vectorised form of cp_iter_kernel for grids whose rows start on 16-byte
-// boundaries (nx and the pair offset multiples of 4): 16 threads per row,
-// each owning 4 consecutive pixels, so every global access of the tile body
-// is a 16-byte load or store.  LDS rows keep the tile body 16-byte aligned
-// at column 4 (x = 0) with the left halo at column 3 (x = -1) and, for a,
-// the right halo at column 68 (x = 64).  The arithmetic per pixel is that
-// of cp_iter_kernel.
+// Vectorised form of cp_iter_kernel: 16 threads per row, each owning 4
+// consecutive pixels (a quad), so every global access of the tile body is
+// one 16-byte load or store.  Rows need not start on a 16-byte boundary:
+// the accesses only need 4-byte alignment, which the memory system serves
+// at full width.  A quad that runs past the end of its row (nx not a
+// multiple of 4) is read and written pixel by pixel, so nothing outside the
+// pair's rows is touched.  LDS rows keep the tile body 16-byte aligned at
+// column 4 (x = 0) with the left halo at column 3 (x = -1) and, for a, the
+// right halo at column 68 (x = 64).  The arithmetic per pixel is that of
+// cp_iter_kernel.
 //
 // NT: the outputs are written with non-temporal stores, which pays once the
 // state no longer fits the Infinity Cache (measured: about +5% at 4096^2 and
 // 8192^2, -15% at 2048^2).  Issuing the next tile's loads before computing
 // the current one was measured too and brought nothing.
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+// Quad load: n = number of the 4 pixels inside the row (>= 4: all); pixels
+// past the row end read as 0 and are never dereferenced.
+__device__ __forceinline__ float4 ld4(const float* p, int n) {
+  if (n >= 4) {
+    const f32x4u v = *reinterpret_cast<const f32x4u*>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (n > 0) r.x = p[0];
+  if (n > 1) r.y = p[1];
+  if (n > 2) r.z = p[2];
+  return r;
+}
+
+// Sets component j (0..3) of v to zero; no-op for other j.
+__device__ __forceinline__ void zero_at(float4& v, int j) {
+  if (j == 0) v.x = 0.f;
+  if (j == 1) v.y = 0.f;
+  if (j == 2) v.z = 0.f;
+  if (j == 3) v.w = 0.f;
+}
+
 template <int MODE, int RES, int BC, int TY>
 struct VecStage {
   static constexpr int NA = (TY + 2 + 15) / 16, NM = (TY + 1 + 15) / 16, PR = TY / 16;
@@ -219,10 +246,11 @@ __device__ __forceinline__ void vec_fetch(const IterArgs& A, const PairInfo& P, 
                                           VecStage<MODE, RES, BC, TY>& S) {
   using St = VecStage<MODE, RES, BC, TY>;
   const int tid = threadIdx.x, q = tid & 15, rr = tid >> 4;
-  const int nx = P.nx, ny = P.ny, gx0 = tl.x0, gy0 = tl.y0;
+  const int nx = P.nx, ny = P.ny, pitch = P.pitch, gx0 = tl.x0, gy0 = tl.y0;
   const long off = P.off;
   const int gxq = gx0 + 4 * q;
-  const bool quad_in = gxq < nx;
+  const int nin = nx - gxq;  // pixels of this quad inside the row (>= 4: all)
+  const bool quad_in = nin > 0;
   const float* __restrict__ a_in = A.in.a + off;
   const float* __restrict__ mx_in = A.in.Mx + off;
   const float* __restrict__ my_in = A.in.My + off;
@@ -231,18 +259,18 @@ __device__ __forceinline__ void vec_fetch(const IterArgs& A, const PairInfo& P, 
   for (int i = 0; i < St::NA; ++i) {
     const int ry = rr + 16 * i, gy = gy0 - 1 + ry;
     S.a[i] = z;
-    if (ry < TY + 2 && gy >= 0 && gy < ny && quad_in) S.a[i] = *reinterpret_cast<const float4*>(a_in + (long)gy * nx + gxq);
+    if (ry < TY + 2 && gy >= 0 && gy < ny && quad_in) S.a[i] = ld4(a_in + (long)gy * pitch + gxq, nin);
   }
 #pragma unroll
   for (int i = 0; i < St::NM; ++i) {
     const int ry = rr + 16 * i, gy = gy0 - 1 + ry;
     S.mx[i] = S.my[i] = z;
     if (ry < TY + 1 && gy >= 0 && gy < ny && quad_in) {
-      const long o = (long)gy * nx + gxq;
-      S.mx[i] = *reinterpret_cast<const float4*>(mx_in + o);
-      S.my[i] = *reinterpret_cast<const float4*>(my_in + o);
+      const long o = (long)gy * pitch + gxq;
+      S.mx[i] = ld4(mx_in + o, nin);
+      S.my[i] = ld4(my_in + o, nin);
       if (BC == 0) {
-        if (gxq + 3 == nx - 1) S.mx[i].w = 0.f;
+        zero_at(S.mx[i], nx - 1 - gxq);
         if (gy == ny - 1) S.my[i] = z;
       }
     }
@@ -251,11 +279,11 @@ __device__ __forceinline__ void vec_fetch(const IterArgs& A, const PairInfo& P, 
   if (tid < 2 * (TY + 2)) {  // halo columns of a: x = -1 and x = 64
     const int ry = tid >> 1, side = tid & 1;
     const int gx = side ? gx0 + 64 : gx0 - 1, gy = gy0 - 1 + ry;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) S.ha = a_in[(long)gy * nx + gx];
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) S.ha = a_in[(long)gy * pitch + gx];
   } else if (tid >= 128 && tid < 128 + TY + 1) {  // halo column of M: x = -1
     const int ry = tid - 128, gx = gx0 - 1, gy = gy0 - 1 + ry;
     if (gx >= 0 && gy >= 0 && gy < ny) {
-      const long o = (long)gy * nx + gx;
+      const long o = (long)gy * pitch + gx;
       S.hmx = mx_in[o];  // gx < nx - 1 here: never the structurally zero column
       S.hmy = (BC == 0 && gy == ny - 1) ? 0.f : my_in[o];
     }
@@ -265,30 +293,34 @@ __device__ __forceinline__ void vec_fetch(const IterArgs& A, const PairInfo& P, 
     const int gy = gy0 + rr + 16 * k;
     S.r[k] = S.c0[k] = S.c1[k] = S.x0[k] = S.x1[k] = z;
     if (quad_in && gy < ny) {
-      const long o = off + (long)gy * nx + gxq;
-      if (RES != R_BAL) S.r[k] = *reinterpret_cast<const float4*>(A.in.r + o);
+      const long o = off + (long)gy * pitch + gxq;
+      if (RES != R_BAL) S.r[k] = ld4(A.in.r + o, nin);
       if (MODE == 0) {
-        S.c0[k] = *reinterpret_cast<const float4*>(A.c + o);
+        S.c0[k] = ld4(A.c + o, nin);
       } else {
-        S.c0[k] = *reinterpret_cast<const float4*>(A.src + o);
-        S.c1[k] = *reinterpret_cast<const float4*>(A.dst + o);
-        if (MODE == 1) S.x0[k] = *reinterpret_cast<const float4*>(A.in.x0 + o);
-        S.x1[k] = *reinterpret_cast<const float4*>(A.in.x1 + o);
+        S.c0[k] = ld4(A.src + o, nin);
+        S.c1[k] = ld4(A.dst + o, nin);
+        if (MODE == 1) S.x0[k] = ld4(A.in.x0 + o, nin);
+        S.x1[k] = ld4(A.in.x1 + o, nin);
       }
     }
   }
 }
 
-typedef float f32x4v __attribute__((ext_vector_type(4)));
-
+// Quad store of the first n (>= 4: all) pixels of v.
 template <bool NT>
-__device__ __forceinline__ void st4(float* p, float4 v) {
-  if (NT) {
-    const f32x4v w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<f32x4v*>(p));
-  } else {
-    *reinterpret_cast<float4*>(p) = v;
+__device__ __forceinline__ void st4(float* p, float4 v, int n) {
+  if (n >= 4) {
+    const f32x4u w = {v.x, v.y, v.z, v.w};
+    if (NT)
+      __builtin_nontemporal_store(w, reinterpret_cast<f32x4u*>(p));
+    else
+      *reinterpret_cast<f32x4u*>(p) = w;
+    return;
   }
+  if (n > 0) p[0] = v.x;
+  if (n > 1) p[1] = v.y;
+  if (n > 2) p[2] = v.z;
 }
 
 template <int MODE, int RES, int BC, int TY, bool NT>
@@ -313,12 +345,13 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
     const PairInfo P = A.pairs[tl.pair];
     vec_fetch<MODE, RES, BC, TY>(A, P, tl, cur);
     {
-      const int nx = P.nx, ny = P.ny;
+      const int nx = P.nx, ny = P.ny, pitch = P.pitch;
       const int gx0 = tl.x0, gy0 = tl.y0;
       const long off = P.off;
       const float tau1 = P.tau1, tau2 = P.tau2;
       const int gxq = gx0 + 4 * q;
-      const bool quad_in = gxq < nx;
+      const int nin = nx - gxq;
+      const bool quad_in = nin > 0;
 
       __syncthreads();  // LDS of the previous tile is no longer read
 #pragma unroll
@@ -439,13 +472,13 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
           }
           an[e] = a + tau2 * (2.f * knew - kold);
         }
-        const long o = off + (long)gy * nx + gxq;
-        st4<NT>(A.out.Mx + o, nxc);
-        st4<NT>(A.out.My + o, nyc);
-        st4<NT>(A.out.a + o, make_float4(an[0], an[1], an[2], an[3]));
-        if (RES != R_BAL) st4<NT>(A.out.r + o, make_float4(rn[0], rn[1], rn[2], rn[3]));
-        if (MODE == 1) st4<NT>(A.out.x0 + o, make_float4(x0n[0], x0n[1], x0n[2], x0n[3]));
-        if (MODE != 0) st4<NT>(A.out.x1 + o, make_float4(x1n[0], x1n[1], x1n[2], x1n[3]));
+        const long o = off + (long)gy * pitch + gxq;
+        st4<NT>(A.out.Mx + o, nxc, nin);
+        st4<NT>(A.out.My + o, nyc, nin);
+        st4<NT>(A.out.a + o, make_float4(an[0], an[1], an[2], an[3]), nin);
+        if (RES != R_BAL) st4<NT>(A.out.r + o, make_float4(rn[0], rn[1], rn[2], rn[3]), nin);
+        if (MODE == 1) st4<NT>(A.out.x0 + o, make_float4(x0n[0], x0n[1], x0n[2], x0n[3]), nin);
+        if (MODE != 0) st4<NT>(A.out.x1 + o, make_float4(x1n[0], x1n[1], x1n[2], x1n[3]), nin);
       }
     }
   }
@@ -495,7 +528,7 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
     const bool swap = A.swap_active && act;
     const Planes C = swap ? A.B : A.A;
     const Planes Q = swap ? A.A : A.B;  // previous iterate
-    const int nx = P.nx, ny = P.ny;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const float it1 = 1.f / P.tau1;
     double acc[NS];
 #pragma unroll
@@ -503,12 +536,12 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
     for (int ly = wv; ly < A.tile_rows; ly += 4) {
       const int gx = tl.x0 + lx, gy = tl.y0 + ly;
       if (gx >= nx || gy >= ny) continue;
-      const long o = P.off + (long)gy * nx + gx;
+      const long o = P.off + (long)gy * pitch + gx;
       const bool hasR = gx + 1 < nx, hasU = gy + 1 < ny;
       const bool hasL = gx > 0, hasD = gy > 0;
       const float a = C.a[o], ap = Q.a[o];
       const float aR = hasR ? C.a[o + 1] : 0.f, apR = hasR ? Q.a[o + 1] : 0.f;
-      const float aU = hasU ? C.a[o + nx] : 0.f, apU = hasU ? Q.a[o + nx] : 0.f;
+      const float aU = hasU ? C.a[o + pitch] : 0.f, apU = hasU ? Q.a[o + pitch] : 0.f;
       float gxx = a - aR, gyy = a - aU;
       float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
       const bool zx = (BC == 0 && gx == nx - 1), zy = (BC == 0 && gy == ny - 1);
@@ -517,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
       const float mx = zx ? 0.f : C.Mx[o], my = zy ? 0.f : C.My[o];
       const float mxp = zx ? 0.f : Q.Mx[o], myp = zy ? 0.f : Q.My[o];
       const float mxl = hasL ? C.Mx[o - 1] : 0.f;
-      const float myd = hasD ? C.My[o - nx] : 0.f;
+      const float myd = hasD ? C.My[o - pitch] : 0.f;
       const float dm = (mx - mxl) + (my - myd);
       float x0 = 0.f, x1 = 0.f, e;
       if (MODE == 0) {
@@ -593,14 +626,14 @@ __global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
   for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
     const Tile tl = A.tiles[t];
     const PairInfo P = A.pairs[tl.pair];
-    const int nx = P.nx, ny = P.ny;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     double acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = 0.0;
     for (int ly = wv; ly < A.tile_rows; ly += 4) {
       const int gx = tl.x0 + lx, gy = tl.y0 + ly;
       if (gx >= nx || gy >= ny) continue;
-      const long o = P.off + (long)gy * nx + gx;
+      const long o = P.off + (long)gy * pitch + gx;
       const float s = A.src[o], d = A.dst[o];
       acc[U_NONFIN_IN] += (isfinite(s) ? 0.0 : 1.0) + (isfinite(d) ? 0.0 : 1.0);
       acc[U_NEG] += (s < 0.f ? 1.0 : 0.0) + (d < 0.f ? 1.0 : 0.0);
@@ -725,7 +758,7 @@ __global__ __launch_bounds__(BLOCK) void copy_active_kernel(Planes dst, Planes s
     for (int ly = wv; ly < tile_rows; ly += 4) {
       const int gx = tl.x0 + lx, gy = tl.y0 + ly;
       if (gx >= P.nx || gy >= P.ny) continue;
-      const long o = P.off + (long)gy * P.nx + gx;
+      const long o = P.off + (long)gy * P.pitch + gx;
       dst.Mx[o] = src.Mx[o];
       dst.My[o] = src.My[o];
       dst.a[o] = src.a[o];
@@ -752,7 +785,7 @@ __global__ __launch_bounds__(BLOCK) void dual_kernel(DualArgs A) {
     for (int ly = wv; ly < A.tile_rows; ly += 4) {
       const int gx = tl.x0 + lx, gy = tl.y0 + ly;
       if (gx >= P.nx || gy >= P.ny) continue;
-      const long o = P.off + (long)gy * P.nx + gx;
+      const long o = P.off + (long)gy * P.pitch + gx;
       const double ah = (double)A.a[o] * is;
       double v = 0.0;
       const double p1 = A.x_dst[o];

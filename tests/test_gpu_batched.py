@@ -173,3 +173,36 @@ def test_autotuner_picks_a_shape_and_keeps_results(dev, tmp_path, monkeypatch):
         assert torch.equal(st[k], st2[k])
     text = cache.read_text()
     assert "gfx950:m0:r1:b0" in text
+
+
+@pytest.mark.parametrize("ty", [116, 316])
+def test_vectorised_kernel_on_odd_offsets_with_nan_gaps(dev, ty):
+    """Pairs packed at offsets that are not multiples of 4, with NaN in the
+    gaps between them (images and state): the vectorised kernel must agree
+    bitwise with the scalar one on every pair, never read a gap into a
+    result, and leave the gaps untouched (61 iterations: the odd tail is
+    copied back too)."""
+    pairs, src, dst, nx, ny, offs = batch_of(SHAPES, dev, seed0=40, gap=3)
+    gaps = torch.ones(src.numel(), dtype=torch.bool, device=dev)
+    for i in range(len(nx)):
+        gaps[offs[i]:offs[i] + nx[i] * ny[i]] = False
+    assert any(o % 4 for o in offs) and bool(gaps.any())
+    src[gaps] = float("nan")
+    dst[gaps] = float("nan")
+    kw = dict(mode=DIST, balanced=False, mu=1.5, max_iter=61, tol=0.0)
+
+    def run(t):
+        st = G.new_state(DIST, False, src.numel(), dev)
+        for v in st.values():
+            v[gaps] = float("nan")
+        st, reps = G.Solver(G.Params(tile_rows=t, **kw)).solve_batched(src, dst, nx, ny, offs, st)
+        torch.cuda.synchronize()
+        return st, reps
+
+    ref, _ = run(4)
+    st, reps = run(ty)
+    assert all(r["tile_rows"] == ty and r["iters"] == 61 for r in reps)
+    for k in ("Mx", "My", "r", "a"):
+        assert torch.equal(ref[k][~gaps], st[k][~gaps]), k
+        assert bool(torch.isfinite(st[k][~gaps]).all()), k
+        assert bool(torch.isnan(st[k][gaps]).all()), k

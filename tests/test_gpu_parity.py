@@ -117,17 +117,32 @@ def test_fixed_iterations_all_modes(dev, mode, balanced, resid, bc, shape):
 @pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332])
 @pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 1), (PROX_FIXED, True, 1),
                                                  (DIST, True, 1), (PROX, False, 2)])
-@pytest.mark.parametrize("shape", [(45, 133), (45, 132), (70, 256)])
+@pytest.mark.parametrize("shape", [(45, 133), (45, 132), (70, 256), (19, 66), (23, 131)])
 def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):
-    """Every tile shape, scalar or vectorised (116/132; rows starting on
-    16-byte boundaries, else the scalar kernel), computes each pixel with
-    the same arithmetic: the iterates are bitwise identical."""
+    """Every tile shape, scalar or vectorised (116/132/316/332, on any row
+    width: rows off 16-byte boundaries and partial quads at row ends
+    included), computes each pixel with the same arithmetic: the iterates
+    are bitwise identical."""
     p, q = pair_inputs(shape, 7, mode)
     if balanced and mode == DIST:
         q = (q * (p.astype(np.float64).sum() / q.astype(np.float64).sum())).astype(np.float32)
     base, _ = run_pair(dev, p, q, mode, balanced, resid, iters=40, tile_rows=4)
     st, _ = run_pair(dev, p, q, mode, balanced, resid, iters=40, tile_rows=ty)
     for k in planes_for(mode, balanced):
+        assert torch.equal(base[k], st[k]), k
+
+
+@pytest.mark.parametrize("ty", [116, 316])
+@pytest.mark.parametrize("shape", [(33, 65), (17, 130), (9, 67), (64, 64)])
+def test_vectorised_literal_boundary_bitwise(dev, ty, shape):
+    """The literal boundary (bc = 1) keeps the right-column and top-row flux
+    free, so the zero padding past the row end is what D* a sees there: the
+    vectorised kernel must agree bitwise with the scalar one on every width."""
+    p, q = pair_inputs(shape, 11, DIST)
+    base, _ = run_pair(dev, p, q, DIST, False, 1, bc=1, iters=40, tile_rows=4)
+    st, rep = run_pair(dev, p, q, DIST, False, 1, bc=1, iters=40, tile_rows=ty)
+    assert rep["tile_rows"] == ty
+    for k in planes_for(DIST, False):
         assert torch.equal(base[k], st[k]), k
 
 
