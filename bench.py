@@ -8,13 +8,17 @@ already resident in HBM.  The printed JSON line carries:
   value      pixel-iterations per second over the K timed steps
              (sum over pairs of pixels x iterations actually run)
   roofline   the fused iteration kernel against the 8 TB/s HBM peak:
-             algorithmic bytes per pixel-iteration x pixels per launch / the
-             kernel's average launch time, from HIP events on the solver's
-             stream around graph-replayed back-to-back launches of the launch
-             the step runs (a batch: every pair live).  `traffic` is the HBM
-             bytes per launch from the profiler's FETCH_SIZE / WRITE_SIZE
-             counters (calibrated on a device copy), or null when they were
-             not taken for this workload and the current kernel sources
+             algorithmic bytes per pixel-iteration x pixel-iterations per
+             launch / the kernel's average launch time, from HIP events on
+             the solver's stream around graph-replayed back-to-back launches
+             of the launch the step runs (a batch: every pair live).  A
+             temporally blocked launch runs several iterations and moves the
+             state once, so its fraction can pass 1: it beats the
+             one-iteration-per-launch HBM bound.  `traffic` is the HBM bytes
+             per launch from the profiler's FETCH_SIZE / WRITE_SIZE counters
+             (calibrated on a device copy), or null when they were not taken
+             for this workload and the current kernel sources.  `alu` is the
+             same launch against the FP32 vector peak (algorithmic flops)
   warm_start time to rel_res <= 1e-4 on held-out 256x256 pairs, cold start
              against the trained network's start (inference included)
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of
@@ -47,9 +51,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per pixel-iteration of the fused kernel: each state plane
-# read once and written once, constants read once (FP32)
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic bytes per pixel-iteration of Algorithm 1: each state plane
+# read once and written once, constants read once (FP32).  A temporally
+# blocked launch runs several iterations of every pixel and moves the state
+# once, so its algorithmic bytes are these times its iterations and its HBM
+# traffic (the profiler's counters) is a fraction of them.
 BYTES = {(0, False): 36, (0, True): 28, (1, False): 56, (1, True): 48, (2, False): 48, (2, True): 40}
+# algorithmic FP32 operations per pixel-iteration (an FMA counts 2, rsqrt 1;
+# compares and selects not counted): flux step 14, D M 3, residual prox 3,
+# the x-steps 5 each, K and the dual step 4-6
+FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False): 32, (2, True): 28}
 
 
 # HBM traffic of one launch of the fused kernel, from two rocprofv3 --pmc
@@ -89,6 +101,8 @@ def measured_traffic(name, shape):
 def kernel_name(mode, balanced, shape):
     """Instantiated name of the fused kernel for a tile_rows code."""
     resid = 0 if balanced else 1
+    if shape >= 1000:
+        return f"cp_iter_tb_kernel<{mode}, {resid}, 0, {shape % 1000}, {shape // 1000}>"
     if shape >= 100:
         return f"cp_iter_vec_kernel<{mode}, {resid}, 0, {shape % 100}, {'true' if shape >= 300 else 'false'}>"
     return f"cp_iter_kernel<{mode}, {resid}, 0, {shape}>"
@@ -250,15 +264,20 @@ def main():
         ms, shape = ksolver.time_iterations(src, dst, kstate, args.kernel_iters)
     bpp = BYTES[(W["mode"], W["balanced"])]
     px_launch = int(sum(npx))
-    alg_bytes = bpp * px_launch
+    T = shape // 1000 if shape >= 1000 else 1  # iterations per launch
+    alg_bytes = bpp * px_launch * T            # per pixel-iteration bytes x pixel-iterations of a launch
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, shape)
+    flops = FLOPS[(W["mode"], W["balanced"])] * px_launch * T / (ms * 1e-3) / 1e12
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_vs_algorithmic": round(traffic / alg_bytes, 4) if traffic else None,
                 "kernel": kernel_name(W["mode"], W["balanced"], shape), "tile_rows": shape,
-                "bytes_per_pixel_iter": bpp, "pixels_per_launch": px_launch,
-                "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5)}
+                "iterations_per_launch": T, "bytes_per_pixel_iter": bpp, "pixels_per_launch": px_launch,
+                "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5),
+                "alu": {"achieved": round(flops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flops / FP32_PEAK_TFLOPS, 4),
+                        "flops_per_pixel_iter": FLOPS[(W["mode"], W["balanced"])]}}
     out = {
         "metric": "pixel-iters/s (%HBM peak); time-to-1e-4 residual, warm-start vs cold",
         "value": value,

@@ -105,7 +105,13 @@ typedef struct uot_params {
                            316 / 332 = the same with non-temporal stores (for states
                            larger than the last-level cache).  The vectorised shapes
                            take any row layout; they run at full speed when every row
-                           starts on a 16-byte boundary (see pitch)                      */
+                           starts on a 16-byte boundary (see pitch).
+                           1000 * T + rows (4008, 2016, 4016, 8016, 4032, 8032):
+                           temporally blocked, up to T iterations per launch on
+                           64 x rows tiles with a T-pixel halo; the last iteration
+                           before each convergence check runs in the single-step
+                           kernel of the same rows (100 + rows; 8 for 4008).  Every
+                           shape computes bit-identical iterates                         */
   int32_t pitch;        /* row stride of uot_solve's planes in elements; 0 = nx.  A
                            pitch rounded up to a multiple of 4 puts every row on a
                            16-byte boundary; the padding is never read or written   */
@@ -207,10 +213,12 @@ uot_status uot_init_poisson_pitched(uot_handle *h, int32_t B, const int32_t *nx,
 /* Profiling aid: captures n (rounded up to even) back-to-back launches of
  * the fused iteration kernel on the handle's grid and stream into a graph,
  * replays it once untimed and once bracketed by HIP events, starting from
- * the caller's state *st (advanced by those 2n iterations; no checks, no
- * zeroing; the state and images are validated first).  *ms_per_iter
- * receives the average event-to-event time per launch; *tile_rows (may be
- * NULL) the kernel shape that ran.  src/dst as for uot_solve. */
+ * the caller's state *st (no checks, no zeroing; the state and images are
+ * validated first).  A launch runs one iteration, or T for a temporally
+ * blocked shape (T = tile_rows / 1000), so *st advances by 2 n T
+ * iterations.  *ms_per_iter receives the average event-to-event time per
+ * launch; *tile_rows (may be NULL) the kernel shape that ran.  src/dst as
+ * for uot_solve. */
 uot_status uot_time_iterations(uot_handle *h, const float *src, const float *dst, uot_state *st,
                                int32_t n, double *ms_per_iter, int32_t *tile_rows);
 

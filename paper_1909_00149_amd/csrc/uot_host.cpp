@@ -85,14 +85,57 @@ void tune_store_locked() {
   std::fclose(f);
 }
 
-// Kernel shape codes: rows per tile for the scalar kernel (4, 8, 16, 32);
-// 100 + rows for the vectorised kernel (rows on 16-byte boundaries); 300 +
-// rows for the vectorised kernel with non-temporal stores, which pays once
-// the state no longer fits the 256 MB Infinity Cache.  Default by size:
-int heuristic_shape(long total_px) {
-  if (total_px <= (1L << 16)) return 4;
-  if (total_px <= (8L << 20)) return 116;
-  return 316;
+// Default kernel shape by size (the codes are listed with shape_rows below).
+// Measured on one MI355X, per iteration: the blocked kernels take 1.8 us at
+// 64^2..256^2 (single-step: 3.7 us, the launch floor), 2.2 us at 512^2 (4.7),
+// 60 us at 4096^2 (121) and 56 us on a 14.7 Mpx ragged batch (110).
+int heuristic_shape(long npx) {
+  // temporally blocked, 4 iterations per launch: 64 x 8 tiles while the
+  // grid is too small to give every CU a 64 x 16 tile (more workgroups hide
+  // more latency), 64 x 16 tiles above (less halo work)
+  return npx <= (1L << 18) ? 4008 : 4016;
+}
+
+// Kernel shape codes: rows (4, 8, 16, 32) = the scalar kernel; 100 + rows =
+// the vectorised kernel; 300 + rows = the same with non-temporal stores;
+// 1000 * T + rows = T iterations per launch (temporally blocked), whose
+// single steps run the vectorised kernel of the same rows (the scalar one
+// for 8 rows, which the vectorised form does not have).
+int shape_rows(int code) { return code >= 1000 ? code % 1000 : code % 100; }
+int shape_steps(int code) { return code >= 1000 ? code / 1000 : 1; }
+int shape_single(int code) {
+  if (code < 1000) return code;
+  const int rows = code % 1000;
+  return rows % 16 == 0 ? 100 + rows : rows;
+}
+bool shape_known(int code) {
+  switch (code) {
+    case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
+    case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: return true;
+  }
+  return false;
+}
+
+// Iterations per launch for n iterations with up to T per launch.  With
+// last_single the final launch runs one iteration (the convergence check
+// compares the last two iterates, which must both be in the ping-pong
+// buffers); with even the number of launches is even, so the iterate ends in
+// the buffer it started in.  The iterations are spread evenly over the
+// launches.
+std::vector<int> step_schedule(int n, int T, bool last_single, bool even) {
+  std::vector<int> v;
+  if (n <= 0) return v;
+  if (T <= 1) return std::vector<int>(n, 1);
+  const int R = last_single ? n - 1 : n;
+  int k = (R + T - 1) / T;
+  int total = k + (last_single ? 1 : 0);
+  if (even && (total & 1)) {
+    if (k + 1 > R) return std::vector<int>(n, 1);
+    ++k;
+  }
+  for (int i = 0; i < k; ++i) v.push_back(R / k + (i < R % k ? 1 : 0));
+  if (last_single) v.push_back(1);
+  return v;
 }
 
 bool aligned4(const void* p) { return p == nullptr || ((uintptr_t)p & 3u) == 0; }
@@ -216,7 +259,8 @@ uot_status uot_check_params(const uot_params* p) {
   if (p->max_iter < 0 || p->check_every < 0) return UOT_ERR_ARG;
   if (!std::isfinite(p->tol)) return UOT_ERR_ARG;
   switch (p->tile_rows) {
-    case 0: case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332: break;
+    case 0: case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
+    case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: break;
     default: return UOT_ERR_ARG;
   }
   if ((p->flags & UOT_ALLOW_SIGNED) && p->mode != UOT_DIST) return UOT_ERR_ARG;
@@ -357,9 +401,9 @@ uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* 
   // the vectorised kernels (100 * variant + rows) take any row layout but
   // need every plane 4-byte aligned; otherwise the scalar kernel of the same
   // rows runs
-  if (ty >= 100 && !J.vec_ok) ty %= 100;
+  if (ty >= 100 && !J.vec_ok) ty = shape_rows(ty);
   J.shape = ty;
-  ty %= 100;
+  ty = shape_rows(ty);
   J.ty = ty;
   J.tiles.clear();
   for (int b = 0; b < B; ++b) {
@@ -563,14 +607,26 @@ struct Launch {
   IterArgs fwd, bwd;   // A -> B and B -> A
   CheckArgs chk;
   DecideArgs dec;
-  int grid_iter, grid_aux, resid;
+  int grid_iter, grid_single, grid_aux, resid;
 };
+
+// One launch of `steps` iterations: the shape's own kernel, or its
+// single-step kernel when steps == 1.
+hipError_t launch_steps(uot_handle* h, int resid, int shape, int steps, int grid_multi, int grid_single,
+                        IterArgs a) {
+  const uot_params& p = h->prm;
+  if (steps <= 1 || shape_steps(shape) == 1)
+    return launch_iter(p.mode, resid, p.bc, shape_single(shape), grid_single, a, h->stream);
+  a.steps = steps;
+  return launch_iter(p.mode, resid, p.bc, shape, grid_multi, a, h->stream);
+}
 
 uot_status enqueue_window(Launch& L, int W, bool check) {
   uot_handle* h = L.h;
   const uot_params& p = h->prm;
-  for (int i = 0; i < W; ++i)
-    HIPCHK(launch_iter(p.mode, L.resid, p.bc, L.J->shape, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
+  const std::vector<int> sched = step_schedule(W, shape_steps(L.J->shape), true, true);
+  for (size_t i = 0; i < sched.size(); ++i)
+    HIPCHK(launch_steps(h, L.resid, L.J->shape, sched[i], L.grid_iter, L.grid_single, (i & 1) ? L.bwd : L.fwd));
   if (check) {
     HIPCHK(launch_check(p.mode, L.resid, p.bc, L.grid_aux, L.chk, h->stream));
     HIPCHK(launch_reduce_decide(L.dec, h->d_partial, h->stream));
@@ -701,7 +757,7 @@ uot_status autotune(uot_handle* h, const Layout& L, const float* src, const floa
   const int resid = resid_of(p);
   std::vector<int> cand = {4, 8, 16, 32};
   if (J.vec_ok) {
-    for (int c : {116, 132, 316, 332}) cand.push_back(c);
+    for (int c : {116, 132, 316, 332, 4008, 2016, 4016, 8016, 4032, 8032}) cand.push_back(c);
   }
   Job J4;
   uot_status s = plan(h, L, J4, 4);
@@ -725,17 +781,19 @@ uot_status autotune(uot_handle* h, const Layout& L, const float* src, const floa
     s = upload_live(h, Jt, ones.data());
     if (s != UOT_OK) break;
     const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
-    const int grid = iter_grid(h, p.mode, resid, p.bc, ty, (int)Jt.tiles.size());
-    for (int i = 0; i < 2; ++i) HIPCHK(launch_iter(p.mode, resid, p.bc, ty, grid, fwd, h->stream));
+    const int grid = iter_grid(h, p.mode, resid, p.bc, Jt.shape, (int)Jt.tiles.size());
+    const int T = shape_steps(Jt.shape);
+    for (int i = 0; i < 2; ++i) HIPCHK(launch_steps(h, resid, Jt.shape, T, grid, grid, fwd));
     HIPCHK(hipEventRecord(e0, h->stream));
-    for (int i = 0; i < 10; ++i) HIPCHK(launch_iter(p.mode, resid, p.bc, ty, grid, fwd, h->stream));
+    for (int i = 0; i < 10; ++i) HIPCHK(launch_steps(h, resid, Jt.shape, T, grid, grid, fwd));
     HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= (float)T;  // per iteration
     if (ms < best) {
       best = ms;
-      best_ty = ty;
+      best_ty = Jt.shape;
     }
   }
   (void)hipEventDestroy(e0);
@@ -824,6 +882,7 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   L.J = &J;
   L.resid = resid;
   L.grid_iter = iter_grid(h, p.mode, resid, p.bc, J.shape, (int)J.tiles.size());
+  L.grid_single = iter_grid(h, p.mode, resid, p.bc, shape_single(J.shape), (int)J.tiles.size());
   L.grid_aux = aux_grid(h, (int)J.tiles.size());
   const Planes A = planes_of(*st), Bp = shadow_planes(h);
   const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
@@ -887,11 +946,12 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   }
   // tail iterations for pairs still running
   const bool run_tail = n_active > 0 && tail > 0;
+  const std::vector<int> tsched = step_schedule(tail, shape_steps(J.shape), true, false);
   if (run_tail) {
-    for (int i = 0; i < tail; ++i)
-      HIPCHK(launch_iter(p.mode, resid, p.bc, J.shape, L.grid_iter, (i & 1) ? L.bwd : L.fwd, h->stream));
+    for (size_t i = 0; i < tsched.size(); ++i)
+      HIPCHK(launch_steps(h, resid, J.shape, tsched[i], L.grid_iter, L.grid_single, (i & 1) ? L.bwd : L.fwd));
   }
-  const bool odd = run_tail && (tail & 1);
+  const bool odd = run_tail && (tsched.size() & 1);
   // final evaluation of every pair, then the final decision
   CheckArgs fin = L.chk;
   if (p.max_iter == 0) fin.B = A;  // no iteration ran: no previous iterate
@@ -978,12 +1038,13 @@ uot_status time_core(uot_handle* h, const Layout& L, const float* src, const flo
   const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
   const IterArgs bwd{Bp, A, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
   const int nn = n + (n & 1);
+  const int T = shape_steps(J.shape);  // iterations per launch
   // the launches are captured once and replayed, as the solver does
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < nn && le == hipSuccess; ++i)
-    le = launch_iter(p.mode, resid, p.bc, J.shape, grid, (i & 1) ? bwd : fwd, h->stream);
+    le = launch_steps(h, resid, J.shape, T, grid, grid, (i & 1) ? bwd : fwd);
   hipError_t ce = hipStreamEndCapture(h->stream, &g);
   if (le != hipSuccess || ce != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);

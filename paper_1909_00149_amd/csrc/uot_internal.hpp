@@ -70,6 +70,7 @@ struct IterArgs {
   const Tile* tiles;
   const int32_t* ntiles;
   const int32_t* active;
+  int32_t steps;      // iterations per launch of the temporally blocked kernel
 };
 
 struct CheckArgs {

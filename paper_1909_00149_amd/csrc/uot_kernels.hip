@@ -484,6 +484,186 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
   }
 }
 
+// Temporally blocked form: one launch runs `steps` (<= T) iterations with
+// the per-pixel arithmetic of the kernels above.  A workgroup loads its
+// 64 x TH tile with a halo of T pixels on every side (a, Mx, My into LDS, the
+// element-wise planes into registers) and repeats the flux phase and the
+// dual phase over the whole region.  One iteration couples a pixel only to
+// pixels at distance one (D* a looks one pixel up and right, D M one pixel
+// down and left, so a^{k+1} depends on a^k within distance one), so after s
+// steps every value is exact except within s pixels of the region's edge,
+// and a halo of T keeps the owned tile exact for up to T steps.  Pixels
+// outside the grid hold zero and are never updated, as in the single-step
+// kernels.  K(z^k) of each pixel is carried in a register from one step to
+// the next (it is the K(z^{k+1}) of the step before), so the old flux is not
+// needed again and the flux is updated in place.  The last iteration before
+// a convergence check runs in a single-step kernel, which leaves both
+// iterates the check compares in the ping-pong buffers.
+template <int MODE, int RES, int BC, int TH, int T>
+__global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
+  constexpr int RW = TX + 2 * T, RH = TH + 2 * T, NCELL = RW * RH;
+  constexpr int NC = (NCELL + BLOCK - 1) / BLOCK;
+  // LDS rows of RW cells plus a zero border; the rows past the region hold
+  // the cells of the last pass that fall outside it (always written zero)
+  constexpr int LW = RW + 2, LH = (NC * BLOCK + RW - 1) / RW + 2;
+  constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4, F_OWN = 8;  // per-cell flags
+  __shared__ float sa[LH * LW];
+  __shared__ float smx[LH * LW];
+  __shared__ float smy[LH * LW];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < LH * LW; i += BLOCK) sa[i] = smx[i] = smy[i] = 0.f;
+  const int steps = A.steps;
+  long t, stride, tend;
+  xcd_chunk(*A.ntiles, t, stride, tend);
+
+  for (; t < tend; t += stride) {
+    const Tile tl = A.tiles[t];
+    if (!A.active[tl.pair]) continue;  // uniform over the block
+    const PairInfo P = A.pairs[tl.pair];
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
+    const long off = P.off;
+    const float tau1 = P.tau1, tau2 = P.tau2, t2 = tau1 * tau1;
+    const int bx = tl.x0 - T, by = tl.y0 - T;  // grid position of region cell (0, 0)
+    int l_[NC], f_[NC];                        // LDS index and flags of each cell
+    float r_[NC], c0_[NC], c1_[NC], x0_[NC], x1_[NC], kp_[NC];
+
+    __syncthreads();  // LDS of the previous tile is no longer read
+    // ---- stage the region ----
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int idx = tid + k * BLOCK;
+      const int ry = idx / RW, rx = idx - ry * RW;
+      const int gx = bx + rx, gy = by + ry;
+      const bool in = ry < RH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      const int l = (ry + 1) * LW + rx + 1;
+      l_[k] = l;
+      f_[k] = (in ? F_IN : 0) | (BC == 0 && gx == nx - 1 ? F_ZX : 0) | (BC == 0 && gy == ny - 1 ? F_ZY : 0) |
+              (rx >= T && rx < T + TX && ry >= T && ry < T + TH ? F_OWN : 0);
+      float a = 0.f, mx = 0.f, my = 0.f;
+      r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
+      if (in) {
+        const long o = off + (long)gy * pitch + gx;
+        a = A.in.a[o];
+        mx = (BC == 0 && gx == nx - 1) ? 0.f : A.in.Mx[o];
+        my = (BC == 0 && gy == ny - 1) ? 0.f : A.in.My[o];
+        if (RES != R_BAL) r_[k] = A.in.r[o];
+        if (MODE == 0) {
+          c0_[k] = A.c[o];
+        } else {
+          c0_[k] = A.src[o];
+          c1_[k] = A.dst[o];
+          if (MODE == 1) x0_[k] = A.in.x0[o];
+          x1_[k] = A.in.x1[o];
+        }
+      }
+      sa[l] = a;
+      smx[l] = mx;
+      smy[l] = my;
+    }
+    __syncthreads();
+
+    // ---- K(z^k) of every cell ----
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int l = l_[k];
+      const float dmo = smx[l] - smx[l - 1] + smy[l] - smy[l - LW];
+      float kold;
+      if (MODE == 0) kold = dmo + c0_[k];
+      else if (MODE == 1) kold = dmo - x0_[k] + x1_[k];
+      else kold = dmo - c0_[k] + x1_[k];
+      if (RES != R_BAL) kold -= r_[k];
+      kp_[k] = kold;
+    }
+    __syncthreads();  // the flux phase overwrites M, which the neighbours read above
+
+    for (int st = 0; st < steps; ++st) {
+      // ---- new flux: read every cell's inputs, then compute and write ----
+      float ac_[NC], ar_[NC], au_[NC], mx_[NC], my_[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int l = l_[k];
+        ac_[k] = sa[l];
+        ar_[k] = sa[l + 1];
+        au_[k] = sa[l + LW];
+        mx_[k] = smx[l];
+        my_[k] = smy[l];
+      }
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        float gxx = ac_[k] - ar_[k];
+        float gyy = ac_[k] - au_[k];
+        if (BC == 0) {
+          if (f_[k] & F_ZX) gxx = 0.f;
+          if (f_[k] & F_ZY) gyy = 0.f;
+        }
+        const float vx = mx_[k] - tau1 * gxx;
+        const float vy = my_[k] - tau1 * gyy;
+        const float n2 = vx * vx + vy * vy;
+        const float sc = n2 > t2 ? 1.f - tau1 * rsqrtf(n2) : 0.f;
+        const bool in = f_[k] & F_IN;
+        smx[l_[k]] = in ? sc * vx : 0.f;
+        smy[l_[k]] = in ? sc * vy : 0.f;
+      }
+      __syncthreads();
+      // ---- element-wise steps and the dual update ----
+      float nc_[NC], nl_[NC], yc_[NC], yd_[NC], a_[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int l = l_[k];
+        nc_[k] = smx[l];
+        nl_[k] = smx[l - 1];
+        yc_[k] = smy[l];
+        yd_[k] = smy[l - LW];
+        a_[k] = sa[l];
+      }
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const float dmn = nc_[k] - nl_[k] + yc_[k] - yd_[k];
+        const float a = a_[k];
+        float knew, x0n = 0.f, x1n = 0.f, rn = 0.f;
+        if (RES == R_P1) rn = shrink1f(r_[k] + tau1 * a, P.mutau);
+        if (RES == R_P2) rn = (r_[k] + tau1 * a) * P.inv2mt;
+        if (MODE == 0) {
+          knew = dmn + c0_[k];
+        } else if (MODE == 1) {
+          const float th = P.theta;
+          x0n = fmaxf(th * c0_[k] + (1.f - th) * (x0_[k] + tau1 * a), 0.f);
+          x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
+          knew = dmn - x0n + x1n;
+        } else {
+          const float th = P.theta;
+          x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
+          knew = dmn - c0_[k] + x1n;
+        }
+        if (RES != R_BAL) knew -= rn;
+        const bool in = f_[k] & F_IN;
+        sa[l_[k]] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
+        kp_[k] = knew;
+        r_[k] = rn;
+        x0_[k] = x0n;
+        x1_[k] = x1n;
+      }
+      __syncthreads();
+    }
+
+    // ---- write the owned tile ----
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if ((f_[k] & (F_IN | F_OWN)) != (F_IN | F_OWN)) continue;
+      const int l = l_[k];
+      const int idx = tid + k * BLOCK;
+      const int ry = idx / RW, rx = idx - ry * RW;
+      const long o = off + (long)(by + ry) * pitch + (bx + rx);
+      A.out.Mx[o] = smx[l];
+      A.out.My[o] = smy[l];
+      A.out.a[o] = sa[l];
+      if (RES != R_BAL) A.out.r[o] = r_[k];
+      if (MODE == 1) A.out.x0[o] = x0_[k];
+      if (MODE != 0) A.out.x1[o] = x1_[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Block reduction of NS double slots into one partial row (and, if fin is
 // given, into that LDS row too, visible to the whole block on return).
@@ -820,6 +1000,12 @@ hipError_t iter_by_ty(int ty, int grid, const IterArgs& a, hipStream_t s) {
     case 132: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 32, false>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 316: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 16, true>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 332: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 32, true>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 4008: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 8, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 2016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 2>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 8016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 4016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 4032: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 32, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 8032: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 32, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -836,6 +1022,12 @@ hipError_t occ_by_ty(int ty, int* n) {
     case 132: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 32, false>, BLOCK, 0);
     case 316: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 16, true>, BLOCK, 0);
     case 332: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 32, true>, BLOCK, 0);
+    case 4008: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 8, 4>, BLOCK, 0);
+    case 2016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 2>, BLOCK, 0);
+    case 8016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 8>, BLOCK, 0);
+    case 4016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 4>, BLOCK, 0);
+    case 4032: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 32, 4>, BLOCK, 0);
+    case 8032: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 32, 8>, BLOCK, 0);
     default: return hipErrorInvalidValue;
   }
 }

@@ -52,6 +52,11 @@ def test_status_strings():
     (dict(max_iter=-1), _lib.UOT_ERR_ARG),
     (dict(tile_rows=5), _lib.UOT_ERR_ARG),
     (dict(tile_rows=16), 0),
+    (dict(tile_rows=4016), 0),
+    (dict(tile_rows=8032), 0),
+    (dict(tile_rows=3016), _lib.UOT_ERR_ARG),
+    (dict(tile_rows=4000), _lib.UOT_ERR_ARG),
+    (dict(nx=10, ny=10, pitch=9), _lib.UOT_ERR_SHAPE),
     (dict(flags=_lib.UOT_ALLOW_SIGNED, mode=PROX), _lib.UOT_ERR_ARG),
     (dict(nx=-1), _lib.UOT_ERR_SHAPE),
 ])

@@ -175,7 +175,7 @@ def test_autotuner_picks_a_shape_and_keeps_results(dev, tmp_path, monkeypatch):
     assert "gfx950:m0:r1:b0" in text
 
 
-@pytest.mark.parametrize("ty", [116, 316])
+@pytest.mark.parametrize("ty", [116, 316, 4016])
 def test_vectorised_kernel_on_odd_offsets_with_nan_gaps(dev, ty):
     """Pairs packed at offsets that are not multiples of 4, with NaN in the
     gaps between them (images and state): the vectorised kernel must agree

@@ -114,15 +114,16 @@ def test_fixed_iterations_all_modes(dev, mode, balanced, resid, bc, shape):
         assert abs(rep["dual"] - g.dual) <= VAL_TOL * max(abs(g.dual), abs(g.primal))
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332])
+@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332, 4008, 2016, 4016, 8016, 4032, 8032])
 @pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 1), (PROX_FIXED, True, 1),
                                                  (DIST, True, 1), (PROX, False, 2)])
 @pytest.mark.parametrize("shape", [(45, 133), (45, 132), (70, 256), (19, 66), (23, 131)])
 def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):
-    """Every tile shape, scalar or vectorised (116/132/316/332, on any row
+    """Every tile shape, scalar, vectorised (116/132/316/332, on any row
     width: rows off 16-byte boundaries and partial quads at row ends
-    included), computes each pixel with the same arithmetic: the iterates
-    are bitwise identical."""
+    included) or temporally blocked (several iterations per launch),
+    computes each pixel with the same arithmetic: the iterates are bitwise
+    identical."""
     p, q = pair_inputs(shape, 7, mode)
     if balanced and mode == DIST:
         q = (q * (p.astype(np.float64).sum() / q.astype(np.float64).sum())).astype(np.float32)
@@ -130,6 +131,32 @@ def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):
     st, _ = run_pair(dev, p, q, mode, balanced, resid, iters=40, tile_rows=ty)
     for k in planes_for(mode, balanced):
         assert torch.equal(base[k], st[k]), k
+
+
+@pytest.mark.parametrize("ty", [4008, 2016, 4016, 8016, 4032, 8032])
+@pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 2), (DIST, True, 1)])
+@pytest.mark.parametrize("shape,iters,check_every", [((3, 5), 17, 6), ((40, 131), 47, 20), ((70, 256), 61, 8),
+                                                     ((130, 9), 33, 10)])
+def test_blocked_shapes_with_checks_and_tails(dev, ty, mode, balanced, resid, shape, iters, check_every):
+    """Temporally blocked launches inside check windows (the last iteration
+    of a window runs single-step) and in an odd tail, with the stopping test
+    active (tol tiny, so it never stops): the iterates and every report
+    field agree bitwise with the single-step kernel over the same tile list
+    (the FP64 sums of the reports are taken per tile, so their rounding
+    follows the tile height).  Grids smaller than the halo and narrower than
+    a tile are included."""
+    p, q = pair_inputs(shape, 5, mode)
+    if balanced and mode == DIST:
+        q = (q * (p.astype(np.float64).sum() / q.astype(np.float64).sum())).astype(np.float32)
+    kw = dict(iters=iters, check_every=check_every, tol=1e-12)
+    rows = ty % 1000
+    base, rb = run_pair(dev, p, q, mode, balanced, resid, tile_rows=100 + rows if rows % 16 == 0 else rows, **kw)
+    st, rs = run_pair(dev, p, q, mode, balanced, resid, tile_rows=ty, **kw)
+    assert rs["tile_rows"] == ty and rs["iters"] == rb["iters"] == iters
+    for k in planes_for(mode, balanced):
+        assert torch.equal(base[k], st[k]), k
+    for f in ("rel_res", "objective", "feas", "primal", "dual"):
+        assert rb[f] == rs[f] or (np.isnan(rb[f]) and np.isnan(rs[f])), f
 
 
 @pytest.mark.parametrize("ty", [116, 316])

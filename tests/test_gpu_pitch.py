@@ -73,7 +73,7 @@ def solve_layout(dev, pairs, pitch_of, mode, balanced, ty, iters, tol=0.0, **kw)
     return by_pair(st, nx, ny, pitch, offs), reps
 
 
-@pytest.mark.parametrize("ty", [4, 16, 116, 316])
+@pytest.mark.parametrize("ty", [4, 16, 116, 316, 4032])
 @pytest.mark.parametrize("mode,balanced", [(DIST, False), (PROX, False), (PROX_FIXED, True)])
 def test_pitched_batch_equals_packed_batch_bitwise(dev, ty, mode, balanced):
     pairs = pairs_of(SHAPES, 100)

@@ -1,8 +1,9 @@
 """The profiling entry points uot_time_iterations(_batched) time the solver's
 own fused-iteration launches: from a zero state, n timed launches (plus the
-untimed replay before them, 2n in all) must leave bit for bit the state a
-cold solve of exactly 2n iterations leaves, and report the kernel shape that
-ran (the vectorised shapes run on any row width)."""
+untimed replay before them, 2n in all, of T iterations each for a
+temporally blocked shape) must leave bit for bit the state a cold solve of
+exactly 2nT iterations leaves, and report the kernel shape that ran (the
+vectorised shapes run on any row width)."""
 import numpy as np
 import pytest
 import torch
@@ -35,20 +36,21 @@ def pair(shape, seed, balanced):
 
 @pytest.mark.parametrize("mode,balanced", [(DIST, False), (DIST, True), (PROX, False)])
 @pytest.mark.parametrize("shape", [(40, 128), (45, 133)])
-@pytest.mark.parametrize("ty", [4, 116, 316])
+@pytest.mark.parametrize("ty", [4, 116, 316, 4016])
 def test_timed_launches_are_solver_iterations(dev, mode, balanced, shape, ty):
     p, q = pair(shape, 3, balanced)
     ny, nx = shape
     src, dst = torch.from_numpy(p).to(dev), torch.from_numpy(q).to(dev)
     n = 6
+    T = ty // 1000 if ty >= 1000 else 1  # iterations per launch
     kw = dict(nx=nx, ny=ny, mode=mode, balanced=balanced, mu=2.0, rho=0.5, tile_rows=ty)
-    ref, rep = G.Solver(G.Params(max_iter=2 * n, tol=0.0, **kw)).solve(src, dst)
+    ref, rep = G.Solver(G.Params(max_iter=2 * n * T, tol=0.0, **kw)).solve(src, dst)
     st = G.new_state(mode, balanced, shape, dev)
     ms, ran = G.Solver(G.Params(**kw)).time_iterations(src, dst, st, n)
     torch.cuda.synchronize()
     assert ran == ty
     assert rep["tile_rows"] == ran
-    assert rep["iters"] == 2 * n
+    assert rep["iters"] == 2 * n * T
     assert ms > 0.0
     for k in PLANES[(mode, balanced)]:
         assert torch.equal(st[k], ref[k]), k
