@@ -16,6 +16,7 @@ Contents
   dr          an independent Douglas-Rachford solver with a dense projection
   poisson     DCT-diagonalised Neumann-Poisson solve and a direct solve
   nn          FP64 conv net forward/backward and Adam for the warm start
+  admm        the ADMM solvers of Sec. IV that call the prox (Algorithm 2)
 
 Grid convention: an image is an array of shape (ny, nx); element [j, i] is
 pixel (i, j) of the paper, x fastest.  The flux M = (Mx, My) uses the same
