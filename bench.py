@@ -34,6 +34,8 @@ Workloads (seeded synthetic inputs):
   video63   the 63 consecutive frame pairs of a 64-frame 256x256 video,
             prox mode (rho = 1, mu = 2), one batched solve
   sweepN    one NxN pair, exactly 200 iterations (the size sweep)
+  uotdf     the run-time study of Algorithm 2 (UOT-DF ADMM, Sec. IV-A):
+            ADMM iterations and time per iteration at sides 8..2048
   copy      a plain 1 GiB device-to-device copy (calibrates the HBM byte
             counters of the profiler and shows the attainable copy rate)
 """
@@ -187,6 +189,9 @@ def main():
     from paper_1909_00149_amd import uot as G
 
     dev = torch.device("cuda:0")
+    if args.workload == "uotdf":
+        run_uotdf(args, dev)
+        return
     if args.workload == "copy":
         n = (1 << 30) // 4
         x = torch.ones(n, dtype=torch.float32, device=dev)
@@ -306,6 +311,88 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
+
+
+UOTDF_SIDES = (8, 16, 32, 64, 128, 256, 512, 1024, 2048)
+UOTDF_KW = dict(kappa=0.1, mu=1.0, rho=1.0)
+
+
+def run_uotdf(args, dev):
+    """The run-time study of Algorithm 2 (UOT-DF ADMM): denoising (Phi = I,
+    no l1 term) of a synthetic frame at sides 8..2048, one warm-started prox
+    pass per ADMM iteration, stop when both residuals are below 1e-3 (tested
+    every 10 iterations).  Per side: ADMM iterations to converge and the
+    device time per iteration (events around the replayed windows; median of
+    the timed steps).  `value` is pixel-ADMM-iterations per second at 512^2."""
+    import torch
+    from paper_1909_00149_amd import admm as A
+    from paper_1909_00149_amd import synth
+
+    rows = []
+    for side in UOTDF_SIDES:
+        s0, y = synth.df_frame(0, side)
+        ty, ts0 = torch.from_numpy(y).to(dev), torch.from_numpy(s0).to(dev)
+        solver = A.UotDf(side, side, prox_iters=1, max_iter=5000, check_every=10, eps=1e-3, **UOTDF_KW)
+        for _ in range(args.warmup):
+            solver.solve(ty, ts0)
+        reps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, rep = solver.solve(ty, ts0)
+            reps.append(rep)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        it = reps[-1]["iters"]
+        ms = float(np.median([r["ms_per_iter"] for r in reps]))
+        rows.append({"side": side, "pixels": side * side, "iters": it, "converged": bool(reps[-1]["converged"]),
+                     "ms_per_iter": round(ms, 5), "wall_ms": round(1e3 * wall, 3),
+                     "us_per_iter_per_kpx": round(1e3 * ms / (side * side / 1e3), 5)})
+        solver.close()
+    r512 = next(r for r in rows if r["side"] == 512)
+    value = 512 * 512 / (r512["ms_per_iter"] * 1e-3)
+    # per ADMM iteration at 512^2: the s/x/centre step streams 9 planes, the
+    # multiplier step 7, the prox pass 48 bytes per pixel (one-argument-fixed,
+    # unbalanced): 112 algorithmic bytes per pixel
+    bpp = 112
+    achieved = bpp * 512 * 512 / (r512["ms_per_iter"] * 1e-3) / 1e9
+    out = {
+        "metric": "UOT-DF ADMM pixel-iterations/s at 512^2 (Algorithm 2 run-time study)",
+        "value": value, "unit": "pixel-ADMM-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r512["wall_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uotdf", "description": "denoising, Phi = I, kappa 0.1, mu 1, rho 1, 1 prox pass "
+                   "per ADMM iteration (warm-started), eps 1e-3, check every 10"},
+        "sizes": rows,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "one ADMM iteration (df_sx_kernel + cp_iter_vec_kernel<2,1,0,16,false> + df_ab_kernel)",
+                     "bytes_per_pixel_iter": bpp},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = uotdf_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def uotdf_cpu_baseline(budget_s=15.0):
+    """The FP64 oracle of Algorithm 2 on one host thread, 64x64 frame: ADMM
+    iterations (one prox pass each) for about budget_s seconds."""
+    from threadpoolctl import threadpool_limits
+    from oracle import admm as ora
+    from paper_1909_00149_amd import synth
+    s0, y = synth.df_frame(0, 64)
+    with threadpool_limits(limits=1):
+        st = ora.df_initial_state(s0, **UOTDF_KW)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget_s:
+            for _ in range(10):
+                st = ora.df_iterate(y, s0, st, prox_iters=1, **UOTDF_KW)
+            n += 10
+        secs = time.perf_counter() - t0
+    return {"value": 64 * 64 * n / secs, "unit": "pixel-ADMM-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} FP64 oracle ADMM iterations (one prox pass each) of a 64x64 frame, one thread, "
+                      f"{secs:.1f} s"}
 
 
 def warm_vs_cold(dev, n):

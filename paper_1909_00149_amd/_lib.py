@@ -48,6 +48,23 @@ class Report(ctypes.Structure):
         return d
 
 
+class DfParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("balanced", ctypes.c_int32), ("residual_p", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("mu", ctypes.c_double), ("lam", ctypes.c_double),
+                ("rho", ctypes.c_double), ("prox_iters", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("eps", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class DfReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("r_primal", ctypes.c_double), ("r_dual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("ms_per_iter", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 SIGNATURES = {
@@ -87,6 +104,12 @@ SIGNATURES = {
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State)]),
     "uot_destroy": (None, [ctypes.c_void_p]),
+    "uotdf_check_params": (ctypes.c_int, [ctypes.POINTER(DfParams)]),
+    "uotdf_create": (ctypes.c_int, [ctypes.POINTER(DfParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "uotdf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.POINTER(DfReport)]),
+    "uotdf_copy_planes": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "uotdf_destroy": (None, [ctypes.c_void_p]),
     "uot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 

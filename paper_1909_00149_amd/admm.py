@@ -1,0 +1,70 @@
+"""Python binding of the ADMM solvers of include/uot_admm.h (argument
+marshalling only: every step runs in the library's HIP kernels).
+
+UOT-DF (Sec. IV-A, Algorithm 2): ``UotDf(nx, ny, kappa=..., mu=..., rho=...)
+.solve(y, s0, phi=None)`` returns the frame estimate s and the report.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from .uot import UOTError, _ptr
+
+
+class UotDf:
+    """One UOT-DF handle for a grid of ny x nx pixels on the current device
+    and stream."""
+
+    def __init__(self, nx, ny, kappa, mu, rho, lam=0.0, balanced=False, residual_p=1, bc=0, prox_iters=1,
+                 max_iter=5000, check_every=10, eps=1e-3, flags=0, stream=None):
+        self.lib = _lib.load()
+        self.shape = (int(ny), int(nx))
+        self._c = _lib.DfParams(int(nx), int(ny), int(balanced), int(residual_p), int(bc), float(kappa), float(mu),
+                                float(lam), float(rho), int(prox_iters), int(max_iter), int(check_every), float(eps),
+                                int(flags))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.uotdf_create(ctypes.byref(self._c), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise UOTError(rc, "uotdf_create")
+        self._h = h
+
+    @staticmethod
+    def check(**kw) -> int:
+        """uotdf_check_params on keyword parameters (0 = valid)."""
+        d = dict(nx=1, ny=1, balanced=0, residual_p=1, bc=0, kappa=1.0, mu=1.0, lam=0.0, rho=1.0, prox_iters=1,
+                 max_iter=10, check_every=1, eps=1e-3, flags=0)
+        d.update(kw)
+        c = _lib.DfParams(*[d[k] for k, _ in _lib.DfParams._fields_])
+        return int(_lib.load().uotdf_check_params(ctypes.byref(c)))
+
+    def solve(self, y, s0, phi=None, out=None):
+        s = torch.empty_like(y) if out is None else out
+        rep = _lib.DfReport()
+        rc = self.lib.uotdf_solve(self._h, _ptr(y), _ptr(phi), _ptr(s0), _ptr(s), ctypes.byref(rep))
+        if rc != 0:
+            raise UOTError(rc, "uotdf_solve")
+        return s, rep.as_dict()
+
+    def planes(self, device="cuda"):
+        """The ADMM planes x, z, a, b left by the last solve."""
+        out = {k: torch.empty(self.shape, dtype=torch.float32, device=device) for k in ("x", "z", "a", "b")}
+        rc = self.lib.uotdf_copy_planes(self._h, *[_ptr(out[k]) for k in ("x", "z", "a", "b")])
+        if rc != 0:
+            raise UOTError(rc, "uotdf_copy_planes")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.uotdf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -33,7 +33,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["uot_kernels.hip", "uot_poisson.hip", "uot_host.cpp", "uotnet_kernels.hip", "uotnet_host.cpp"]
+SOURCES = ["uot_kernels.hip", "uot_poisson.hip", "uot_host.cpp", "uot_admm_kernels.hip", "uot_admm_host.cpp",
+           "uotnet_kernels.hip", "uotnet_host.cpp"]
 
 
 def hipcc():

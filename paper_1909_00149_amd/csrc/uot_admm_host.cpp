@@ -1,0 +1,343 @@
+// Host runtime of the ADMM solvers that call the UOT prox (C ABI of
+// include/uot_admm.h).
+//
+// UOT-DF (Sec. IV-A, Algorithm 2).  One ADMM iteration is three groups of
+// launches on the handle's stream: the element-wise s/x/centre step, the
+// prox passes (the fused Algorithm-1 kernel in the one-argument-fixed mode,
+// warm-started: its state stays on the device between ADMM iterations), and
+// the element-wise multiplier step.  A check window of ADMM iterations is
+// captured once as a HIP graph and replayed; on the window's last iteration
+// the element-wise kernels leave residual partials, one reduction adds them
+// and three doubles come back to the host, which decides whether to stop.
+// The prox state ping-pongs between two copies; a window flips the copy it
+// ends in when it holds an odd number of prox launches, so graphs are kept
+// for both starting copies.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "uot.h"
+#include "uot_admm.h"
+#include "uot_admm_internal.hpp"
+
+using namespace uot;
+
+namespace {
+
+#define DFCHK(x)                          \
+  do {                                    \
+    if ((x) != hipSuccess) return UOT_ERR_DEVICE; \
+  } while (0)
+
+constexpr int NPLANES = 5;  // prox state: Mx, My, r, a (prox dual), x1 (= z)
+
+struct GraphSlot {
+  hipGraphExec_t exec = nullptr;
+  int W = -1;
+  const void *y = nullptr, *phi = nullptr, *s0 = nullptr;
+};
+
+}  // namespace
+
+struct uotdf_handle {
+  uotdf_params prm{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;  // NULL was passed: a stream of our own (graphs cannot capture the null stream)
+  int device = 0, num_cu = 256;
+  long n = 0;
+  int resid = R_P1;
+  float *s = nullptr, *x = nullptr, *a = nullptr, *b = nullptr, *p = nullptr, *zo = nullptr;
+  float* st[2][NPLANES] = {};
+  PairInfo* d_pair = nullptr;
+  Tile* d_tiles = nullptr;
+  int32_t* d_ntiles = nullptr;
+  int32_t* d_active = nullptr;
+  int ntiles = 0, shape = 4, T = 1, grid = 8, launches_per_iter = 1;
+  double* d_partial = nullptr;
+  double* d_sums = nullptr;
+  double* h_sums = nullptr;  // pinned
+  int nblocks = 1;
+  int parity = 0;            // copy holding the current prox state
+  GraphSlot graphs[2];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+
+  ~uotdf_handle() {
+    for (auto& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (float* q : {s, x, a, b, p, zo})
+      if (q) (void)hipFree(q);
+    for (auto& c : st)
+      for (float* q : c)
+        if (q) (void)hipFree(q);
+    if (d_pair) (void)hipFree(d_pair);
+    if (d_tiles) (void)hipFree(d_tiles);
+    if (d_ntiles) (void)hipFree(d_ntiles);
+    if (d_active) (void)hipFree(d_active);
+    if (d_partial) (void)hipFree(d_partial);
+    if (d_sums) (void)hipFree(d_sums);
+    if (h_sums) (void)hipHostFree(h_sums);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+Planes prox_planes(uotdf_handle* h, int c) {
+  float** q = h->st[c];
+  return Planes{q[0], q[1], h->prm.balanced ? nullptr : q[2], q[3], nullptr, q[4]};
+}
+
+// One ADMM iteration (see the file comment); record: leave residual partials.
+uot_status enqueue_iteration(uotdf_handle* h, const float* y, const float* phi, const float* s0, bool record) {
+  const uotdf_params& P = h->prm;
+  DfArgs A{h->n, y, phi, h->s, h->x, h->a, h->b, h->p, h->zo, h->st[h->parity][4], (float)P.rho,
+           (float)(P.lam / (2.0 * P.rho)), record ? 1 : 0, h->d_partial};
+  DFCHK(launch_df_sx(A, h->stream));
+  for (int left = P.prox_iters; left > 0;) {
+    const int k = std::min(h->T, left);
+    IterArgs it{prox_planes(h, h->parity), prox_planes(h, h->parity ^ 1), nullptr, s0, h->p, h->d_pair,
+                h->d_tiles, h->d_ntiles, h->d_active, k};
+    DFCHK(launch_iter(UOT_PROX_FIXED, h->resid, P.bc, h->shape, h->grid, it, h->stream));
+    h->parity ^= 1;
+    left -= k;
+  }
+  A.z = h->st[h->parity][4];
+  DFCHK(launch_df_ab(A, h->stream));
+  return UOT_OK;
+}
+
+// W ADMM iterations with residual partials on the last, then the reduction
+// and the copy of the three sums to the host (not waited for).
+uot_status enqueue_window(uotdf_handle* h, int W, const float* y, const float* phi, const float* s0) {
+  for (int i = 0; i < W; ++i) {
+    uot_status s = enqueue_iteration(h, y, phi, s0, i == W - 1);
+    if (s != UOT_OK) return s;
+  }
+  DFCHK(launch_df_reduce(h->d_partial, h->nblocks, h->d_sums, h->stream));
+  DFCHK(hipMemcpyAsync(h->h_sums, h->d_sums, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  return UOT_OK;
+}
+
+uot_status run_window(uotdf_handle* h, int W, const float* y, const float* phi, const float* s0, bool use_graph) {
+  if (!use_graph) return enqueue_window(h, W, y, phi, s0);
+  const int start = h->parity;
+  GraphSlot& g = h->graphs[start];
+  if (!(g.exec && g.W == W && g.y == y && g.phi == phi && g.s0 == s0)) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    DFCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    uot_status st = enqueue_window(h, W, y, phi, s0);
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (st != UOT_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      h->parity = start;
+      return st != UOT_OK ? st : UOT_ERR_DEVICE;
+    }
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      h->parity = start;
+      return UOT_ERR_DEVICE;
+    }
+    g.W = W;
+    g.y = y;
+    g.phi = phi;
+    g.s0 = s0;
+    // capturing advanced the host's parity bookkeeping; the replay below does it again
+    h->parity = start;
+  }
+  DFCHK(hipGraphLaunch(g.exec, h->stream));
+  if ((W * h->launches_per_iter) & 1) h->parity ^= 1;
+  return UOT_OK;
+}
+
+double elapsed_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+uot_status uotdf_check_params(const uotdf_params* p) {
+  if (!p) return UOT_ERR_ARG;
+  if (p->nx < 1 || p->ny < 1) return UOT_ERR_SHAPE;
+  if (!(p->kappa > 0.0) || !(p->rho > 0.0) || !(p->lam >= 0.0) || !std::isfinite(p->kappa) ||
+      !std::isfinite(p->rho) || !std::isfinite(p->lam) || !std::isfinite(p->eps))
+    return UOT_ERR_ARG;
+  if (!p->balanced && (!(p->mu > 0.0) || !std::isfinite(p->mu))) return UOT_ERR_ARG;
+  if (p->residual_p != 1 && p->residual_p != 2) return UOT_ERR_ARG;
+  if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
+  if (p->prox_iters < 1 || p->max_iter < 1 || p->check_every < 1) return UOT_ERR_ARG;
+  return UOT_OK;
+}
+
+uot_status uotdf_create(const uotdf_params* prm, void* hip_stream, uotdf_handle** out) {
+  if (!out) return UOT_ERR_ARG;
+  *out = nullptr;
+  uot_status s = uotdf_check_params(prm);
+  if (s != UOT_OK) return s;
+  uotdf_handle* h = new (std::nothrow) uotdf_handle();
+  if (!h) return UOT_ERR_OOM;
+  h->prm = *prm;
+  h->n = (long)prm->nx * prm->ny;
+  h->resid = prm->balanced ? R_BAL : (prm->residual_p == 2 ? R_P2 : R_P1);
+  auto fail = [&](uot_status e) {
+    delete h;
+    return e;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return fail(UOT_ERR_DEVICE);
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) return fail(UOT_ERR_DEVICE);
+    h->own_stream = true;
+  }
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cu > 0)
+    h->num_cu = cu;
+  const size_t bytes = (size_t)h->n * sizeof(float);
+  for (float** q : {&h->s, &h->x, &h->a, &h->b, &h->p, &h->zo})
+    if (hipMalloc((void**)q, bytes) != hipSuccess) return fail(UOT_ERR_OOM);
+  for (int c = 0; c < 2; ++c)
+    for (int k = 0; k < NPLANES; ++k)
+      if (hipMalloc((void**)&h->st[c][k], bytes) != hipSuccess) return fail(UOT_ERR_OOM);
+
+  // the prox as one Algorithm-1 pair: fixed argument s0, step kappa / rho
+  const double k2 = uot_knorm2(prm->nx, prm->ny, UOT_PROX_FIXED, prm->balanced, prm->bc);
+  const double t = 0.99 / std::sqrt(k2);
+  const double rho_prox = prm->kappa / prm->rho;
+  // kernel shape: one pass per ADMM iteration -> the single-step kernel;
+  // several -> the temporally blocked kernel, up to 4 passes per launch
+  if (prm->prox_iters == 1) {
+    h->shape = h->n <= (1L << 16) ? 4 : 116;
+    h->T = 1;
+  } else {
+    h->shape = h->n <= (1L << 18) ? 4008 : 4016;
+    h->T = 4;
+  }
+  h->launches_per_iter = (prm->prox_iters + h->T - 1) / h->T;
+  const int rows = h->shape >= 1000 ? h->shape % 1000 : h->shape % 100;
+  std::vector<Tile> tiles;
+  for (int y = 0; y < prm->ny; y += rows)
+    for (int x = 0; x < prm->nx; x += TX) tiles.push_back(Tile{0, x, y, 0});
+  h->ntiles = (int)tiles.size();
+  PairInfo P{};
+  P.off = 0;
+  P.nx = prm->nx;
+  P.ny = prm->ny;
+  P.tau1 = (float)t;
+  P.tau2 = (float)t;
+  P.theta = (float)(t / (rho_prox + t));
+  P.mutau = (float)(prm->mu * t);
+  P.inv2mt = (float)(1.0 / (1.0 + 2.0 * prm->mu * t));
+  P.tile_begin = 0;
+  P.tile_count = h->ntiles;
+  P.pitch = prm->nx;
+  const int32_t one = 1;
+  if (hipMalloc((void**)&h->d_pair, sizeof(PairInfo)) != hipSuccess ||
+      hipMalloc((void**)&h->d_tiles, tiles.size() * sizeof(Tile)) != hipSuccess ||
+      hipMalloc((void**)&h->d_ntiles, sizeof(int32_t)) != hipSuccess ||
+      hipMalloc((void**)&h->d_active, sizeof(int32_t)) != hipSuccess)
+    return fail(UOT_ERR_OOM);
+  if (hipMemcpy(h->d_pair, &P, sizeof(PairInfo), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_ntiles, &h->ntiles, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_active, &one, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(UOT_ERR_DEVICE);
+  int occ = 0;
+  if (iter_occupancy(UOT_PROX_FIXED, h->resid, prm->bc, h->shape, &occ) != hipSuccess || occ <= 0) occ = 2;
+  long g = std::min<long>(h->ntiles, (long)h->num_cu * occ);
+  h->grid = (int)std::max<long>(8, (g + 7) / 8 * 8);
+  h->nblocks = df_blocks(h->n);
+  if (hipMalloc((void**)&h->d_partial, 3 * (size_t)h->nblocks * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->d_sums, 3 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_sums, 3 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return fail(UOT_ERR_OOM);
+  if (hipEventCreate(&h->e0) != hipSuccess || hipEventCreate(&h->e1) != hipSuccess) return fail(UOT_ERR_DEVICE);
+  *out = h;
+  return UOT_OK;
+}
+
+uot_status uotdf_solve(uotdf_handle* h, const float* y, const float* phi, const float* s0, float* s_out,
+                       uotdf_report* rep) {
+  if (!h || !y || !s0 || !s_out || !rep) return UOT_ERR_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  const uotdf_params& P = h->prm;
+  std::memset(rep, 0, sizeof(*rep));
+  if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+  // inputs: finite, s0 >= 0
+  DFCHK(launch_df_validate(h->n, y, phi, s0, h->d_partial, h->stream));
+  DFCHK(launch_df_reduce(h->d_partial, h->nblocks, h->d_sums, h->stream));
+  DFCHK(hipMemcpyAsync(h->h_sums, h->d_sums, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  DFCHK(hipStreamSynchronize(h->stream));
+  if (h->h_sums[0] > 0.0) return UOT_ERR_NONFINITE;
+  if (h->h_sums[1] > 0.0) return UOT_ERR_NEGATIVE;
+  // every variable and the prox state start at zero (Algorithm 2)
+  const size_t bytes = (size_t)h->n * sizeof(float);
+  for (float* q : {h->s, h->x, h->a, h->b, h->p, h->zo}) DFCHK(hipMemsetAsync(q, 0, bytes, h->stream));
+  for (auto& c : h->st)
+    for (float* q : c) DFCHK(hipMemsetAsync(q, 0, bytes, h->stream));
+  h->parity = 0;
+
+  const bool use_graph = !(P.flags & UOT_NO_GRAPH);
+  const int W = P.check_every;
+  const int nwin = P.max_iter / W, tail = P.max_iter % W;
+  int k = 0;
+  bool conv = false;
+  double rp = std::nan(""), rd = std::nan("");
+  DFCHK(hipEventRecord(h->e0, h->stream));
+  auto test = [&](int iters) -> uot_status {
+    DFCHK(hipStreamSynchronize(h->stream));
+    rp = std::sqrt(std::max(0.0, h->h_sums[0]));
+    rd = P.rho * std::sqrt(std::max(0.0, h->h_sums[1] + h->h_sums[2]));
+    k = iters;
+    if (P.eps > 0.0 && rp < P.eps && rd < P.eps) conv = true;
+    return UOT_OK;
+  };
+  for (int w = 0; w < nwin && !conv; ++w) {
+    uot_status s = run_window(h, W, y, phi, s0, use_graph);
+    if (s != UOT_OK) return s;
+    s = test((w + 1) * W);
+    if (s != UOT_OK) return s;
+  }
+  if (!conv && tail > 0) {
+    uot_status s = enqueue_window(h, tail, y, phi, s0);
+    if (s != UOT_OK) return s;
+    s = test(P.max_iter);
+    if (s != UOT_OK) return s;
+  }
+  DFCHK(hipEventRecord(h->e1, h->stream));
+  DFCHK(hipMemcpyAsync(s_out, h->s, bytes, hipMemcpyDeviceToDevice, h->stream));
+  DFCHK(hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  DFCHK(hipEventElapsedTime(&ms, h->e0, h->e1));
+  rep->iters = k;
+  rep->converged = conv ? 1 : 0;
+  rep->r_primal = rp;
+  rep->r_dual = rd;
+  rep->ms_per_iter = k > 0 ? (double)ms / k : 0.0;
+  rep->seconds = elapsed_s(t0);
+  return UOT_OK;
+}
+
+uot_status uotdf_copy_planes(uotdf_handle* h, float* x, float* z, float* a, float* b) {
+  if (!h) return UOT_ERR_ARG;
+  const size_t bytes = (size_t)h->n * sizeof(float);
+  const float* src[4] = {h->x, h->st[h->parity][4], h->a, h->b};
+  float* dst[4] = {x, z, a, b};
+  for (int i = 0; i < 4; ++i)
+    if (dst[i]) DFCHK(hipMemcpyAsync(dst[i], src[i], bytes, hipMemcpyDeviceToDevice, h->stream));
+  DFCHK(hipStreamSynchronize(h->stream));
+  return UOT_OK;
+}
+
+void uotdf_destroy(uotdf_handle* h) { delete h; }
+
+}  // extern "C"

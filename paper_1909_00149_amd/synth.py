@@ -103,6 +103,17 @@ def sweep_pair(seed: int, side: int):
     return unbalanced_pair(seed, side=side, nblobs=nb, margin=min(24.0, side / 4.0))
 
 
+def df_frame(seed: int, side: int):
+    """A frame for the dynamic filter of Sec. IV-A: the prediction s0 (the
+    previous frame) and the observation y of the next frame with Phi = I, by
+    the sweep recipe (blob count proportional to the area, sub-pixel motion,
+    mass change, Poisson noise), both divided by the peak of s0 so that
+    active pixels are of order one as in the paper's experiments."""
+    p, q = sweep_pair(seed, side)
+    m = float(p.max())
+    return (p / m).astype(np.float32), (q / m).astype(np.float32)
+
+
 def ragged_batch(seed: int, batch: int = 256, lo: int = 32, hi: int = 512):
     """Ragged batch: sides round(exp(U[ln lo, ln hi])), square pairs."""
     rng = np.random.default_rng(seed)

@@ -73,3 +73,13 @@ def test_knorm2_matches_oracle(mode, bal, bc):
     from oracle import ops
     for nx, ny in [(1, 1), (64, 64), (512, 37), (3, 1000)]:
         assert abs(knorm2(nx, ny, mode, bal, bc) - ops.knorm2(nx, ny, mode, bal, bc)) < 1e-12
+
+
+@pytest.mark.parametrize("kw,ok", [({}, True), (dict(kappa=0.0), False), (dict(rho=-1.0), False),
+                                   (dict(prox_iters=0), False), (dict(check_every=0), False),
+                                   (dict(mu=0.0), False), (dict(mu=0.0, balanced=1), True),
+                                   (dict(lam=-0.1), False), (dict(residual_p=3), False), (dict(nx=0), False),
+                                   (dict(eps=float("nan")), False)])
+def test_uotdf_check_params(kw, ok):
+    from paper_1909_00149_amd.admm import UotDf
+    assert (UotDf.check(**kw) == 0) == ok
