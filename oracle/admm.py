@@ -136,3 +136,167 @@ def uotdf_objective(y, s, s0, kappa, mu, phi=None, lam=0.0, balanced=False):
     ph = np.ones_like(y) if phi is None else np.asarray(phi, float)
     v = beckmann_aniso(s, np.asarray(s0, float), mu=None if balanced else mu, balanced=balanced)
     return 0.5 * float(np.sum((y - ph * s) ** 2)) + lam * float(np.sum(np.abs(s))) + kappa * v
+
+
+# ---------------------------------------------------------------------------
+# RPCA+UOT-DF (Sec. IV-B, eq. RPCA_UOTDF, Algorithm 3):
+#
+#   min_{S, L >= 0} 1/2 sum_t ||y_t - Phi_t (s_t + l_t)||^2 + lam ||S||_1
+#                   + gam ||L||_* + kappa sum_{t<T} V_mu(s_t, s_{t+1})
+#
+# frames are the first axis (S[t] is frame t, an ny x nx image).  Splitting
+# X = S + L, Tn = L, z_t = s_t, w_{t+1} = s_{t+1} with multipliers A, D, b, c
+# and penalty rho, one ADMM iteration in the order of Algorithm 3:
+#
+#   k_t  = (x_t - l_t + a_t) + wz_t (z_t + b_t) + ww_t (w_t + c_t)
+#   s_t  = max(k_t / sig_t - lam / (rho sig_t), 0),  sig_t = 1 + wz_t + ww_t
+#   L    = max((Tn - D + X - S + A) / 2, 0)
+#   x_t  = (Phi_t^T Phi_t + rho I)^{-1} (Phi_t^T y_t + rho (s_t + l_t - a_t))
+#   Tn   = SVT_{gam/rho}(L + D)          (singular-value soft threshold)
+#   (z_t, w_{t+1}) = prox_{(kappa/rho) V_mu}(s_t - b_t, s_{t+1} - c_{t+1})
+#   A   += X - S - L,   D += L - Tn
+#   b_t += z_t - s_t,   c_{t+1} += w_{t+1} - s_{t+1}
+#
+# with wz_t = 1 for t < T and ww_t = 1 for t > 1 (zero otherwise).
+#
+# Readings:
+#   - S >= 0 makes the s-step the one-sided shrink max(k/sig - lam/(rho sig), 0).
+#   - x-step: the augmented Lagrangian's block rho/2 ||X - S - L + A||^2 gives
+#     Phi^T y + rho (s + l - a); the printed line omits rho on the second term.
+#   - A-step: the same block gives A += X - S - L; the printed line has + L.
+#   - The prox of each frame pair is the full prox (eq. Prox_UOT) with both
+#     arguments free and prox step kappa / rho, warm-started per pair.
+#   - Residuals (the paper cites Boyd et al. Sec. 3.3 and, for Algorithm 2,
+#     stacks the constraint violations and the changes of the split
+#     variables): primal ||[X - S - L; L - Tn; z - s; w - s]||, dual
+#     rho ||[dX; dTn; dz; dw]||.
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class RpcaState:
+    S: np.ndarray
+    L: np.ndarray
+    X: np.ndarray
+    Tn: np.ndarray
+    A: np.ndarray
+    D: np.ndarray
+    b: np.ndarray   # frames 1..T-1 (index t-1 ... stored for pairs 0..T-2)
+    c: np.ndarray   # multipliers of w: pair t holds c_{t+1}
+    prox: list      # per frame pair: uot.State (x0 = z_t, x1 = w_{t+1})
+
+    @property
+    def Z(self):
+        return np.stack([p.x0 for p in self.prox]) if self.prox else np.zeros((0,) + self.S.shape[1:])
+
+    @property
+    def W(self):
+        return np.stack([p.x1 for p in self.prox]) if self.prox else np.zeros((0,) + self.S.shape[1:])
+
+
+def svt(M, thr):
+    """Singular-value soft threshold of the N x T matrix whose columns are
+    the frames of M (frames on the first axis)."""
+    T = M.shape[0]
+    flat = M.reshape(T, -1).T
+    U, sv, Vt = np.linalg.svd(flat, full_matrices=False)
+    out = (U * np.maximum(sv - thr, 0.0)) @ Vt
+    return out.T.reshape(M.shape)
+
+
+def rpca_problem(p0, p1, kappa, mu, rho, balanced=False, residual_p=1, bc=0):
+    """The (z_t, w_{t+1}) subproblem as an Algorithm-1 problem: PROX with
+    centres p0 = s_t - b_t, p1 = s_{t+1} - c_{t+1}, prox step kappa / rho."""
+    from .ops import PROX
+    return uot.Problem(np.asarray(p0, float), np.asarray(p1, float), mode=PROX, balanced=balanced,
+                       residual_p=residual_p, bc=bc, mu=mu, rho=kappa / rho)
+
+
+def rpca_initial_state(shape, kappa, mu, rho, balanced=False, residual_p=1, bc=0) -> RpcaState:
+    T = shape[0]
+    z = np.zeros(shape)
+    zf = np.zeros(shape[1:])
+    prox = [uot.initial_state(rpca_problem(zf, zf, kappa, mu, rho, balanced, residual_p, bc)) for _ in range(T - 1)]
+    return RpcaState(z.copy(), z.copy(), z.copy(), z.copy(), z.copy(), z.copy(), np.zeros((T - 1,) + shape[1:]),
+                     np.zeros((T - 1,) + shape[1:]), prox)
+
+
+def rpca_iterate(Y, st: RpcaState, kappa, mu, rho, lam, gam, phi=None, balanced=False, residual_p=1, bc=0,
+                 prox_iters=1, tau=None) -> RpcaState:
+    """One ADMM iteration of Algorithm 3 (see the comment above)."""
+    Y = np.asarray(Y, float)
+    T = Y.shape[0]
+    ph = np.ones_like(Y) if phi is None else np.asarray(phi, float)
+    Z, W = st.Z, st.W
+    k = st.X - st.L + st.A
+    sig = np.ones((T,) + Y.shape[1:])
+    if T > 1:
+        k[:-1] += Z + st.b
+        k[1:] += W + st.c
+        sig[:-1] += 1.0
+        sig[1:] += 1.0
+    S = np.maximum(k / sig - lam / (rho * sig), 0.0)
+    L = np.maximum(0.5 * (st.Tn - st.D + st.X - S + st.A), 0.0)
+    X = (ph * Y + rho * (S + L - st.A)) / (ph * ph + rho)
+    Tn = svt(L + st.D, gam / rho)
+    prox = []
+    for t in range(T - 1):
+        prob = rpca_problem(S[t] - st.b[t], S[t + 1] - st.c[t], kappa, mu, rho, balanced, residual_p, bc)
+        t1, t2 = prob.default_steps() if tau is None else tau
+        pst = st.prox[t]
+        for _ in range(prox_iters):
+            pst = uot.iterate(prob, pst, t1, t2)
+        prox.append(pst)
+    nz = np.stack([p.x0 for p in prox]) if prox else Z
+    nw = np.stack([p.x1 for p in prox]) if prox else W
+    A = st.A + X - S - L
+    D = st.D + L - Tn
+    b = st.b + (nz - S[:-1])
+    c = st.c + (nw - S[1:])
+    return RpcaState(S, L, X, Tn, A, D, b, c, prox)
+
+
+def rpca_residuals(prev: RpcaState, cur: RpcaState, rho):
+    S = cur.S
+    rp2 = np.sum((cur.X - S - cur.L) ** 2) + np.sum((cur.L - cur.Tn) ** 2)
+    rd2 = np.sum((cur.X - prev.X) ** 2) + np.sum((cur.Tn - prev.Tn) ** 2)
+    if cur.prox:
+        rp2 += np.sum((cur.Z - S[:-1]) ** 2) + np.sum((cur.W - S[1:]) ** 2)
+        rd2 += np.sum((cur.Z - prev.Z) ** 2) + np.sum((cur.W - prev.W) ** 2)
+    return float(np.sqrt(rp2)), float(rho * np.sqrt(rd2))
+
+
+def rpca_uotdf(Y, kappa, mu, rho, lam, gam, phi=None, balanced=False, residual_p=1, bc=0, prox_iters=1,
+               max_iter=5000, eps=1e-4, check_every=1, tau=None, record=False):
+    """Algorithm 3 until both residuals are below eps (tested every
+    check_every iterations) or max_iter; returns (state, report)."""
+    Y = np.asarray(Y, float)
+    st = rpca_initial_state(Y.shape, kappa, mu, rho, balanced, residual_p, bc)
+    rep = DfReport()
+    for k in range(1, max_iter + 1):
+        nxt = rpca_iterate(Y, st, kappa, mu, rho, lam, gam, phi, balanced, residual_p, bc, prox_iters, tau)
+        if k % check_every == 0 or k == max_iter:
+            rp, rd = rpca_residuals(st, nxt, rho)
+            rep.r_primal, rep.r_dual = rp, rd
+            if record:
+                rep.history.append((k, rp, rd))
+            if rp < eps and rd < eps:
+                rep.iters, rep.converged = k, True
+                return nxt, rep
+        st = nxt
+    rep.iters = max_iter
+    return st, rep
+
+
+def rpca_objective(Y, S, L, kappa, mu, lam, gam, phi=None, balanced=False):
+    """The objective of eq. RPCA_UOTDF with V from the linear program (exact
+    on grids one pixel high or wide)."""
+    from .lp import beckmann_aniso
+    Y = np.asarray(Y, float)
+    ph = np.ones_like(Y) if phi is None else np.asarray(phi, float)
+    T = Y.shape[0]
+    f = 0.5 * float(np.sum((Y - ph * (S + L)) ** 2)) + lam * float(np.sum(np.abs(S)))
+    f += gam * float(np.sum(np.linalg.svd(L.reshape(T, -1).T, compute_uv=False)))
+    for t in range(T - 1):
+        f += kappa * beckmann_aniso(S[t], S[t + 1], mu=None if balanced else mu, balanced=balanced)
+    return f
