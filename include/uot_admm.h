@@ -96,6 +96,69 @@ uot_status uotdf_copy_planes(uotdf_handle *h, float *x, float *z, float *a, floa
 
 void uotdf_destroy(uotdf_handle *h);
 
+/*
+ * RPCA+UOT-DF (Sec. IV-B, eq. RPCA_UOTDF, Algorithm 3): separation of T
+ * frames y_t = Phi_t (s_t + l_t) + noise into a sparse part S >= 0, coupled
+ * across consecutive frames by unbalanced transport, and a low-rank part
+ * L >= 0:
+ *
+ *   min 1/2 sum_t ||y_t - Phi_t (s_t + l_t)||^2 + lam ||S||_1 + gam ||L||_*
+ *       + kappa sum_{t<T} V_mu(s_t, s_{t+1})
+ *
+ * by ADMM with the splitting X = S + L, Tn = L, z_t = s_t, w_{t+1} = s_{t+1}
+ * (multipliers A, D, b, c); one iteration runs the lines of Algorithm 3:
+ * the s-step (one-sided l1 shrink of the sigma-weighted average), the L-step,
+ * the x-step (diagonal Phi), the singular-value threshold of L + D, the full
+ * prox of every frame pair ((kappa/rho) V_mu at (s_t - b_t, s_{t+1} - c_{t+1}),
+ * `prox_iters` warm-started passes of Algorithm 1 over the batch of T - 1
+ * pairs), and the multiplier steps.  Stops when the stacked constraint
+ * violations ||[X - S - L; L - Tn; z - s; w - s]|| and rho times the stacked
+ * changes ||[dX; dTn; dz; dw]|| are both below eps.
+ *
+ * Readings: the x-step carries rho on (s + l - a) and the A-step subtracts L
+ * (both as the augmented Lagrangian the paper writes gives them; the printed
+ * lines differ).  The singular-value threshold goes through the T x T Gram
+ * matrix of L + D, whose eigenvectors a parallel Jacobi method finds,
+ * started from the previous iteration's.
+ *
+ * Layout: frames packed back to back, frame t at element t * nx * ny; y and
+ * phi hold T frames, S and L (outputs) T frames.  2 <= frames <= 64.
+ */
+typedef struct rpca_params {
+  int32_t nx, ny, frames;
+  int32_t balanced, residual_p, bc;
+  double lam;           /* l1 weight of S, >= 0                                             */
+  double gam;           /* nuclear-norm weight of L, >= 0                                   */
+  double kappa, mu;     /* transport weight (> 0) and growth/decay weight (> 0, unbalanced) */
+  double rho;           /* ADMM penalty, > 0                                                */
+  int32_t prox_iters, max_iter, check_every;
+  double eps;           /* residual threshold (the paper uses 1e-4); <= 0 runs max_iter      */
+  uint32_t flags;       /* UOT_NO_GRAPH                                                      */
+} rpca_params;
+
+typedef struct rpca_report {
+  int32_t iters, converged;
+  double r_primal, r_dual;
+  double seconds;       /* wall time of the call                                            */
+  double ms_per_iter;   /* device time per ADMM iteration                                   */
+  int32_t jacobi_sweeps;/* sweeps of the last eigensolve                                    */
+  int32_t reserved;
+} rpca_report;
+
+typedef struct rpca_handle rpca_handle;
+
+uot_status rpca_check_params(const rpca_params *prm);
+uot_status rpca_create(const rpca_params *prm, void *hip_stream, rpca_handle **out);
+/* y, phi (may be NULL): device, T frames; S, L (may be NULL): device outputs,
+ * T frames.  Every variable starts at zero.  Synchronous. */
+uot_status rpca_solve(rpca_handle *h, const float *y, const float *phi, float *S, float *L, rpca_report *rep);
+/* Copies the split variables and multipliers after the last solve into
+ * caller-owned device buffers (X, Tn, A, D: T frames; Z, W, B, C: T - 1
+ * frames; any may be NULL).  Synchronous. */
+uot_status rpca_copy_planes(rpca_handle *h, float *X, float *Tn, float *A, float *D, float *Z, float *W, float *B,
+                            float *C);
+void rpca_destroy(rpca_handle *h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,25 @@ class DfReport(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RpParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("frames", ctypes.c_int32),
+                ("balanced", ctypes.c_int32), ("residual_p", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("gam", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("mu", ctypes.c_double), ("rho", ctypes.c_double), ("prox_iters", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+class RpReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("r_primal", ctypes.c_double), ("r_dual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("ms_per_iter", ctypes.c_double),
+                ("jacobi_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lib = None
 
 SIGNATURES = {
@@ -110,6 +129,12 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.POINTER(DfReport)]),
     "uotdf_copy_planes": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "uotdf_destroy": (None, [ctypes.c_void_p]),
+    "rpca_check_params": (ctypes.c_int, [ctypes.POINTER(RpParams)]),
+    "rpca_create": (ctypes.c_int, [ctypes.POINTER(RpParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rpca_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.POINTER(RpReport)]),
+    "rpca_copy_planes": (ctypes.c_int, [ctypes.c_void_p] * 9),
+    "rpca_destroy": (None, [ctypes.c_void_p]),
     "uot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 

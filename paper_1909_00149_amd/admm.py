@@ -68,3 +68,62 @@ class UotDf:
             self.close()
         except Exception:
             pass
+
+
+class Rpca:
+    """One RPCA+UOT-DF handle (Algorithm 3) for T frames of ny x nx pixels."""
+
+    PLANES = ("X", "Tn", "A", "D", "Z", "W", "B", "C")
+
+    def __init__(self, nx, ny, frames, lam, gam, kappa, mu, rho, balanced=False, residual_p=1, bc=0, prox_iters=1,
+                 max_iter=5000, check_every=10, eps=1e-4, flags=0, stream=None):
+        self.lib = _lib.load()
+        self.shape = (int(frames), int(ny), int(nx))
+        self._c = _lib.RpParams(int(nx), int(ny), int(frames), int(balanced), int(residual_p), int(bc), float(lam),
+                                float(gam), float(kappa), float(mu), float(rho), int(prox_iters), int(max_iter),
+                                int(check_every), float(eps), int(flags))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.rpca_create(ctypes.byref(self._c), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise UOTError(rc, "rpca_create")
+        self._h = h
+
+    @staticmethod
+    def check(**kw) -> int:
+        d = dict(nx=4, ny=4, frames=3, balanced=0, residual_p=1, bc=0, lam=0.1, gam=0.1, kappa=1.0, mu=1.0,
+                 rho=1.0, prox_iters=1, max_iter=10, check_every=1, eps=1e-4, flags=0)
+        d.update(kw)
+        c = _lib.RpParams(*[d[k] for k, _ in _lib.RpParams._fields_])
+        return int(_lib.load().rpca_check_params(ctypes.byref(c)))
+
+    def solve(self, y, phi=None):
+        """y (and phi): (T, ny, nx) device tensors; returns (S, L, report)."""
+        S = torch.empty_like(y)
+        L = torch.empty_like(y)
+        rep = _lib.RpReport()
+        rc = self.lib.rpca_solve(self._h, _ptr(y), _ptr(phi), _ptr(S), _ptr(L), ctypes.byref(rep))
+        if rc != 0:
+            raise UOTError(rc, "rpca_solve")
+        return S, L, rep.as_dict()
+
+    def planes(self, device="cuda"):
+        T, ny, nx = self.shape
+        out = {k: torch.empty((T if k in ("X", "Tn", "A", "D") else T - 1, ny, nx), dtype=torch.float32,
+                              device=device) for k in self.PLANES}
+        rc = self.lib.rpca_copy_planes(self._h, *[_ptr(out[k]) for k in self.PLANES])
+        if rc != 0:
+            raise UOTError(rc, "rpca_copy_planes")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.rpca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -83,3 +83,12 @@ def test_knorm2_matches_oracle(mode, bal, bc):
 def test_uotdf_check_params(kw, ok):
     from paper_1909_00149_amd.admm import UotDf
     assert (UotDf.check(**kw) == 0) == ok
+
+
+@pytest.mark.parametrize("kw,ok", [({}, True), (dict(frames=1), False), (dict(frames=65), False),
+                                   (dict(frames=64), True), (dict(kappa=0.0), False), (dict(gam=-1.0), False),
+                                   (dict(lam=0.0, gam=0.0), True), (dict(mu=0.0), False),
+                                   (dict(mu=0.0, balanced=1), True), (dict(prox_iters=0), False)])
+def test_rpca_check_params(kw, ok):
+    from paper_1909_00149_amd.admm import Rpca
+    assert (Rpca.check(**kw) == 0) == ok

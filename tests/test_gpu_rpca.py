@@ -1,0 +1,122 @@
+"""RPCA+UOT-DF ADMM (Algorithm 3) on the GPU against the FP64 oracle: every
+split variable and multiplier iteration by iteration (the singular-value
+threshold through the Gram matrix and the Jacobi eigensolve against the
+oracle's SVD), the converged separation, graph replay against direct
+launches, and the input checks."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm as ora
+from paper_1909_00149_amd import admm as A
+from paper_1909_00149_amd import synth
+from paper_1909_00149_amd import uot as G
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 3e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch.device("cuda:0")
+
+
+def t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+def video(seed, T, ny, nx):
+    rng = np.random.default_rng(seed)
+    S = (rng.uniform(0.5, 1.5, (T, ny, nx)) * (rng.uniform(0, 1, (T, ny, nx)) < 0.08)).astype(np.float32)
+    u = rng.uniform(0, 1, (ny, nx))
+    v = rng.uniform(0, 1, T)
+    L = (v[:, None, None] * u[None] / 4.0).astype(np.float32)
+    Y = (S + L + rng.normal(0, 1e-3, S.shape)).astype(np.float32)
+    return Y
+
+
+def close(g, o, what):
+    g = g.double().cpu().numpy()
+    err = float(np.abs(g - o).max())
+    scale = max(1.0, float(np.abs(o).max()))
+    assert err <= ITER_TOL * scale, f"{what}: max err {err:.3e}"
+
+
+@pytest.mark.parametrize("T,shape", [(2, (9, 14)), (3, (12, 20)), (6, (16, 33)), (7, (8, 70))])
+@pytest.mark.parametrize("prox_iters", [1, 3])
+@pytest.mark.parametrize("variant", ["plain", "balanced", "masked", "p2"])
+def test_iterates_match_oracle(dev, T, shape, prox_iters, variant):
+    """23 ADMM iterations (windows of 5 and a tail of 3), stopping off."""
+    Y = video(T + 10 * prox_iters, T, *shape)
+    kw = dict(lam=0.05, gam=0.3, kappa=0.3, mu=0.8, rho=1.2, balanced=False, residual_p=1)
+    phi = None
+    if variant == "balanced":
+        kw["balanced"] = True
+    elif variant == "masked":
+        rng = np.random.default_rng(5)
+        phi = (rng.uniform(0.3, 1.5, Y.shape) * (rng.uniform(0, 1, Y.shape) > 0.15)).astype(np.float32)
+    elif variant == "p2":
+        kw["residual_p"] = 2
+    iters = 23
+    solver = A.Rpca(shape[1], shape[0], T, prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0, **kw)
+    S, L, rep = solver.solve(t(Y, dev), None if phi is None else t(phi, dev))
+    pl = solver.planes()
+    torch.cuda.synchronize()
+    assert rep["iters"] == iters and rep["converged"] == 0
+    st, rr = ora.rpca_uotdf(Y, phi=phi, prox_iters=prox_iters, max_iter=iters, eps=0.0, check_every=5, **kw)
+    close(S, st.S, "S")
+    close(L, st.L, "L")
+    for k, o in (("X", st.X), ("Tn", st.Tn), ("A", st.A), ("D", st.D), ("Z", st.Z), ("W", st.W), ("B", st.b),
+                 ("C", st.c)):
+        close(pl[k], o, k)
+    assert abs(rep["r_primal"] - rr.r_primal) <= 2e-3 * max(rr.r_primal, 1e-3)
+    assert abs(rep["r_dual"] - rr.r_dual) <= 2e-3 * max(rr.r_dual, 1e-3)
+
+
+def test_converges_like_the_oracle(dev):
+    """The paper's stopping rule at 1e-4 on a small synthetic video: the GPU
+    stops within one check window of the oracle, at the same separation; the
+    warm-started eigensolve then needs at most a few sweeps."""
+    S0, L0, Y = synth.video_frames(2, frames=6, side=16, nblobs=3, rank=1)
+    kw = dict(lam=0.05, gam=0.2, kappa=0.3, mu=1.0, rho=1.0)
+    solver = A.Rpca(16, 16, 6, prox_iters=1, max_iter=5000, check_every=10, eps=1e-4, **kw)
+    S, L, rep = solver.solve(t(Y, dev))
+    torch.cuda.synchronize()
+    st, rr = ora.rpca_uotdf(Y, prox_iters=1, max_iter=5000, eps=1e-4, check_every=10, **kw)
+    assert rep["converged"] == 1 and rr.converged
+    assert abs(rep["iters"] - rr.iters) <= 10
+    np.testing.assert_allclose(S.double().cpu().numpy(), st.S, atol=2e-3)
+    np.testing.assert_allclose(L.double().cpu().numpy(), st.L, atol=2e-3)
+    assert rep["jacobi_sweeps"] <= 4
+
+
+@pytest.mark.parametrize("prox_iters,check_every", [(1, 5), (1, 4), (3, 3)])
+def test_graph_replay_equals_direct_launches(dev, prox_iters, check_every):
+    Y = video(3, 5, 20, 40)
+    out = []
+    for flags in (0, G.UOT_NO_GRAPH):
+        solver = A.Rpca(40, 20, 5, lam=0.05, gam=0.3, kappa=0.3, mu=0.8, rho=1.0, prox_iters=prox_iters,
+                        max_iter=17, check_every=check_every, eps=0.0, flags=flags)
+        S, L, rep = solver.solve(t(Y, dev))
+        pl = solver.planes()
+        torch.cuda.synchronize()
+        out.append((S, L, pl, rep))
+    (S1, L1, p1, r1), (S2, L2, p2, r2) = out
+    assert torch.equal(S1, S2) and torch.equal(L1, L2)
+    for k in p1:
+        assert torch.equal(p1[k], p2[k]), k
+    assert r1["r_primal"] == r2["r_primal"] and r1["r_dual"] == r2["r_dual"]
+
+
+def test_input_checks(dev):
+    Y = video(1, 3, 8, 8)
+    Y[1, 2, 3] = np.inf
+    solver = A.Rpca(8, 8, 3, lam=0.1, gam=0.1, kappa=0.3, mu=0.8, rho=1.0, max_iter=5, check_every=5)
+    with pytest.raises(G.UOTError):
+        solver.solve(t(Y, dev))
+    with pytest.raises(G.UOTError):
+        A.Rpca(8, 8, 1, lam=0.1, gam=0.1, kappa=0.3, mu=0.8, rho=1.0)
+    with pytest.raises(G.UOTError):
+        A.Rpca(8, 8, 65, lam=0.1, gam=0.1, kappa=0.3, mu=0.8, rho=1.0)
