@@ -63,6 +63,9 @@ typedef struct uotdf_params {
   int32_t check_every;  /* ADMM iterations between residual tests, >= 1                       */
   double eps;           /* residual threshold (the paper uses 1e-3); <= 0 runs max_iter         */
   uint32_t flags;       /* UOT_NO_GRAPH: launch directly instead of replaying graphs           */
+  double prox_tau_ratio;/* tau1 / tau2 of the prox passes, the product kept at 0.98 / ||K||^2;
+                           0 = 1 (equal steps).  The paper tunes its steps by search; an
+                           inexact, warm-started prox is sensitive to this ratio              */
 } uotdf_params;
 
 typedef struct uotdf_report {
@@ -134,6 +137,7 @@ typedef struct rpca_params {
   int32_t prox_iters, max_iter, check_every;
   double eps;           /* residual threshold (the paper uses 1e-4); <= 0 runs max_iter      */
   uint32_t flags;       /* UOT_NO_GRAPH                                                      */
+  double prox_tau_ratio;/* tau1 / tau2 of the prox passes (as in uotdf_params); 0 = 1       */
 } rpca_params;
 
 typedef struct rpca_report {

@@ -53,7 +53,8 @@ class DfParams(ctypes.Structure):
                 ("balanced", ctypes.c_int32), ("residual_p", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("kappa", ctypes.c_double), ("mu", ctypes.c_double), ("lam", ctypes.c_double),
                 ("rho", ctypes.c_double), ("prox_iters", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("eps", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("check_every", ctypes.c_int32), ("eps", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("prox_tau_ratio", ctypes.c_double)]
 
 
 class DfReport(ctypes.Structure):
@@ -71,7 +72,7 @@ class RpParams(ctypes.Structure):
                 ("lam", ctypes.c_double), ("gam", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("mu", ctypes.c_double), ("rho", ctypes.c_double), ("prox_iters", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("prox_tau_ratio", ctypes.c_double)]
 
 
 class RpReport(ctypes.Structure):

@@ -19,12 +19,12 @@ class UotDf:
     and stream."""
 
     def __init__(self, nx, ny, kappa, mu, rho, lam=0.0, balanced=False, residual_p=1, bc=0, prox_iters=1,
-                 max_iter=5000, check_every=10, eps=1e-3, flags=0, stream=None):
+                 max_iter=5000, check_every=10, eps=1e-3, flags=0, prox_tau_ratio=0.0, stream=None):
         self.lib = _lib.load()
         self.shape = (int(ny), int(nx))
         self._c = _lib.DfParams(int(nx), int(ny), int(balanced), int(residual_p), int(bc), float(kappa), float(mu),
                                 float(lam), float(rho), int(prox_iters), int(max_iter), int(check_every), float(eps),
-                                int(flags))
+                                int(flags), float(prox_tau_ratio))
         if stream is None:
             stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -37,7 +37,7 @@ class UotDf:
     def check(**kw) -> int:
         """uotdf_check_params on keyword parameters (0 = valid)."""
         d = dict(nx=1, ny=1, balanced=0, residual_p=1, bc=0, kappa=1.0, mu=1.0, lam=0.0, rho=1.0, prox_iters=1,
-                 max_iter=10, check_every=1, eps=1e-3, flags=0)
+                 max_iter=10, check_every=1, eps=1e-3, flags=0, prox_tau_ratio=0.0)
         d.update(kw)
         c = _lib.DfParams(*[d[k] for k, _ in _lib.DfParams._fields_])
         return int(_lib.load().uotdf_check_params(ctypes.byref(c)))
@@ -76,12 +76,12 @@ class Rpca:
     PLANES = ("X", "Tn", "A", "D", "Z", "W", "B", "C")
 
     def __init__(self, nx, ny, frames, lam, gam, kappa, mu, rho, balanced=False, residual_p=1, bc=0, prox_iters=1,
-                 max_iter=5000, check_every=10, eps=1e-4, flags=0, stream=None):
+                 max_iter=5000, check_every=10, eps=1e-4, flags=0, prox_tau_ratio=0.0, stream=None):
         self.lib = _lib.load()
         self.shape = (int(frames), int(ny), int(nx))
         self._c = _lib.RpParams(int(nx), int(ny), int(frames), int(balanced), int(residual_p), int(bc), float(lam),
                                 float(gam), float(kappa), float(mu), float(rho), int(prox_iters), int(max_iter),
-                                int(check_every), float(eps), int(flags))
+                                int(check_every), float(eps), int(flags), float(prox_tau_ratio))
         if stream is None:
             stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -93,7 +93,7 @@ class Rpca:
     @staticmethod
     def check(**kw) -> int:
         d = dict(nx=4, ny=4, frames=3, balanced=0, residual_p=1, bc=0, lam=0.1, gam=0.1, kappa=1.0, mu=1.0,
-                 rho=1.0, prox_iters=1, max_iter=10, check_every=1, eps=1e-4, flags=0)
+                 rho=1.0, prox_iters=1, max_iter=10, check_every=1, eps=1e-4, flags=0, prox_tau_ratio=0.0)
         d.update(kw)
         c = _lib.RpParams(*[d[k] for k, _ in _lib.RpParams._fields_])
         return int(_lib.load().rpca_check_params(ctypes.byref(c)))

@@ -175,6 +175,7 @@ uot_status uotdf_check_params(const uotdf_params* p) {
   if (p->residual_p != 1 && p->residual_p != 2) return UOT_ERR_ARG;
   if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
   if (p->prox_iters < 1 || p->max_iter < 1 || p->check_every < 1) return UOT_ERR_ARG;
+  if (!(p->prox_tau_ratio >= 0.0) || !std::isfinite(p->prox_tau_ratio)) return UOT_ERR_ARG;
   return UOT_OK;
 }
 
@@ -212,6 +213,8 @@ uot_status uotdf_create(const uotdf_params* prm, void* hip_stream, uotdf_handle*
   // the prox as one Algorithm-1 pair: fixed argument s0, step kappa / rho
   const double k2 = uot_knorm2(prm->nx, prm->ny, UOT_PROX_FIXED, prm->balanced, prm->bc);
   const double t = 0.99 / std::sqrt(k2);
+  const double rr = prm->prox_tau_ratio > 0.0 ? std::sqrt(prm->prox_tau_ratio) : 1.0;
+  const double t1 = t * rr, t2 = t / rr;  // tau1 tau2 ||K||^2 = 0.98 whatever the ratio
   const double rho_prox = prm->kappa / prm->rho;
   // kernel shape: one pass per ADMM iteration -> the single-step kernel;
   // several -> the temporally blocked kernel, up to 4 passes per launch
@@ -232,11 +235,11 @@ uot_status uotdf_create(const uotdf_params* prm, void* hip_stream, uotdf_handle*
   P.off = 0;
   P.nx = prm->nx;
   P.ny = prm->ny;
-  P.tau1 = (float)t;
-  P.tau2 = (float)t;
-  P.theta = (float)(t / (rho_prox + t));
-  P.mutau = (float)(prm->mu * t);
-  P.inv2mt = (float)(1.0 / (1.0 + 2.0 * prm->mu * t));
+  P.tau1 = (float)t1;
+  P.tau2 = (float)t2;
+  P.theta = (float)(t1 / (rho_prox + t1));
+  P.mutau = (float)(prm->mu * t1);
+  P.inv2mt = (float)(1.0 / (1.0 + 2.0 * prm->mu * t1));
   P.tile_begin = 0;
   P.tile_count = h->ntiles;
   P.pitch = prm->nx;
@@ -518,6 +521,7 @@ uot_status rpca_check_params(const rpca_params* p) {
   if (p->residual_p != 1 && p->residual_p != 2) return UOT_ERR_ARG;
   if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
   if (p->prox_iters < 1 || p->max_iter < 1 || p->check_every < 1) return UOT_ERR_ARG;
+  if (!(p->prox_tau_ratio >= 0.0) || !std::isfinite(p->prox_tau_ratio)) return UOT_ERR_ARG;
   return UOT_OK;
 }
 
@@ -556,7 +560,7 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
     for (int k = 0; k < RP_NPLANES; ++k)
       if (hipMalloc((void**)&h->st[c][k], pb) != hipSuccess) return fail(UOT_ERR_OOM);
   const int Tf = prm->frames, npairs_g = Tf * (Tf + 1) / 2;
-  h->gblocks = (int)std::min<long>(256, std::max<long>(1, (h->npx + 63) / 64));
+  h->gblocks = (int)std::min<long>(64, std::max<long>(1, (h->npx + 63) / 64));
   if (hipMalloc((void**)&h->d_gpart, (size_t)h->gblocks * npairs_g * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_G, (size_t)npairs_g * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_V, (size_t)Tf * Tf * sizeof(double)) != hipSuccess ||
@@ -567,6 +571,8 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
   // the frame pairs as one batch of Algorithm-1 problems (full prox, step kappa / rho)
   const double k2 = uot_knorm2(prm->nx, prm->ny, UOT_PROX, prm->balanced, prm->bc);
   const double t = 0.99 / std::sqrt(k2);
+  const double rr = prm->prox_tau_ratio > 0.0 ? std::sqrt(prm->prox_tau_ratio) : 1.0;
+  const double t1 = t * rr, t2 = t / rr;
   const double rho_prox = prm->kappa / prm->rho;
   if (prm->prox_iters == 1) {
     h->shape = h->np1 <= (1L << 16) ? 4 : 116;
@@ -584,11 +590,11 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
     P.off = (int64_t)b * h->npx;
     P.nx = prm->nx;
     P.ny = prm->ny;
-    P.tau1 = (float)t;
-    P.tau2 = (float)t;
-    P.theta = (float)(t / (rho_prox + t));
-    P.mutau = (float)(prm->mu * t);
-    P.inv2mt = (float)(1.0 / (1.0 + 2.0 * prm->mu * t));
+    P.tau1 = (float)t1;
+    P.tau2 = (float)t2;
+    P.theta = (float)(t1 / (rho_prox + t1));
+    P.mutau = (float)(prm->mu * t1);
+    P.inv2mt = (float)(1.0 / (1.0 + 2.0 * prm->mu * t1));
     P.tile_begin = (int32_t)tiles.size();
     for (int y = 0; y < prm->ny; y += rows)
       for (int x = 0; x < prm->nx; x += TX) tiles.push_back(Tile{b, x, y, 0});

@@ -151,46 +151,55 @@ __global__ __launch_bounds__(RB) void rp_sx_kernel(RpArgs A) {
 
 // Gram matrix of M = L + D (columns = frames): per-block partial sums of
 // G[p][q] = sum_i M[p][i] M[q][i] for p <= q (packed upper triangle), FP64.
-// A block stages 64 pixels of every frame in LDS, then each thread
-// accumulates its share of the T (T + 1) / 2 entries.
+// A block stages 64 pixels of every frame in LDS; thread (bp, bq) of the
+// 16 x 16 grid of threads owns the 4 x 4 block of entries p in 4bp..4bp+3,
+// q in 4bq..4bq+3 (blocks below the diagonal idle), so 8 LDS reads feed 16
+// FP64 multiply-adds.
 __global__ __launch_bounds__(RB) void rp_gram_kernel(RpArgs A, double* gpart) {
-  constexpr int CH = 64, NE = (RP_MAX_FRAMES * (RP_MAX_FRAMES + 1) / 2 + RB - 1) / RB;
+  constexpr int CH = 64;
+  static_assert(RP_MAX_FRAMES == 64 && RB == 256, "16 x 16 threads of 4 x 4 entries");
   __shared__ float sm[RP_MAX_FRAMES][CH + 1];
-  __shared__ unsigned char pp[RP_MAX_FRAMES * (RP_MAX_FRAMES + 1) / 2], qq[RP_MAX_FRAMES * (RP_MAX_FRAMES + 1) / 2];
   const int T = A.T, np = T * (T + 1) / 2;
   const long npx = A.npx;
-  for (int p = 0, j = 0; p < T; ++p)
-    for (int q = p; q < T; ++q, ++j)
-      if (j % RB == (int)threadIdx.x) {
-        pp[j] = (unsigned char)p;
-        qq[j] = (unsigned char)q;
-      }
-  double acc[NE];
+  const int bp = threadIdx.x >> 4, bq = threadIdx.x & 15;
+  const int p0 = 4 * bp, q0 = 4 * bq;
+  const bool live = p0 < T && q0 < T && p0 <= q0 + 3;
+  double acc[4][4];
 #pragma unroll
-  for (int m = 0; m < NE; ++m) acc[m] = 0.0;
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   for (long c = blockIdx.x; c * CH < npx; c += gridDim.x) {
     __syncthreads();
-    for (int e = threadIdx.x; e < T * CH; e += RB) {
+    for (int e = threadIdx.x; e < RP_MAX_FRAMES * CH; e += RB) {
       const int t = e / CH, i = e - t * CH;
       const long g = c * CH + i;
-      sm[t][i] = g < npx ? A.L[(long)t * npx + g] + A.D[(long)t * npx + g] : 0.f;
+      sm[t][i] = (t < T && g < npx) ? A.L[(long)t * npx + g] + A.D[(long)t * npx + g] : 0.f;
     }
     __syncthreads();
+    if (live) {
+      for (int i = 0; i < CH; ++i) {
+        double a[4], b[4];
 #pragma unroll
-    for (int m = 0; m < NE; ++m) {
-      const int j = threadIdx.x + RB * m;
-      if (j < np) {
-        const int p = pp[j], q = qq[j];
-        double v = 0.0;
-        for (int i = 0; i < CH; ++i) v += (double)sm[p][i] * (double)sm[q][i];
-        acc[m] += v;
+        for (int u = 0; u < 4; ++u) {
+          a[u] = (double)sm[p0 + u][i];
+          b[u] = (double)sm[q0 + u][i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
       }
     }
   }
+  if (live) {
 #pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int j = threadIdx.x + RB * m;
-    if (j < np) gpart[(long)blockIdx.x * np + j] = acc[m];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = p0 + u, q = q0 + v;
+        if (p < T && q < T && p <= q) gpart[(long)blockIdx.x * np + (p * T - p * (p - 1) / 2 + (q - p))] = acc[u][v];
+      }
   }
 }
 
@@ -198,6 +207,7 @@ __global__ __launch_bounds__(RB) void rp_gram_kernel(RpArgs A, double* gpart) {
 __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart, int blocks, int np, double* G) {
   for (int j = blockIdx.x * RB + threadIdx.x; j < np; j += gridDim.x * RB) {
     double v = 0.0;
+#pragma unroll 8
     for (int b = 0; b < blocks; ++b) v += gpart[(long)b * np + j];
     G[j] = v;
   }
@@ -209,8 +219,8 @@ __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart,
 // method with the parallel round-robin ordering (every round rotates T/2
 // disjoint pairs at once), started from the previous call's eigenvectors V:
 // the iteration moves little from one ADMM step to the next, so V^T G V is
-// nearly diagonal and one or two sweeps finish it.  One workgroup; A and V
-// in LDS in FP64.  Writes Wm = V diag(f) V^T (FP32), the new V, and the
+// nearly diagonal and one or two sweeps finish it (often none).  One
+// workgroup; G is staged into LDS, A and V live there in FP64.  Writes Wm = V diag(f) V^T (FP32), the new V, and the
 // number of sweeps.
 __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg, float* Wm,
                                                      int* sweeps) {
@@ -227,7 +237,11 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     const int p = i < j ? i : j, q = i < j ? j : i;
     return G[p * T - p * (p - 1) / 2 + (q - p)];
   };
-  for (int e = tid; e < TT; e += RB) Vm[(e / T) * LD + e % T] = Vg[e];
+  for (int e = tid; e < TT; e += RB) {
+    const int i = e / T, j = e % T;
+    Vm[i * LD + j] = Vg[e];
+    Am[i * LD + j] = g(i, j);
+  }
   __syncthreads();
   // A = V^T G V, in two products through registers
   constexpr int PER = (MT * MT + RB - 1) / RB;
@@ -239,10 +253,11 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     if (e < TT) {
       const int i = e / T, j = e % T;
       double v = 0.0;
-      for (int k = 0; k < T; ++k) v += g(i, k) * Vm[k * LD + j];
+      for (int k = 0; k < T; ++k) v += Am[i * LD + k] * Vm[k * LD + j];
       tmp[m] = v;
     }
   }
+  __syncthreads();
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
     const int e = tid + RB * m;
@@ -292,7 +307,9 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
       tot += red[1][w];
     }
     __syncthreads();
-    if (!(off > 1e-28 * tot)) break;  // uniform: every thread holds the same sums
+    // off-diagonal norm below 1e-10 of the whole: eigenvalues to about 1e-20 relative,
+    // eigenvectors to about 1e-10, far below the FP32 result
+    if (!(off > 1e-20 * tot)) break;  // uniform: every thread holds the same sums
     for (int r = 0; r < Tp - 1; ++r) {
       if (tid < Tp / 2) {
         // round-robin pairing: player Tp - 1 fixed, the others rotate
@@ -363,31 +380,51 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
   if (tid == 0) *sweeps = sweep;
 }
 
-// Tn = (L + D) Wm per pixel (T x T product from LDS), then D += L - Tn.
+// Tn = (L + D) Wm per pixel (T x T product from LDS), then D += L - Tn.  Wm
+// rows are padded to a multiple of 4 with zeros so that every LDS read
+// fetches 4 outputs' weights at once (a broadcast: all lanes read one row).
 __global__ __launch_bounds__(RB) void rp_svt_apply_kernel(RpArgs A) {
-  __shared__ float w[RP_MAX_FRAMES * RP_MAX_FRAMES];
-  const int T = A.T;
-  for (int e = threadIdx.x; e < T * T; e += RB) w[e] = A.Wm[e];
+  constexpr int MP = RP_MAX_FRAMES;
+  __shared__ __attribute__((aligned(16))) float w[RP_MAX_FRAMES * MP];
+  const int T = A.T, TP = (T + 3) & ~3;
+  for (int e = threadIdx.x; e < T * TP; e += RB) {
+    const int s_ = e / TP, t = e - s_ * TP;
+    w[s_ * MP + t] = t < T ? A.Wm[s_ * T + t] : 0.f;
+  }
   __syncthreads();
   double lt2 = 0.0, dt2 = 0.0;
   const long npx = A.npx;
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
     float m[RP_MAX_FRAMES];
 #pragma unroll
-    for (int s = 0; s < RP_MAX_FRAMES; ++s) m[s] = s < T ? A.L[(long)s * npx + i] + A.D[(long)s * npx + i] : 0.f;
-    for (int t = 0; t < T; ++t) {
-      float acc = 0.f;
+    for (int s_ = 0; s_ < RP_MAX_FRAMES; ++s_)
+      m[s_] = s_ < T ? A.L[(long)s_ * npx + i] + A.D[(long)s_ * npx + i] : 0.f;
+    for (int t4 = 0; t4 < TP; t4 += 4) {
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-      for (int s = 0; s < RP_MAX_FRAMES; ++s)
-        if (s < T) acc += m[s] * w[s * T + t];
-      const long e = (long)t * npx + i;
-      const float l = A.L[e], told = A.Tn[e];
-      A.Tn[e] = acc;
-      A.D[e] = A.D[e] + (l - acc);
-      if (A.record) {
-        const float u = l - acc, v = acc - told;
-        lt2 += (double)u * u;
-        dt2 += (double)v * v;
+      for (int s_ = 0; s_ < RP_MAX_FRAMES; ++s_) {
+        if (s_ < T) {
+          const float4 wv = *reinterpret_cast<const float4*>(&w[s_ * MP + t4]);
+          acc.x += m[s_] * wv.x;
+          acc.y += m[s_] * wv.y;
+          acc.z += m[s_] * wv.z;
+          acc.w += m[s_] * wv.w;
+        }
+      }
+      const float av[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t4 + u;
+        if (t >= T) break;
+        const long e = (long)t * npx + i;
+        const float l = A.L[e], told = A.Tn[e];
+        A.Tn[e] = av[u];
+        A.D[e] = A.D[e] + (l - av[u]);
+        if (A.record) {
+          const float d1 = l - av[u], d2 = av[u] - told;
+          lt2 += (double)d1 * d1;
+          dt2 += (double)d2 * d2;
+        }
       }
     }
   }

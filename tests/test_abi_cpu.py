@@ -79,7 +79,9 @@ def test_knorm2_matches_oracle(mode, bal, bc):
                                    (dict(prox_iters=0), False), (dict(check_every=0), False),
                                    (dict(mu=0.0), False), (dict(mu=0.0, balanced=1), True),
                                    (dict(lam=-0.1), False), (dict(residual_p=3), False), (dict(nx=0), False),
-                                   (dict(eps=float("nan")), False)])
+                                   (dict(eps=float("nan")), False), (dict(prox_tau_ratio=0.01), True),
+                                   (dict(prox_tau_ratio=-0.5), False),
+                                   (dict(prox_tau_ratio=float("inf")), False)])
 def test_uotdf_check_params(kw, ok):
     from paper_1909_00149_amd.admm import UotDf
     assert (UotDf.check(**kw) == 0) == ok
@@ -88,7 +90,8 @@ def test_uotdf_check_params(kw, ok):
 @pytest.mark.parametrize("kw,ok", [({}, True), (dict(frames=1), False), (dict(frames=65), False),
                                    (dict(frames=64), True), (dict(kappa=0.0), False), (dict(gam=-1.0), False),
                                    (dict(lam=0.0, gam=0.0), True), (dict(mu=0.0), False),
-                                   (dict(mu=0.0, balanced=1), True), (dict(prox_iters=0), False)])
+                                   (dict(mu=0.0, balanced=1), True), (dict(prox_iters=0), False),
+                                   (dict(prox_tau_ratio=0.01), True), (dict(prox_tau_ratio=-1.0), False)])
 def test_rpca_check_params(kw, ok):
     from paper_1909_00149_amd.admm import Rpca
     assert (Rpca.check(**kw) == 0) == ok

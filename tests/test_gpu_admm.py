@@ -42,11 +42,12 @@ def close(g, o, what):
 
 @pytest.mark.parametrize("shape", [(24, 31), (9, 70), (40, 64)])
 @pytest.mark.parametrize("prox_iters", [1, 3, 6])
-@pytest.mark.parametrize("variant", ["uotdf", "bpdn", "balanced", "masked", "p2"])
+@pytest.mark.parametrize("variant", ["uotdf", "bpdn", "balanced", "masked", "p2", "ratio"])
 def test_iterates_match_oracle(dev, shape, prox_iters, variant):
     """37 ADMM iterations (windows of 5 and a tail of 2) with the stopping
     test off: s, x, z, a, b agree with the oracle's to the iterate
-    tolerance."""
+    tolerance.  "ratio" runs the prox passes with unequal steps
+    tau1 / tau2 = 0.05 (product unchanged)."""
     s0, y = frame(7, shape)
     kw = dict(kappa=0.3, mu=0.8, rho=1.0, lam=0.0, balanced=False, residual_p=1)
     phi = None
@@ -59,13 +60,20 @@ def test_iterates_match_oracle(dev, shape, prox_iters, variant):
         phi = (rng.uniform(0.2, 1.5, shape) * (rng.uniform(0, 1, shape) > 0.2)).astype(np.float32)
     elif variant == "p2":
         kw["residual_p"] = 2
+    ratio, tau = 0.0, None
+    if variant == "ratio":
+        ratio = 0.05
+        tt = ora.df_problem(s0, np.zeros_like(s0), kw["kappa"], kw["mu"], kw["rho"]).default_steps()[0]
+        tau = (tt * np.sqrt(ratio), tt / np.sqrt(ratio))
     iters = 37
-    solver = A.UotDf(shape[1], shape[0], prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0, **kw)
+    solver = A.UotDf(shape[1], shape[0], prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0,
+                     prox_tau_ratio=ratio, **kw)
     s, rep = solver.solve(t(y, dev), t(s0, dev), None if phi is None else t(phi, dev))
     pl = solver.planes()
     torch.cuda.synchronize()
     assert rep["iters"] == iters and rep["converged"] == 0
-    rs, st, rr = ora.uotdf(y, s0, phi=phi, prox_iters=prox_iters, max_iter=iters, eps=0.0, check_every=5, **kw)
+    rs, st, rr = ora.uotdf(y, s0, phi=phi, prox_iters=prox_iters, max_iter=iters, eps=0.0, check_every=5, tau=tau,
+                           **kw)
     close(s, st.s, "s")
     for k in ("x", "z", "a", "b"):
         close(pl[k], getattr(st, k), k)
@@ -145,5 +153,7 @@ def test_input_checks(dev):
     assert A.UotDf.check(kappa=0.0) != 0
     assert A.UotDf.check(rho=-1.0) != 0
     assert A.UotDf.check(prox_iters=0) != 0
+    assert A.UotDf.check(prox_tau_ratio=-0.5) != 0
+    assert A.UotDf.check(prox_tau_ratio=float("inf")) != 0
     assert A.UotDf.check(mu=0.0, balanced=1) == 0
     assert A.UotDf.check() == 0

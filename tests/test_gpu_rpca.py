@@ -46,9 +46,10 @@ def close(g, o, what):
 
 @pytest.mark.parametrize("T,shape", [(2, (9, 14)), (3, (12, 20)), (6, (16, 33)), (7, (8, 70))])
 @pytest.mark.parametrize("prox_iters", [1, 3])
-@pytest.mark.parametrize("variant", ["plain", "balanced", "masked", "p2"])
+@pytest.mark.parametrize("variant", ["plain", "balanced", "masked", "p2", "ratio"])
 def test_iterates_match_oracle(dev, T, shape, prox_iters, variant):
-    """23 ADMM iterations (windows of 5 and a tail of 3), stopping off."""
+    """23 ADMM iterations (windows of 5 and a tail of 3), stopping off;
+    "ratio" runs the prox passes with tau1 / tau2 = 0.02."""
     Y = video(T + 10 * prox_iters, T, *shape)
     kw = dict(lam=0.05, gam=0.3, kappa=0.3, mu=0.8, rho=1.2, balanced=False, residual_p=1)
     phi = None
@@ -59,13 +60,21 @@ def test_iterates_match_oracle(dev, T, shape, prox_iters, variant):
         phi = (rng.uniform(0.3, 1.5, Y.shape) * (rng.uniform(0, 1, Y.shape) > 0.15)).astype(np.float32)
     elif variant == "p2":
         kw["residual_p"] = 2
+    ratio, tau = 0.0, None
+    if variant == "ratio":
+        ratio = 0.02
+        zf = np.zeros(shape)
+        tt = ora.rpca_problem(zf, zf, kw["kappa"], kw["mu"], kw["rho"]).default_steps()[0]
+        tau = (tt * np.sqrt(ratio), tt / np.sqrt(ratio))
     iters = 23
-    solver = A.Rpca(shape[1], shape[0], T, prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0, **kw)
+    solver = A.Rpca(shape[1], shape[0], T, prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0,
+                    prox_tau_ratio=ratio, **kw)
     S, L, rep = solver.solve(t(Y, dev), None if phi is None else t(phi, dev))
     pl = solver.planes()
     torch.cuda.synchronize()
     assert rep["iters"] == iters and rep["converged"] == 0
-    st, rr = ora.rpca_uotdf(Y, phi=phi, prox_iters=prox_iters, max_iter=iters, eps=0.0, check_every=5, **kw)
+    st, rr = ora.rpca_uotdf(Y, phi=phi, prox_iters=prox_iters, max_iter=iters, eps=0.0, check_every=5, tau=tau,
+                            **kw)
     close(S, st.S, "S")
     close(L, st.L, "L")
     for k, o in (("X", st.X), ("Tn", st.Tn), ("A", st.A), ("D", st.D), ("Z", st.Z), ("W", st.W), ("B", st.b),
@@ -120,3 +129,5 @@ def test_input_checks(dev):
         A.Rpca(8, 8, 1, lam=0.1, gam=0.1, kappa=0.3, mu=0.8, rho=1.0)
     with pytest.raises(G.UOTError):
         A.Rpca(8, 8, 65, lam=0.1, gam=0.1, kappa=0.3, mu=0.8, rho=1.0)
+    assert A.Rpca.check(prox_tau_ratio=-1.0) != 0
+    assert A.Rpca.check(prox_tau_ratio=0.01) == 0
