@@ -103,9 +103,9 @@ def measured_traffic(name, shape):
     return int(round((rec[1] * FETCH_SCALE + rec[2] * WRITE_SCALE) * 1024))
 
 
-def kernel_name(mode, balanced, shape):
+def kernel_name(mode, balanced, shape, residual_p=1):
     """Instantiated name of the fused kernel for a tile_rows code."""
-    resid = 0 if balanced else 1
+    resid = 0 if balanced else residual_p
     if shape >= 1000:
         return f"cp_iter_tb_kernel<{mode}, {resid}, 0, {shape % 1000}, {shape // 1000}>"
     if shape >= 100:
@@ -120,6 +120,12 @@ def workload(name):
                          "stop at rel_res<=1e-4 or 2000 iterations",
                     pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
                     adaptive=True)
+    if name == "pair512p2":
+        p, q = synth.unbalanced_pair(0, side=512)
+        return dict(desc="single unbalanced pair 512x512, 20 blobs, Poisson-noised target, mu=8, squared "
+                         "l2 source term (p=2), stop at rel_res<=1e-4 or 2000 iterations",
+                    pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
+                    adaptive=True, residual_p=2)
     if name == "balanced64":
         p, q = synth.balanced_pair(0)
         return dict(desc="single balanced pair 64x64, 3 blobs, exactly 500 iterations",
@@ -154,7 +160,7 @@ def cpu_baseline(W, budget_s=20.0):
     from oracle import uot as ora
     p, q = W["pairs"][0]
     prob = ora.Problem(p.astype(np.float64), q.astype(np.float64), mode=W["mode"],
-                       balanced=W["balanced"], mu=W["mu"], rho=W["rho"])
+                       balanced=W["balanced"], mu=W["mu"], rho=W["rho"], residual_p=W.get("residual_p", 1))
     t1, t2 = prob.default_steps()
     with threadpool_limits(limits=1):
         st = ora.initial_state(prob)
@@ -182,6 +188,10 @@ def main():
     ap.add_argument("--kernel-iters", type=int, default=400)
     ap.add_argument("--warm-pairs", type=int, default=64,
                     help="held-out 256x256 pairs for the warm-vs-cold time to 1e-4 (0: skip)")
+    ap.add_argument("--prox-iters", default=None,
+                    help="rpca: comma-separated prox passes per ADMM iteration to study (default: all)")
+    ap.add_argument("--tau-ratios", default=None,
+                    help="rpca: comma-separated tau1/tau2 of the prox passes (default: 1,0.01)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"this benchmark runs on one GPU only (asked for {args.gpus}); the batched solver "
@@ -231,13 +241,14 @@ def main():
         src, nx, ny, pitch, offs = G.pack_pitched(imgs_p, align=64)
         dst, _, _, _, _ = G.pack_pitched(imgs_q, align=64)
         prm = G.Params(mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"], tol=W["tol"],
-                       max_iter=W["max_iter"], check_every=20, flags=flags)
+                       max_iter=W["max_iter"], check_every=20, flags=flags, residual_p=W.get("residual_p", 1))
         state = G.new_state(W["mode"], W["balanced"], src.numel(), dev)
     else:
         src, dst = imgs_p[0], imgs_q[0]
         ny0, nx0 = src.shape
         prm = G.Params(nx=nx0, ny=ny0, mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"],
-                       tol=W["tol"], max_iter=W["max_iter"], check_every=20, flags=flags)
+                       tol=W["tol"], max_iter=W["max_iter"], check_every=20, flags=flags,
+                       residual_p=W.get("residual_p", 1))
         state = G.new_state(W["mode"], W["balanced"], src.shape, dev)
     solver = G.Solver(prm)
     npx = [int(p.size) for p, _ in pairs]
@@ -283,7 +294,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_vs_algorithmic": round(traffic / alg_bytes, 4) if traffic else None,
-                "kernel": kernel_name(W["mode"], W["balanced"], shape), "tile_rows": shape,
+                "kernel": kernel_name(W["mode"], W["balanced"], shape, W.get("residual_p", 1)), "tile_rows": shape,
                 "iterations_per_launch": T, "bytes_per_pixel_iter": bpp, "pixels_per_launch": px_launch,
                 "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5),
                 "alu": {"achieved": round(flops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -304,7 +315,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "pairs": len(pairs),
                    "pixels": int(sum(npx)), "mode": ["DIST", "PROX", "PROX_FIXED"][W["mode"]],
-                   "balanced": W["balanced"]},
+                   "balanced": W["balanced"], "residual_p": W.get("residual_p", 1)},
         "effective_hbm_frac_step": round(value * bpp / (HBM_PEAK_GBS * 1e9), 4),
         "iters_per_step": [int(r["iters"]) for r in reps][:8],
         "time_to_tol_ms": round(1e3 * secs / args.steps, 3),
@@ -422,10 +433,12 @@ def run_rpca(args, dev):
     S0, L0, Y = synth.video_frames(0)
     T, ny, nx = Y.shape
     ty = torch.from_numpy(Y).to(dev)
+    ks = RPCA_PROX_ITERS if args.prox_iters is None else tuple(int(v) for v in args.prox_iters.split(","))
+    ratios = RPCA_TAU_RATIOS if args.tau_ratios is None else tuple(float(v) for v in args.tau_ratios.split(","))
     rows = []
-    for ratio in RPCA_TAU_RATIOS:
+    for ratio in ratios:
         part = []
-        for k in RPCA_PROX_ITERS:
+        for k in ks:
             solver = A.Rpca(nx, ny, T, prox_iters=k, max_iter=5000, check_every=10, eps=1e-4,
                             prox_tau_ratio=ratio, **RPCA_KW)
             if k == 1 and not rows:
@@ -445,9 +458,10 @@ def run_rpca(args, dev):
             solver.close()
             print(f"# rpca ratio {ratio} prox_iters {k}: {rep['iters']} ADMM iterations, "
                   f"{rep['ms_per_iter']:.3f} ms each", file=sys.stderr, flush=True)
-        b30 = next(r["admm_iters"] for r in part if r["prox_iters"] == 30)
+        b30 = next((r["admm_iters"] for r in part if r["prox_iters"] == 30), None)
         for r in part:
-            r["additional_pct"] = round(100.0 * abs(r["admm_iters"] - b30) / b30, 2)
+            if b30:
+                r["additional_pct"] = round(100.0 * abs(r["admm_iters"] - b30) / b30, 2)
         rows += part
     r1 = rows[0]
     out = {

@@ -25,7 +25,7 @@
  *
  * Readings where the paper is silent or inconsistent:
  *   - the s-step minimises the augmented Lagrangian the paper writes, which
- *     holds both penalty blocks; the printed line keeps only the x-block,
+ *     holds both penalty blocks; the printed update keeps only the x-block,
  *     with which the iteration converges to the transport-free least-squares
  *     point (s = y for Phi = I).  The l1 threshold is lam / (2 rho).
  *   - V_mu is symmetric in its two arguments, so the z-prox of V_mu(z, s0) is
@@ -109,7 +109,7 @@ void uotdf_destroy(uotdf_handle *h);
  *       + kappa sum_{t<T} V_mu(s_t, s_{t+1})
  *
  * by ADMM with the splitting X = S + L, Tn = L, z_t = s_t, w_{t+1} = s_{t+1}
- * (multipliers A, D, b, c); one iteration runs the lines of Algorithm 3:
+ * (multipliers A, D, b, c); one iteration runs the steps of Algorithm 3:
  * the s-step (one-sided l1 shrink of the sigma-weighted average), the L-step,
  * the x-step (diagonal Phi), the singular-value threshold of L + D, the full
  * prox of every frame pair ((kappa/rho) V_mu at (s_t - b_t, s_{t+1} - c_{t+1}),
@@ -120,7 +120,7 @@ void uotdf_destroy(uotdf_handle *h);
  *
  * Readings: the x-step carries rho on (s + l - a) and the A-step subtracts L
  * (both as the augmented Lagrangian the paper writes gives them; the printed
- * lines differ).  The singular-value threshold goes through the T x T Gram
+ * updates differ).  The singular-value threshold goes through the T x T Gram
  * matrix of L + D, whose eigenvectors a parallel Jacobi method finds,
  * started from the previous iteration's.
  *

@@ -23,7 +23,7 @@ Stopping (the paper's, after Boyd et al. Sec. 3.3.1): both
 
 Readings:
   - The s-step minimises the augmented Lagrangian the paper writes down,
-    which holds both penalty terms in s.  The printed line keeps only the
+    which holds both penalty terms in s.  The printed update keeps only the
     x-block, max(x + a - ., 0); with it the z-block never feeds back into s
     and the iteration settles at the transport-free least-squares point
     (s = y for Phi = I), which the single-pixel closed form rules out.  The
@@ -162,8 +162,8 @@ def uotdf_objective(y, s, s0, kappa, mu, phi=None, lam=0.0, balanced=False):
 # Readings:
 #   - S >= 0 makes the s-step the one-sided shrink max(k/sig - lam/(rho sig), 0).
 #   - x-step: the augmented Lagrangian's block rho/2 ||X - S - L + A||^2 gives
-#     Phi^T y + rho (s + l - a); the printed line omits rho on the second term.
-#   - A-step: the same block gives A += X - S - L; the printed line has + L.
+#     Phi^T y + rho (s + l - a); the printed update omits rho on the second term.
+#   - A-step: the same block gives A += X - S - L; the printed update has + L.
 #   - The prox of each frame pair is the full prox (eq. Prox_UOT) with both
 #     arguments free and prox step kappa / rho, warm-started per pair.
 #   - Residuals (the paper cites Boyd et al. Sec. 3.3 and, for Algorithm 2,

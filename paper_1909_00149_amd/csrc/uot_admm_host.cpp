@@ -346,12 +346,12 @@ void uotdf_destroy(uotdf_handle* h) { delete h; }
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// RPCA+UOT-DF (Sec. IV-B, Algorithm 3).  One ADMM iteration: rp_sx (lines
-// 5-9 and the prox centres), the singular-value threshold of L + D (Gram
+// RPCA+UOT-DF (Sec. IV-B, Algorithm 3).  One ADMM iteration: rp_sx (the s-,
+// L- and x-steps and the prox centres), the singular-value threshold of L + D (Gram
 // matrix, its reduction, the warm-started Jacobi eigensolve, the apply with
 // the D step), the prox passes of the T - 1 frame pairs (the fused
 // Algorithm-1 kernel in the full-prox mode over a batch of pairs), and
-// rp_dual (lines 12-15).  Windows, graphs and the two prox-state copies as
+// rp_dual (the multiplier steps).  Windows, graphs and the two prox-state copies as
 // for UOT-DF.
 
 namespace {
@@ -380,7 +380,10 @@ struct rpca_handle {
   double* d_partial = nullptr;
   double* d_sums = nullptr;
   double* h_sums = nullptr;
-  int nblocks = 1;
+  int bx = 1;       // pixel blocks per frame of the (bx, T) grids of rp_sx and rp_dual
+  int sblocks = 1;  // blocks of the svt apply (64 pixels each per pass)
+  int vblocks = 1;  // blocks of the input check
+  int pstride = 1;  // partials per residual slot
   int parity = 0;
   GraphSlot graphs[2];
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -439,17 +442,18 @@ RpArgs rp_args(rpca_handle* h, const float* y, const float* phi, bool record) {
   a.record = record ? 1 : 0;
   a.partial = h->d_partial;
   a.Wm = h->d_Wm;
+  a.pstride = h->pstride;
   return a;
 }
 
 uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, bool record) {
   const rpca_params& P = h->prm;
   RpArgs a = rp_args(h, y, phi, record);
-  DFCHK(launch_rp_sx(a, h->nblocks, h->stream));
+  DFCHK(launch_rp_sx(a, h->bx, h->stream));
   DFCHK(launch_rp_gram(a, h->gblocks, h->d_gpart, h->stream));
   DFCHK(launch_rp_gram_reduce(h->d_gpart, h->gblocks, P.frames, h->d_G, h->stream));
   DFCHK(launch_rp_eig(h->d_G, P.frames, P.gam / P.rho, h->d_V, h->d_Wm, h->d_sweeps, h->stream));
-  DFCHK(launch_rp_svt_apply(a, h->nblocks, h->stream));
+  DFCHK(launch_rp_svt_apply(a, h->sblocks, h->stream));
   for (int left = P.prox_iters; left > 0;) {
     const int k = std::min(h->T, left);
     IterArgs it{rp_planes(h, h->parity), rp_planes(h, h->parity ^ 1), nullptr, h->P0, h->P1, h->d_pairs,
@@ -460,8 +464,15 @@ uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, bool r
   }
   a.Z = h->st[h->parity][4];
   a.W = h->st[h->parity][5];
-  DFCHK(launch_rp_dual(a, h->nblocks, h->stream));
+  DFCHK(launch_rp_dual(a, h->bx, h->stream));
   return UOT_OK;
+}
+
+// partials per residual slot after a recorded iteration (slots 0 and 4:
+// rp_dual, 1: rp_sx, 2 and 3: the svt apply)
+RpCounts rp_counts(const rpca_handle* h) {
+  const int f = h->bx * h->prm.frames;
+  return RpCounts{{f, f, h->sblocks, h->sblocks, f}};
 }
 
 uot_status rp_window(rpca_handle* h, int W, const float* y, const float* phi) {
@@ -469,7 +480,7 @@ uot_status rp_window(rpca_handle* h, int W, const float* y, const float* phi) {
     uot_status s = rp_iteration(h, y, phi, i == W - 1);
     if (s != UOT_OK) return s;
   }
-  DFCHK(launch_rp_reduce(h->d_partial, h->nblocks, h->d_sums, h->stream));
+  DFCHK(launch_rp_reduce(h->d_partial, h->pstride, rp_counts(h), h->d_sums, h->stream));
   DFCHK(hipMemcpyAsync(h->h_sums, h->d_sums, RP_SLOTS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   return UOT_OK;
 }
@@ -560,7 +571,7 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
     for (int k = 0; k < RP_NPLANES; ++k)
       if (hipMalloc((void**)&h->st[c][k], pb) != hipSuccess) return fail(UOT_ERR_OOM);
   const int Tf = prm->frames, npairs_g = Tf * (Tf + 1) / 2;
-  h->gblocks = (int)std::min<long>(64, std::max<long>(1, (h->npx + 63) / 64));
+  h->gblocks = (int)std::min<long>(h->num_cu, std::max<long>(1, (h->npx + 63) / 64));
   if (hipMalloc((void**)&h->d_gpart, (size_t)h->gblocks * npairs_g * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_G, (size_t)npairs_g * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_V, (size_t)Tf * Tf * sizeof(double)) != hipSuccess ||
@@ -617,8 +628,11 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
   if (iter_occupancy(UOT_PROX, h->resid, prm->bc, h->shape, &occ) != hipSuccess || occ <= 0) occ = 2;
   long g = std::min<long>(h->ntiles, (long)h->num_cu * occ);
   h->grid = (int)std::max<long>(8, (g + 7) / 8 * 8);
-  h->nblocks = df_blocks(h->n);
-  if (hipMalloc((void**)&h->d_partial, RP_SLOTS * (size_t)h->nblocks * sizeof(double)) != hipSuccess ||
+  h->bx = (int)std::min<long>((h->npx + 255) / 256, std::max(1, 2048 / Tf));
+  h->sblocks = (int)std::min<long>(1024, (h->npx + 63) / 64);
+  h->vblocks = df_blocks(h->n);
+  h->pstride = std::max(std::max(h->bx * Tf, h->sblocks), h->vblocks);
+  if (hipMalloc((void**)&h->d_partial, RP_SLOTS * (size_t)h->pstride * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_sums, RP_SLOTS * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&h->h_sums, RP_SLOTS * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(UOT_ERR_OOM);
@@ -634,8 +648,8 @@ uot_status rpca_solve(rpca_handle* h, const float* y, const float* phi, float* S
   const rpca_params& P = h->prm;
   std::memset(rep, 0, sizeof(*rep));
   if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
-  DFCHK(launch_rp_validate(h->n, y, phi, h->d_partial, h->nblocks, h->stream));
-  DFCHK(launch_rp_reduce(h->d_partial, h->nblocks, h->d_sums, h->stream));
+  DFCHK(launch_rp_validate(h->n, y, phi, h->d_partial, h->vblocks, h->stream));
+  DFCHK(launch_rp_reduce(h->d_partial, h->pstride, RpCounts{{h->vblocks, 0, 0, 0, 0}}, h->d_sums, h->stream));
   DFCHK(hipMemcpyAsync(h->h_sums, h->d_sums, RP_SLOTS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   DFCHK(hipStreamSynchronize(h->stream));
   if (h->h_sums[0] > 0.0) return UOT_ERR_NONFINITE;

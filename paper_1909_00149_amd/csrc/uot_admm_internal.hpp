@@ -38,19 +38,25 @@ struct RpArgs {
   const float *Z, *W;          // the prox state's free arguments x0 (z_t), x1 (w_{t+1})
   float rho, lam;
   int record;
-  double* partial;             // [blocks][RP_SLOTS]: 0 ||X-S-L||^2+||z-s||^2+||w-s||^2, 1 ||dX||^2,
+  double* partial;             // [RP_SLOTS][pstride]: 0 ||X-S-L||^2+||z-s||^2+||w-s||^2, 1 ||dX||^2,
                                // 2 ||L-Tn||^2, 3 ||dTn||^2, 4 ||dz||^2+||dw||^2
   const float* Wm;             // T x T matrix of the singular-value threshold (svt apply)
+  int pstride;                 // partial slot j of block b at partial[j * pstride + b]
+};
+
+// Number of partials each residual slot holds after a recorded iteration.
+struct RpCounts {
+  int n[RP_SLOTS];
 };
 
 int df_blocks(long n);
-hipError_t launch_rp_sx(const RpArgs& a, int blocks, hipStream_t s);
+hipError_t launch_rp_sx(const RpArgs& a, int bx, hipStream_t s);  // grid bx x T
 hipError_t launch_rp_gram(const RpArgs& a, int blocks, double* gpart, hipStream_t s);
 hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double* G, hipStream_t s);
 hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, float* Wm, int* sweeps, hipStream_t s);
 hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s);
-hipError_t launch_rp_dual(const RpArgs& a, int blocks, hipStream_t s);
-hipError_t launch_rp_reduce(const double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s);  // grid bx x T
+hipError_t launch_rp_reduce(const double* partial, int pstride, const RpCounts& cnt, double* out, hipStream_t s);
 hipError_t launch_rp_validate(long n, const float* y, const float* phi, double* partial, int blocks, hipStream_t s);
 hipError_t launch_df_sx(const DfArgs& a, hipStream_t s);
 hipError_t launch_df_ab(const DfArgs& a, hipStream_t s);

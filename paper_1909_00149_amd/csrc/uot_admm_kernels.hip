@@ -99,31 +99,40 @@ __global__ __launch_bounds__(RB) void df_validate_kernel(long n, const float* y,
 
 // ---------------------------------------------------------------------------
 // RPCA+UOT-DF (Sec. IV-B, Algorithm 3).  Frames are packed back to back; e
-// indexes pixel i of frame t as t * npx + i.  wz_t = 1 for t < T - 1 and
-// ww_t = 1 for t > 0 (0-based); pair t couples frames t and t + 1.
+// indexes pixel i of frame t as t * npx + i.  Pair t couples frames t and
+// t + 1; its planes (b, c, prox centres, z, w) are packed the same way.
+// The frame-wise kernels run on a (pixel blocks, frames) grid, so the frame
+// comes from blockIdx.y and no index is divided.  Residual partials go to
+// partial[slot * pstride + block] (one block id per launch block).
 
-// Lines 5-9 of Algorithm 3 and the prox centres, per pixel and frame:
-//   k = (x - l + a) + wz (z_t + b_t) + ww (w_t + c_t),  sig = 1 + wz + ww
+// The s-, L- and x-steps and the prox centres, per pixel of frame t:
+//   k = (x - l + a) + wz (z_t + b_t) + ww (w_{t-1} + c_{t-1}),  sig = 1 + wz + ww
 //   s = max(k / sig - lam / (rho sig), 0)
 //   l = max((Tn - D + x - s + a) / 2, 0)
 //   x = (phi y + rho (s + l - a)) / (phi^2 + rho)
-//   p0_t = s_t - b_t,  p1_{t-1} = s_t - c_{t-1}; z, w saved for the residual
+//   p0_t = s_t - b_t,  p1_{t-1} = s_t - c_{t-1}
+// with wz = 1 unless t is the last frame and ww = 1 unless t is the first.
+// z and w are saved (zo, wo) only where the residual is recorded.
 __global__ __launch_bounds__(RB) void rp_sx_kernel(RpArgs A) {
   double dx2 = 0.0;
-  const long npx = A.npx, n = npx * A.T;
+  const int t = blockIdx.y;
+  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx;
+  const bool hz = t < A.T - 1, hw = t > 0;
   const float rho = A.rho, lam = A.lam;
-  for (long e = blockIdx.x * (long)RB + threadIdx.x; e < n; e += (long)gridDim.x * RB) {
-    const int t = (int)(e / npx);
-    const long i = e - (long)t * npx;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
+    const long e = fe + i;
     const float x = A.X[e], l = A.L[e], a = A.A[e];
-    float k = x - l + a, sig = 1.f;
-    const long pe = (long)t * npx + i, pw = (long)(t - 1) * npx + i;
-    if (t < A.T - 1) {
-      k += A.Z[pe] + A.B[pe];
+    float k = x - l + a, sig = 1.f, z = 0.f, w = 0.f, bz = 0.f, cw = 0.f;
+    if (hz) {
+      z = A.Z[e];
+      bz = A.B[e];
+      k += z + bz;
       sig += 1.f;
     }
-    if (t > 0) {
-      k += A.W[pw] + A.C[pw];
+    if (hw) {
+      w = A.W[fw + i];
+      cw = A.C[fw + i];
+      k += w + cw;
       sig += 1.f;
     }
     const float s = fmaxf(k / sig - lam / (rho * sig), 0.f);
@@ -133,62 +142,75 @@ __global__ __launch_bounds__(RB) void rp_sx_kernel(RpArgs A) {
     A.S[e] = s;
     A.L[e] = ln;
     A.X[e] = xn;
+    if (hz) A.P0[e] = s - bz;
+    if (hw) A.P1[fw + i] = s - cw;
     if (A.record) {
       const float d = xn - x;
       dx2 += (double)d * d;
-    }
-    if (t < A.T - 1) {
-      A.P0[pe] = s - A.B[pe];
-      A.zo[pe] = A.Z[pe];
-    }
-    if (t > 0) {
-      A.P1[pw] = s - A.C[pw];
-      A.wo[pw] = A.W[pw];
+      if (hz) A.zo[e] = z;
+      if (hw) A.wo[fw + i] = w;
     }
   }
-  if (A.record) block_sum(dx2, A.partial + RP_SLOTS * blockIdx.x + 1);
+  if (A.record) block_sum(dx2, A.partial + 1 * A.pstride + blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Gram matrix of M = L + D (columns = frames): per-block partial sums of
 // G[p][q] = sum_i M[p][i] M[q][i] for p <= q (packed upper triangle), FP64.
-// A block stages 64 pixels of every frame in LDS; thread (bp, bq) of the
-// 16 x 16 grid of threads owns the 4 x 4 block of entries p in 4bp..4bp+3,
-// q in 4bq..4bq+3 (blocks below the diagonal idle), so 8 LDS reads feed 16
-// FP64 multiply-adds.
+// A block stages 64 pixels of every frame in LDS (converted to FP64 once);
+// its threads own the 4 x 4 tiles on and above the diagonal (136 tiles for
+// T = 64, numbered row by row), so 8 LDS reads of two doubles feed 32 FP64
+// multiply-adds.  The next chunk's loads are in flight while a chunk is
+// multiplied.
 __global__ __launch_bounds__(RB) void rp_gram_kernel(RpArgs A, double* gpart) {
-  constexpr int CH = 64;
-  static_assert(RP_MAX_FRAMES == 64 && RB == 256, "16 x 16 threads of 4 x 4 entries");
-  __shared__ float sm[RP_MAX_FRAMES][CH + 1];
-  const int T = A.T, np = T * (T + 1) / 2;
+  constexpr int CH = 64, LDC = CH + 2, PER = RP_MAX_FRAMES * CH / RB;
+  static_assert(RP_MAX_FRAMES == 64 && RB == 256, "64 frames x 64 pixels staged by 256 threads");
+  __shared__ __attribute__((aligned(16))) double sm[RP_MAX_FRAMES * LDC];
+  const int T = A.T, nb = (T + 3) >> 2, np = T * (T + 1) / 2;
   const long npx = A.npx;
-  const int bp = threadIdx.x >> 4, bq = threadIdx.x & 15;
-  const int p0 = 4 * bp, q0 = 4 * bq;
-  const bool live = p0 < T && q0 < T && p0 <= q0 + 3;
+  int bp = 0, rem = threadIdx.x;
+  while (bp < nb && rem >= nb - bp) {
+    rem -= nb - bp;
+    ++bp;
+  }
+  const bool live = bp < nb;
+  const int p0 = 4 * bp, q0 = 4 * (bp + rem);
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (long c = blockIdx.x; c * CH < npx; c += gridDim.x) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < RP_MAX_FRAMES * CH; e += RB) {
-      const int t = e / CH, i = e - t * CH;
+  float pf[PER];
+  auto fetch = [&](long c) {
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = threadIdx.x + RB * m, t = e >> 6, i = e & (CH - 1);
       const long g = c * CH + i;
-      sm[t][i] = (t < T && g < npx) ? A.L[(long)t * npx + g] + A.D[(long)t * npx + g] : 0.f;
+      pf[m] = (t < T && g < npx) ? A.L[(long)t * npx + g] + A.D[(long)t * npx + g] : 0.f;
+    }
+  };
+  long c = blockIdx.x;
+  if (c * CH < npx) fetch(c);
+  for (; c * CH < npx; c += gridDim.x) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = threadIdx.x + RB * m;
+      sm[(e >> 6) * LDC + (e & (CH - 1))] = (double)pf[m];
     }
     __syncthreads();
+    if ((c + gridDim.x) * CH < npx) fetch(c + gridDim.x);
     if (live) {
-      for (int i = 0; i < CH; ++i) {
-        double a[4], b[4];
+      for (int i = 0; i < CH; i += 2) {
+        double2 a[4], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          a[u] = (double)sm[p0 + u][i];
-          b[u] = (double)sm[q0 + u][i];
+          a[u] = *reinterpret_cast<const double2*>(&sm[(p0 + u) * LDC + i]);
+          b[u] = *reinterpret_cast<const double2*>(&sm[(q0 + u) * LDC + i]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u].y, b[v].y, fma(a[u].x, b[v].x, acc[u][v]));
       }
     }
   }
@@ -203,91 +225,115 @@ __global__ __launch_bounds__(RB) void rp_gram_kernel(RpArgs A, double* gpart) {
   }
 }
 
-// G[j] = sum over blocks of gpart[b][j], in block order.
+// G[j] = sum over blocks of gpart[b][j]: a block adds 64 entries, its four
+// waves take every fourth partial, and the four sums are combined in a
+// fixed order (the result does not depend on timing).
 __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart, int blocks, int np, double* G) {
-  for (int j = blockIdx.x * RB + threadIdx.x; j < np; j += gridDim.x * RB) {
-    double v = 0.0;
-#pragma unroll 8
-    for (int b = 0; b < blocks; ++b) v += gpart[(long)b * np + j];
-    G[j] = v;
-  }
+  __shared__ double red[RB / 64][64];
+  const int jl = threadIdx.x & 63, q = threadIdx.x >> 6, j = blockIdx.x * 64 + jl;
+  double v = 0.0;
+  if (j < np)
+    for (int b = q; b < blocks; b += RB / 64) v += gpart[(long)b * np + j];
+  red[q][jl] = v;
+  __syncthreads();
+  if (q == 0 && j < np) G[j] = (red[0][jl] + red[1][jl]) + (red[2][jl] + red[3][jl]);
 }
 
 // Singular-value threshold of M from its Gram matrix G = M^T M = V Lam V^T:
 // SVT_thr(M) = M V diag(f) V^T with f_j = max(1 - thr / sigma_j, 0),
 // sigma_j = sqrt(lam_j).  The eigenvectors come from the cyclic Jacobi
-// method with the parallel round-robin ordering (every round rotates T/2
+// method with the parallel round-robin ordering (every round rotates 32
 // disjoint pairs at once), started from the previous call's eigenvectors V:
 // the iteration moves little from one ADMM step to the next, so V^T G V is
-// nearly diagonal and one or two sweeps finish it (often none).  One
-// workgroup; G is staged into LDS, A and V live there in FP64.  Writes Wm = V diag(f) V^T (FP32), the new V, and the
-// number of sweeps.
+// nearly diagonal and one sweep usually finishes it.  One workgroup; the
+// matrix is padded to 64 x 64 (zero rows and columns of A, identity in V,
+// which no rotation touches since their off-diagonal entries stay zero), so
+// all index arithmetic is shifts.  A and V live in LDS in FP64.  A round:
+// 32 threads form the rotations; then every 2 x 2 block (pair k1 rows, pair
+// k2 columns) of A becomes R_k1^T A R_k2 and the two columns of V of every
+// pair rotate, each block and column pair owned by one thread (no
+// conflicting writes), diagonal blocks taking the exact diagonalisation.
+// The products V^T G V and V diag(f) V^T keep a 4 x 4 block per thread.
+// Writes Wm = V diag(f) V^T (FP32, T x T), the new V, and the number of
+// sweeps.
 __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg, float* Wm,
                                                      int* sweeps) {
-  constexpr int MT = RP_MAX_FRAMES, LD = MT + 1;
-  __shared__ double Am[MT * LD];
-  __shared__ double Vm[MT * LD];
-  __shared__ double cs[MT / 2][2];
-  __shared__ int pq[MT / 2][2];
-  __shared__ double fj[MT];
+  constexpr int N = RP_MAX_FRAMES, LD = N + 1, NP = N / 2;
+  static_assert(N == 64 && RB == 256, "64 x 64 matrices, 16 x 16 threads of 4 x 4 blocks");
+  __shared__ double Am[N * LD];
+  __shared__ double Vm[N * LD];
+  __shared__ double rot[NP][3];  // c, s, t = s / c
+  __shared__ int pq[NP][2];
+  __shared__ double fj[N];
   __shared__ double red[2][RB / 64];
   const int tid = threadIdx.x;
-  const int TT = T * T;
-  auto g = [&](int i, int j) {
-    const int p = i < j ? i : j, q = i < j ? j : i;
-    return G[p * T - p * (p - 1) / 2 + (q - p)];
-  };
-  for (int e = tid; e < TT; e += RB) {
-    const int i = e / T, j = e % T;
-    Vm[i * LD + j] = Vg[e];
-    Am[i * LD + j] = g(i, j);
-  }
-  __syncthreads();
-  // A = V^T G V, in two products through registers
-  constexpr int PER = (MT * MT + RB - 1) / RB;
-  double tmp[PER];
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = tid + RB * m;
-    tmp[m] = 0.0;
-    if (e < TT) {
-      const int i = e / T, j = e % T;
-      double v = 0.0;
-      for (int k = 0; k < T; ++k) v += Am[i * LD + k] * Vm[k * LD + j];
-      tmp[m] = v;
+  for (int e = tid; e < N * N; e += RB) {
+    const int i = e >> 6, j = e & (N - 1);
+    double gv = 0.0, vv = i == j ? 1.0 : 0.0;
+    if (i < T && j < T) {
+      const int p = i < j ? i : j, q = i < j ? j : i;
+      gv = G[p * T - p * (p - 1) / 2 + (q - p)];
+      vv = Vg[i * T + j];
     }
+    Am[i * LD + j] = gv;
+    Vm[i * LD + j] = vv;
   }
   __syncthreads();
+  const int bi = tid >> 4, bj = tid & 15;
+  double acc[4][4];
+  // Am <- G V
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = tid + RB * m;
-    if (e < TT) Am[(e / T) * LD + e % T] = tmp[m];
-  }
-  __syncthreads();
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = tid + RB * m;
-    if (e < TT) {
-      const int i = e / T, j = e % T;
-      double v = 0.0;
-      for (int k = 0; k < T; ++k) v += Vm[k * LD + i] * Am[k * LD + j];
-      tmp[m] = v;
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k = 0; k < N; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Am[(4 * bi + u) * LD + k];
+      b[u] = Vm[k * LD + 4 * bj + u];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = tid + RB * m;
-    if (e < TT) Am[(e / T) * LD + e % T] = tmp[m];
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
+  __syncthreads();
+  // Am <- V^T Am
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k = 0; k < N; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Vm[k * LD + 4 * bi + u];
+      b[u] = Am[k * LD + 4 * bj + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
   }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
   __syncthreads();
 
-  const int Tp = T + (T & 1);  // even; index T is a dummy when T is odd
+  const int k2 = tid & (NP - 1), r1 = tid >> 5;  // this thread's column pair; first row pair / V row
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < TT; e += RB) {
-      const int i = e / T, j = e % T;
+    for (int e = tid; e < N * N; e += RB) {
+      const int i = e >> 6, j = e & (N - 1);
       const double v = Am[i * LD + j];
       tot += v * v;
       if (i != j) off += v * v;
@@ -307,158 +353,190 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
       tot += red[1][w];
     }
     __syncthreads();
-    // off-diagonal norm below 1e-10 of the whole: eigenvalues to about 1e-20 relative,
-    // eigenvectors to about 1e-10, far below the FP32 result
+    // off-diagonal norm below 1e-10 of the whole: eigenvalues to about 1e-20
+    // relative, eigenvectors to about 1e-10, far below the FP32 result
     if (!(off > 1e-20 * tot)) break;  // uniform: every thread holds the same sums
-    for (int r = 0; r < Tp - 1; ++r) {
-      if (tid < Tp / 2) {
-        // round-robin pairing: player Tp - 1 fixed, the others rotate
-        int p, q;
-        if (tid == 0) {
-          p = r;
-          q = Tp - 1;
-        } else {
-          p = (r + tid) % (Tp - 1);
-          q = (r - tid + (Tp - 1)) % (Tp - 1);
-        }
+    for (int r = 0; r < N - 1; ++r) {
+      if (tid < NP) {
+        // round-robin pairing: player N - 1 fixed, the others rotate
+        int p = tid == 0 ? r : (r + tid) % (N - 1);
+        int q = tid == 0 ? N - 1 : (r - tid + (N - 1)) % (N - 1);
         if (p > q) {
           const int u = p;
           p = q;
           q = u;
         }
-        double c = 1.0, s = 0.0;
-        if (q < T) {
-          const double apq = Am[p * LD + q];
-          if (apq != 0.0) {
-            const double tau = (Am[q * LD + q] - Am[p * LD + p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
+        double c = 1.0, s = 0.0, t = 0.0;
+        const double apq = Am[p * LD + q];
+        if (apq != 0.0) {
+          const double tau = (Am[q * LD + q] - Am[p * LD + p]) / (2.0 * apq);
+          t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
         }
-        cs[tid][0] = c;
-        cs[tid][1] = s;
+        rot[tid][0] = c;
+        rot[tid][1] = s;
+        rot[tid][2] = t;
         pq[tid][0] = p;
         pq[tid][1] = q;
       }
       __syncthreads();
-      for (int e = tid; e < (Tp / 2) * T; e += RB) {  // rows p, q of A
-        const int k = e / T, j = e % T, p = pq[k][0], q = pq[k][1];
-        if (q >= T) continue;
-        const double c = cs[k][0], s = cs[k][1];
-        const double a = Am[p * LD + j], b = Am[q * LD + j];
-        Am[p * LD + j] = c * a - s * b;
-        Am[q * LD + j] = s * a + c * b;
+      const int p2 = pq[k2][0], q2 = pq[k2][1];
+      const double c2 = rot[k2][0], s2 = rot[k2][1];
+#pragma unroll
+      for (int m = 0; m < NP / 8; ++m) {
+        const int k1 = r1 + 8 * m;
+        const int p1 = pq[k1][0], q1 = pq[k1][1];
+        const double a = Am[p1 * LD + p2], b = Am[p1 * LD + q2], cc = Am[q1 * LD + p2], d = Am[q1 * LD + q2];
+        if (k1 == k2) {
+          const double t1 = rot[k1][2];
+          Am[p1 * LD + p1] = a - t1 * b;
+          Am[q1 * LD + q1] = d + t1 * b;
+          Am[p1 * LD + q1] = 0.0;
+          Am[q1 * LD + p1] = 0.0;
+        } else {
+          const double c1 = rot[k1][0], s1 = rot[k1][1];
+          const double rpp = c1 * a - s1 * cc, rpq = c1 * b - s1 * d;
+          const double rqp = s1 * a + c1 * cc, rqq = s1 * b + c1 * d;
+          Am[p1 * LD + p2] = c2 * rpp - s2 * rpq;
+          Am[p1 * LD + q2] = s2 * rpp + c2 * rpq;
+          Am[q1 * LD + p2] = c2 * rqp - s2 * rqq;
+          Am[q1 * LD + q2] = s2 * rqp + c2 * rqq;
+        }
       }
-      __syncthreads();
-      for (int e = tid; e < (Tp / 2) * T; e += RB) {  // columns p, q of A and V
-        const int k = e / T, i = e % T, p = pq[k][0], q = pq[k][1];
-        if (q >= T) continue;
-        const double c = cs[k][0], s = cs[k][1];
-        const double a = Am[i * LD + p], b = Am[i * LD + q];
-        Am[i * LD + p] = c * a - s * b;
-        Am[i * LD + q] = s * a + c * b;
-        const double va = Vm[i * LD + p], vb = Vm[i * LD + q];
-        Vm[i * LD + p] = c * va - s * vb;
-        Vm[i * LD + q] = s * va + c * vb;
+#pragma unroll
+      for (int m = 0; m < N / 8; ++m) {
+        const int i = r1 + 8 * m;
+        const double va = Vm[i * LD + p2], vb = Vm[i * LD + q2];
+        Vm[i * LD + p2] = c2 * va - s2 * vb;
+        Vm[i * LD + q2] = s2 * va + c2 * vb;
       }
       __syncthreads();
     }
   }
-  for (int j = tid; j < T; j += RB) {
-    const double sig = sqrt(fmax(Am[j * LD + j], 0.0));
-    fj[j] = sig > thr ? 1.0 - thr / sig : 0.0;
+  if (tid < N) {
+    const double sig = sqrt(fmax(Am[tid * LD + tid], 0.0));
+    fj[tid] = sig > thr ? 1.0 - thr / sig : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < TT; e += RB) {
-    const int i = e / T, j = e % T;
-    double v = 0.0;
-    for (int k = 0; k < T; ++k) v += Vm[i * LD + k] * fj[k] * Vm[j * LD + k];
-    Wm[e] = (float)v;
-    Vg[e] = Vm[i * LD + j];
+  // Wm = V diag(f) V^T
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double f = fj[k];
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Vm[(4 * bi + u) * LD + k] * f;
+      b[u] = Vm[(4 * bj + u) * LD + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
   }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * bi + u, j = 4 * bj + v;
+      if (i < T && j < T) {
+        Wm[i * T + j] = (float)acc[u][v];
+        Vg[i * T + j] = Vm[i * LD + j];
+      }
+    }
   if (tid == 0) *sweeps = sweep;
 }
 
-// Tn = (L + D) Wm per pixel (T x T product from LDS), then D += L - Tn.  Wm
-// rows are padded to a multiple of 4 with zeros so that every LDS read
-// fetches 4 outputs' weights at once (a broadcast: all lanes read one row).
+// Tn = (L + D) Wm per pixel, then D <- (L + D) - Tn (= D + L - Tn).  A
+// block takes 64 pixels at a time; its wave g computes the outputs of frames
+// 16g .. 16g + 15 from float4 rows of Wm in LDS (every lane reads the same
+// address) while it streams L + D of all frames; the four waves read the
+// same pixels, so HBM sees them once.
 __global__ __launch_bounds__(RB) void rp_svt_apply_kernel(RpArgs A) {
   constexpr int MP = RP_MAX_FRAMES;
-  __shared__ __attribute__((aligned(16))) float w[RP_MAX_FRAMES * MP];
-  const int T = A.T, TP = (T + 3) & ~3;
-  for (int e = threadIdx.x; e < T * TP; e += RB) {
-    const int s_ = e / TP, t = e - s_ * TP;
-    w[s_ * MP + t] = t < T ? A.Wm[s_ * T + t] : 0.f;
+  static_assert(RB == 4 * 64 && MP == 64, "four waves of 16 output frames");
+  __shared__ __attribute__((aligned(16))) float w[MP * MP];
+  const int T = A.T;
+  for (int e = threadIdx.x; e < MP * MP; e += RB) {
+    const int s_ = e >> 6, t = e & (MP - 1);
+    w[e] = (s_ < T && t < T) ? A.Wm[s_ * T + t] : 0.f;
   }
   __syncthreads();
   double lt2 = 0.0, dt2 = 0.0;
   const long npx = A.npx;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
-    float m[RP_MAX_FRAMES];
+  const int t0 = 16 * (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t0 < T) {
+    for (long c = blockIdx.x; c * 64 < npx; c += gridDim.x) {
+      const long i = c * 64 + lane;
+      const bool valid = i < npx;
+      float acc[16];
 #pragma unroll
-    for (int s_ = 0; s_ < RP_MAX_FRAMES; ++s_)
-      m[s_] = s_ < T ? A.L[(long)s_ * npx + i] + A.D[(long)s_ * npx + i] : 0.f;
-    for (int t4 = 0; t4 < TP; t4 += 4) {
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int u = 0; u < 16; ++u) acc[u] = 0.f;
+#pragma unroll 4
+      for (int s_ = 0; s_ < T; ++s_) {
+        const float m = valid ? A.L[(long)s_ * npx + i] + A.D[(long)s_ * npx + i] : 0.f;
+        const float4* wr = reinterpret_cast<const float4*>(&w[s_ * MP + t0]);
 #pragma unroll
-      for (int s_ = 0; s_ < RP_MAX_FRAMES; ++s_) {
-        if (s_ < T) {
-          const float4 wv = *reinterpret_cast<const float4*>(&w[s_ * MP + t4]);
-          acc.x += m[s_] * wv.x;
-          acc.y += m[s_] * wv.y;
-          acc.z += m[s_] * wv.z;
-          acc.w += m[s_] * wv.w;
+        for (int j = 0; j < 4; ++j) {
+          const float4 wv = wr[j];
+          acc[4 * j + 0] += m * wv.x;
+          acc[4 * j + 1] += m * wv.y;
+          acc[4 * j + 2] += m * wv.z;
+          acc[4 * j + 3] += m * wv.w;
         }
       }
-      const float av[4] = {acc.x, acc.y, acc.z, acc.w};
+      if (!valid) continue;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int t = t4 + u;
-        if (t >= T) break;
-        const long e = (long)t * npx + i;
-        const float l = A.L[e], told = A.Tn[e];
-        A.Tn[e] = av[u];
-        A.D[e] = A.D[e] + (l - av[u]);
-        if (A.record) {
-          const float d1 = l - av[u], d2 = av[u] - told;
-          lt2 += (double)d1 * d1;
-          dt2 += (double)d2 * d2;
+      for (int u = 0; u < 16; ++u) {
+        const int t = t0 + u;
+        if (t < T) {
+          const long e = (long)t * npx + i;
+          const float l = A.L[e], m = l + A.D[e];
+          if (A.record) {
+            const float d1 = l - acc[u], d2 = acc[u] - A.Tn[e];
+            lt2 += (double)d1 * d1;
+            dt2 += (double)d2 * d2;
+          }
+          A.Tn[e] = acc[u];
+          A.D[e] = m - acc[u];
         }
       }
     }
   }
   if (A.record) {
-    block_sum(lt2, A.partial + RP_SLOTS * blockIdx.x + 2);
-    block_sum(dt2, A.partial + RP_SLOTS * blockIdx.x + 3);
+    block_sum(lt2, A.partial + 2 * A.pstride + blockIdx.x);
+    block_sum(dt2, A.partial + 3 * A.pstride + blockIdx.x);
   }
 }
 
-// Lines 12-15: A += X - S - L, b_t += z_t - s_t, c_t += w_{t+1} - s_{t+1}.
+// The multiplier steps, per pixel of frame t: A += X - S - L,
+// b_t += z_t - s_t (t below the last frame), c_{t-1} += w_{t-1} - s_t
+// (t above the first).
 __global__ __launch_bounds__(RB) void rp_dual_kernel(RpArgs A) {
   double rp2 = 0.0, dz2 = 0.0;
-  const long npx = A.npx, n = npx * A.T;
-  for (long e = blockIdx.x * (long)RB + threadIdx.x; e < n; e += (long)gridDim.x * RB) {
-    const int t = (int)(e / npx);
-    const long i = e - (long)t * npx;
+  const int t = blockIdx.y;
+  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx;
+  const bool hz = t < A.T - 1, hw = t > 0;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
+    const long e = fe + i;
     const float x = A.X[e], s = A.S[e], l = A.L[e];
-    A.A[e] = A.A[e] + x - s - l;
-    if (A.record) {
-      const float u = x - s - l;
-      rp2 += (double)u * u;
-    }
-    if (t < A.T - 1) {
-      const long pe = (long)t * npx + i;
-      const float z = A.Z[pe];
-      A.B[pe] = A.B[pe] + (z - s);
+    const float u0 = x - s - l;
+    A.A[e] = A.A[e] + u0;
+    if (A.record) rp2 += (double)u0 * u0;
+    if (hz) {
+      const float z = A.Z[e];
+      A.B[e] = A.B[e] + (z - s);
       if (A.record) {
-        const float u = z - s, v = z - A.zo[pe];
+        const float u = z - s, v = z - A.zo[e];
         rp2 += (double)u * u;
         dz2 += (double)v * v;
       }
     }
-    if (t > 0) {
-      const long pw = (long)(t - 1) * npx + i;
+    if (hw) {
+      const long pw = fw + i;
       const float w = A.W[pw];
       A.C[pw] = A.C[pw] + (w - s);
       if (A.record) {
@@ -469,28 +547,29 @@ __global__ __launch_bounds__(RB) void rp_dual_kernel(RpArgs A) {
     }
   }
   if (A.record) {
-    block_sum(rp2, A.partial + RP_SLOTS * blockIdx.x + 0);
-    block_sum(dz2, A.partial + RP_SLOTS * blockIdx.x + 4);
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    block_sum(rp2, A.partial + 0 * A.pstride + b);
+    block_sum(dz2, A.partial + 4 * A.pstride + b);
   }
 }
 
-__global__ __launch_bounds__(RB) void rp_reduce_kernel(const double* partial, int nblocks, double* out) {
+// out[j] = sum of the first count[j] partials of slot j (one block, fixed order).
+__global__ __launch_bounds__(RB) void rp_reduce_kernel(const double* partial, int pstride, RpCounts cnt, double* out) {
   for (int j = 0; j < RP_SLOTS; ++j) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += RB) v += partial[RP_SLOTS * b + j];
+    for (int b = threadIdx.x; b < cnt.n[j]; b += RB) v += partial[(long)j * pstride + b];
     block_sum(v, out + j);
   }
 }
 
+// Input check: counts the non-finite entries of y and phi into slot 0.
 __global__ __launch_bounds__(RB) void rp_validate_kernel(long n, const float* y, const float* phi, double* partial) {
   double bad = 0.0;
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
     const float v = y[i], f = phi ? phi[i] : 1.f;
     bad += (isfinite(v) && isfinite(f)) ? 0.0 : 1.0;
   }
-  block_sum(bad, partial + RP_SLOTS * blockIdx.x);
-  if (threadIdx.x == 0)
-    for (int j = 1; j < RP_SLOTS; ++j) partial[RP_SLOTS * blockIdx.x + j] = 0.0;
+  block_sum(bad, partial + blockIdx.x);
 }
 
 int df_blocks(long n) { return (int)std::min<long>(1024, std::max<long>(1, (n + RB - 1) / RB)); }
@@ -516,8 +595,8 @@ hipError_t launch_df_validate(long n, const float* y, const float* phi, const fl
   return hipGetLastError();
 }
 
-hipError_t launch_rp_sx(const RpArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(rp_sx_kernel, dim3(blocks), dim3(RB), 0, s, a);
+hipError_t launch_rp_sx(const RpArgs& a, int bx, hipStream_t s) {
+  hipLaunchKernelGGL(rp_sx_kernel, dim3(bx, a.T), dim3(RB), 0, s, a);
   return hipGetLastError();
 }
 
@@ -528,7 +607,7 @@ hipError_t launch_rp_gram(const RpArgs& a, int blocks, double* gpart, hipStream_
 
 hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double* G, hipStream_t s) {
   const int np = T * (T + 1) / 2;
-  hipLaunchKernelGGL(rp_gram_reduce_kernel, dim3((np + RB - 1) / RB), dim3(RB), 0, s, gpart, blocks, np, G);
+  hipLaunchKernelGGL(rp_gram_reduce_kernel, dim3((np + 63) / 64), dim3(RB), 0, s, gpart, blocks, np, G);
   return hipGetLastError();
 }
 
@@ -542,13 +621,13 @@ hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rp_dual(const RpArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(rp_dual_kernel, dim3(blocks), dim3(RB), 0, s, a);
+hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s) {
+  hipLaunchKernelGGL(rp_dual_kernel, dim3(bx, a.T), dim3(RB), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_rp_reduce(const double* partial, int nblocks, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(rp_reduce_kernel, dim3(1), dim3(RB), 0, s, partial, nblocks, out);
+hipError_t launch_rp_reduce(const double* partial, int pstride, const RpCounts& cnt, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(rp_reduce_kernel, dim3(1), dim3(RB), 0, s, partial, pstride, cnt, out);
   return hipGetLastError();
 }
 

@@ -111,7 +111,7 @@ def test_residuals_shrink_and_iterates_agree_at_convergence():
 
 
 def test_printed_one_block_s_step_ignores_the_transport_term():
-    """The reading of the s-step: with the printed line (only the x-block,
+    """The reading of the s-step: with the printed update (only the x-block,
     max(x + a, 0)) ADMM settles at s = y on one pixel, whatever kappa is,
     while the closed form moves s towards s0.  Planted here, in a copy of the
     oracle's iteration, to show why the step minimises both blocks."""
