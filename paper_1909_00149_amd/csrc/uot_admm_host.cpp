@@ -368,7 +368,8 @@ struct rpca_handle {
   float *S = nullptr, *L = nullptr, *X = nullptr, *Tn = nullptr, *A = nullptr, *D = nullptr;
   float *B = nullptr, *C = nullptr, *P0 = nullptr, *P1 = nullptr, *zo = nullptr, *wo = nullptr;
   float* st[2][RP_NPLANES] = {};
-  double *d_gpart = nullptr, *d_G = nullptr, *d_V = nullptr;
+  double *d_gpart = nullptr, *d_G = nullptr, *d_V = nullptr, *d_lam = nullptr;
+  double2* d_rot = nullptr;
   float* d_Wm = nullptr;
   int* d_sweeps = nullptr;
   int gblocks = 1;
@@ -396,8 +397,9 @@ struct rpca_handle {
     for (auto& c : st)
       for (float* q : c)
         if (q) (void)hipFree(q);
-    for (double* q : {d_gpart, d_G, d_V, d_partial, d_sums})
+    for (double* q : {d_gpart, d_G, d_V, d_lam, d_partial, d_sums})
       if (q) (void)hipFree(q);
+    if (d_rot) (void)hipFree(d_rot);
     if (d_sweeps) (void)hipFree(d_sweeps);
     if (d_pairs) (void)hipFree(d_pairs);
     if (d_tiles) (void)hipFree(d_tiles);
@@ -452,7 +454,8 @@ uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, bool r
   DFCHK(launch_rp_sx(a, h->bx, h->stream));
   DFCHK(launch_rp_gram(a, h->gblocks, h->d_gpart, h->stream));
   DFCHK(launch_rp_gram_reduce(h->d_gpart, h->gblocks, P.frames, h->d_G, h->stream));
-  DFCHK(launch_rp_eig(h->d_G, P.frames, P.gam / P.rho, h->d_V, h->d_Wm, h->d_sweeps, h->stream));
+  DFCHK(launch_rp_eig(h->d_G, P.frames, P.gam / P.rho, h->d_V, h->d_rot, h->d_lam, h->d_Wm, h->d_sweeps,
+                      h->stream));
   DFCHK(launch_rp_svt_apply(a, h->sblocks, h->stream));
   for (int left = P.prox_iters; left > 0;) {
     const int k = std::min(h->T, left);
@@ -576,6 +579,8 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
       hipMalloc((void**)&h->d_G, (size_t)npairs_g * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_V, (size_t)Tf * Tf * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_Wm, (size_t)Tf * Tf * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->d_lam, RP_MAX_FRAMES * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->d_rot, (size_t)RP_MAX_SWEEPS * RP_ROT_PER_SWEEP * sizeof(double2)) != hipSuccess ||
       hipMalloc((void**)&h->d_sweeps, sizeof(int)) != hipSuccess)
     return fail(UOT_ERR_OOM);
 
@@ -629,7 +634,7 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
   long g = std::min<long>(h->ntiles, (long)h->num_cu * occ);
   h->grid = (int)std::max<long>(8, (g + 7) / 8 * 8);
   h->bx = (int)std::min<long>((h->npx + 255) / 256, std::max(1, 2048 / Tf));
-  h->sblocks = (int)std::min<long>(1024, (h->npx + 63) / 64);
+  h->sblocks = (int)std::min<long>(512, (h->npx + 127) / 128);
   h->vblocks = df_blocks(h->n);
   h->pstride = std::max(std::max(h->bx * Tf, h->sblocks), h->vblocks);
   if (hipMalloc((void**)&h->d_partial, RP_SLOTS * (size_t)h->pstride * sizeof(double)) != hipSuccess ||

@@ -226,14 +226,25 @@ __global__ __launch_bounds__(RB) void rp_gram_kernel(RpArgs A, double* gpart) {
 }
 
 // G[j] = sum over blocks of gpart[b][j]: a block adds 64 entries, its four
-// waves take every fourth partial, and the four sums are combined in a
-// fixed order (the result does not depend on timing).
+// waves take every fourth partial (eight loads in flight, added in block
+// order), and the four sums are combined in a fixed order (the result does
+// not depend on timing).
 __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart, int blocks, int np, double* G) {
   __shared__ double red[RB / 64][64];
+  constexpr int Q = RB / 64, U = 8;
   const int jl = threadIdx.x & 63, q = threadIdx.x >> 6, j = blockIdx.x * 64 + jl;
   double v = 0.0;
-  if (j < np)
-    for (int b = q; b < blocks; b += RB / 64) v += gpart[(long)b * np + j];
+  if (j < np) {
+    int b = q;
+    for (; b + Q * (U - 1) < blocks; b += Q * U) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = gpart[(long)(b + Q * u) * np + j];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v += x[u];
+    }
+    for (; b < blocks; b += Q) v += gpart[(long)b * np + j];
+  }
   red[q][jl] = v;
   __syncthreads();
   if (q == 0 && j < np) G[j] = (red[0][jl] + red[1][jl]) + (red[2][jl] + red[3][jl]);
@@ -245,28 +256,48 @@ __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart,
 // method with the parallel round-robin ordering (every round rotates 32
 // disjoint pairs at once), started from the previous call's eigenvectors V:
 // the iteration moves little from one ADMM step to the next, so V^T G V is
-// nearly diagonal and one sweep usually finishes it.  One workgroup; the
-// matrix is padded to 64 x 64 (zero rows and columns of A, identity in V,
-// which no rotation touches since their off-diagonal entries stay zero), so
-// all index arithmetic is shifts.  A and V live in LDS in FP64.  A round:
-// 32 threads form the rotations; then every 2 x 2 block (pair k1 rows, pair
-// k2 columns) of A becomes R_k1^T A R_k2 and the two columns of V of every
-// pair rotate, each block and column pair owned by one thread (no
-// conflicting writes), diagonal blocks taking the exact diagonalisation.
-// The products V^T G V and V diag(f) V^T keep a 4 x 4 block per thread.
-// Writes Wm = V diag(f) V^T (FP32, T x T), the new V, and the number of
-// sweeps.
-__global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg, float* Wm,
-                                                     int* sweeps) {
+// nearly diagonal and one sweep usually finishes it.  Three kernels:
+//   rp_eig_kernel   A = V^T G V, then Jacobi sweeps on A; stores every
+//                   rotation (c, s) and the eigenvalues diag(A)
+//   rp_vrot_kernel  applies the stored rotations to V, one row per workgroup
+//                   (rows are independent)
+//   rp_wm_kernel    Wm = V diag(f) V^T
+// The matrices are padded to 64 x 64 (zero rows and columns of A, identity
+// in V; no rotation touches the padding since its off-diagonal entries stay
+// zero), so all index arithmetic is shifts.
+
+// Round r of the round-robin: pair k of 32 is (p, q), p < q; player 63 is
+// fixed, the others rotate.
+__device__ __forceinline__ void rr_pair(int r, int k, int& p, int& q) {
+  constexpr int N1 = RP_MAX_FRAMES - 1;
+  int a = k == 0 ? r : (r + k) % N1;
+  int b = k == 0 ? N1 : (r - k + N1) % N1;
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// One workgroup.  A lives in LDS in FP64; after the start only its upper
+// triangle (with the diagonal) is kept.  A round: 32 threads form the
+// rotations (symmetric Schur, Golub and Van Loan); then every block of the
+// upper triangle (pair k1 rows, pair k2 >= k1 columns) becomes
+// R_k1^T A R_k2, each block owned by one thread, the diagonal blocks taking
+// the exact diagonalisation.  V^T G V keeps a 4 x 4 block per thread.
+__global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, const double* Vg, double2* rots,
+                                                     double* lam, int* sweeps) {
   constexpr int N = RP_MAX_FRAMES, LD = N + 1, NP = N / 2;
   static_assert(N == 64 && RB == 256, "64 x 64 matrices, 16 x 16 threads of 4 x 4 blocks");
   __shared__ double Am[N * LD];
   __shared__ double Vm[N * LD];
   __shared__ double rot[NP][3];  // c, s, t = s / c
-  __shared__ int pq[NP][2];
-  __shared__ double fj[N];
   __shared__ double red[2][RB / 64];
+  __shared__ int prs[(N - 1) * NP];  // round r, pair k: p | q << 8
   const int tid = threadIdx.x;
+  for (int e = tid; e < (N - 1) * NP; e += RB) {
+    int p, q;
+    rr_pair(e / NP, e % NP, p, q);
+    prs[e] = p | q << 8;
+  }
+#pragma unroll
   for (int e = tid; e < N * N; e += RB) {
     const int i = e >> 6, j = e & (N - 1);
     double gv = 0.0, vv = i == j ? 1.0 : 0.0;
@@ -286,6 +317,7 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
   for (int k = 0; k < N; ++k) {
     double a[4], b[4];
 #pragma unroll
@@ -309,6 +341,7 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
   for (int k = 0; k < N; ++k) {
     double a[4], b[4];
 #pragma unroll
@@ -328,15 +361,18 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
   __syncthreads();
 
-  const int k2 = tid & (NP - 1), r1 = tid >> 5;  // this thread's column pair; first row pair / V row
+  auto up = [](int i, int j) { return i < j ? i * LD + j : j * LD + i; };  // upper-triangle slot
   int sweep = 0;
-  for (; sweep < 40; ++sweep) {
+  for (; sweep < RP_MAX_SWEEPS; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < N * N; e += RB) {
       const int i = e >> 6, j = e & (N - 1);
-      const double v = Am[i * LD + j];
-      tot += v * v;
-      if (i != j) off += v * v;
+      if (i <= j) {
+        const double v = Am[i * LD + j];
+        const double w2 = i == j ? v * v : 2.0 * v * v;
+        tot += w2;
+        if (i != j) off += w2;
+      }
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_down(off, o, 64);
@@ -358,72 +394,116 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     if (!(off > 1e-20 * tot)) break;  // uniform: every thread holds the same sums
     for (int r = 0; r < N - 1; ++r) {
       if (tid < NP) {
-        // round-robin pairing: player N - 1 fixed, the others rotate
-        int p = tid == 0 ? r : (r + tid) % (N - 1);
-        int q = tid == 0 ? N - 1 : (r - tid + (N - 1)) % (N - 1);
-        if (p > q) {
-          const int u = p;
-          p = q;
-          q = u;
-        }
-        double c = 1.0, s = 0.0, t = 0.0;
-        const double apq = Am[p * LD + q];
+        const int pqv = prs[r * NP + tid], p = pqv & 255, q = pqv >> 8;
+        // symmetric Schur: t = tan of the angle that zeroes A[p][q]
+        const double apq = Am[p * LD + q], d = Am[q * LD + q] - Am[p * LD + p];
+        double c = 1.0, s_ = 0.0, t = 0.0;
         if (apq != 0.0) {
-          const double tau = (Am[q * LD + q] - Am[p * LD + p]) / (2.0 * apq);
-          t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
+          t = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+          c = rsqrt(1.0 + t * t);
+          s_ = t * c;
         }
         rot[tid][0] = c;
-        rot[tid][1] = s;
+        rot[tid][1] = s_;
         rot[tid][2] = t;
-        pq[tid][0] = p;
-        pq[tid][1] = q;
+        rots[((long)sweep * (N - 1) + r) * NP + tid] = make_double2(c, s_);
       }
       __syncthreads();
-      const int p2 = pq[k2][0], q2 = pq[k2][1];
+      // every upper-triangle block of this round, branch-free: a diagonal
+      // block (k1 = k2) writes its first off-diagonal slot twice, both zero
+      const int k2 = tid & (NP - 1), pq2 = prs[r * NP + k2], p2 = pq2 & 255, q2 = pq2 >> 8;
       const double c2 = rot[k2][0], s2 = rot[k2][1];
+      int ix[NP / 8][4];
+      double nv[NP / 8][4];
 #pragma unroll
       for (int m = 0; m < NP / 8; ++m) {
-        const int k1 = r1 + 8 * m;
-        const int p1 = pq[k1][0], q1 = pq[k1][1];
-        const double a = Am[p1 * LD + p2], b = Am[p1 * LD + q2], cc = Am[q1 * LD + p2], d = Am[q1 * LD + q2];
-        if (k1 == k2) {
-          const double t1 = rot[k1][2];
-          Am[p1 * LD + p1] = a - t1 * b;
-          Am[q1 * LD + q1] = d + t1 * b;
-          Am[p1 * LD + q1] = 0.0;
-          Am[q1 * LD + p1] = 0.0;
-        } else {
-          const double c1 = rot[k1][0], s1 = rot[k1][1];
-          const double rpp = c1 * a - s1 * cc, rpq = c1 * b - s1 * d;
-          const double rqp = s1 * a + c1 * cc, rqq = s1 * b + c1 * d;
-          Am[p1 * LD + p2] = c2 * rpp - s2 * rpq;
-          Am[p1 * LD + q2] = s2 * rpp + c2 * rpq;
-          Am[q1 * LD + p2] = c2 * rqp - s2 * rqq;
-          Am[q1 * LD + q2] = s2 * rqp + c2 * rqq;
-        }
+        const int k1 = (tid >> 5) + 8 * m;
+        const int pq1 = prs[r * NP + k1], p1 = pq1 & 255, q1 = pq1 >> 8;
+        ix[m][0] = up(p1, p2);
+        ix[m][1] = up(p1, q2);
+        ix[m][2] = up(q1, p2);
+        ix[m][3] = up(q1, q2);
+        const double a = Am[ix[m][0]], b = Am[ix[m][1]], cc = Am[ix[m][2]], d = Am[ix[m][3]];
+        const double c1 = rot[k1][0], s1 = rot[k1][1], t1 = rot[k1][2];
+        const double rpp = c1 * a - s1 * cc, rpq = c1 * b - s1 * d;
+        const double rqp = s1 * a + c1 * cc, rqq = s1 * b + c1 * d;
+        const bool dg = k1 == k2;
+        nv[m][0] = dg ? a - t1 * b : c2 * rpp - s2 * rpq;
+        nv[m][1] = dg ? 0.0 : s2 * rpp + c2 * rpq;
+        nv[m][2] = dg ? 0.0 : c2 * rqp - s2 * rqq;
+        nv[m][3] = dg ? d + t1 * b : s2 * rqp + c2 * rqq;
       }
 #pragma unroll
-      for (int m = 0; m < N / 8; ++m) {
-        const int i = r1 + 8 * m;
-        const double va = Vm[i * LD + p2], vb = Vm[i * LD + q2];
-        Vm[i * LD + p2] = c2 * va - s2 * vb;
-        Vm[i * LD + q2] = s2 * va + c2 * vb;
+      for (int m = 0; m < NP / 8; ++m) {
+        if ((tid >> 5) + 8 * m <= k2) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) Am[ix[m][u]] = nv[m][u];
+        }
       }
       __syncthreads();
     }
   }
+  if (tid < N) lam[tid] = Am[tid * LD + tid];
+  if (tid == 0) *sweeps = sweep;
+}
+
+// V <- V J for every stored rotation, in order; workgroup i (one wave) owns
+// row i of V, lane j its entry j (rows at and beyond T are identity rows
+// that no rotation touches).  In round r the partner of j is 2r - j mod 63
+// (j = 63 and j = r pair with each other), which a shuffle fetches.  A
+// sweep's rotations (63 rounds of 32) are staged in LDS first.
+__global__ __launch_bounds__(64) void rp_vrot_kernel(int T, const double2* rots, const int* sweeps, double* Vg) {
+  constexpr int N = RP_MAX_FRAMES, NP = N / 2, NR = (N - 1) * NP, N1 = N - 1;
+  __shared__ double2 rs[NR];
+  const int i = blockIdx.x, lane = threadIdx.x;
+  double v = lane < T ? Vg[i * T + lane] : 0.0;
+  const int nsw = *sweeps;
+  for (int sw = 0; sw < nsw; ++sw) {
+    __syncthreads();
+#pragma unroll
+    for (int e = lane; e < NR; e += 64) rs[e] = rots[(long)sw * NR + e];
+    __syncthreads();
+    for (int r = 0; r < N1; ++r) {
+      int partner, k;
+      if (lane == N1 || lane == r) {
+        partner = lane == N1 ? r : N1;
+        k = 0;
+      } else {
+        partner = (2 * r - lane + 2 * N1) % N1;
+        const int d = (lane - r + N1) % N1;
+        k = d <= NP - 1 ? d : N1 - d;
+      }
+      const double2 cs = rs[r * NP + k];
+      const double w = __shfl(v, partner, 64);
+      v = lane < partner ? cs.x * v - cs.y * w : cs.y * w + cs.x * v;
+    }
+  }
+  if (lane < T) Vg[i * T + lane] = v;
+}
+
+// Wm = V diag(f) V^T, f_k = max(1 - thr / sqrt(lam_k), 0) (FP32 result).
+__global__ __launch_bounds__(RB) void rp_wm_kernel(int T, double thr, const double* Vg, const double* lam, float* Wm) {
+  constexpr int N = RP_MAX_FRAMES, LD = N + 1;
+  __shared__ double Vm[N * LD];
+  __shared__ double fj[N];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = tid; e < N * N; e += RB) {
+    const int i = e >> 6, j = e & (N - 1);
+    Vm[i * LD + j] = (i < T && j < T) ? Vg[i * T + j] : 0.0;
+  }
   if (tid < N) {
-    const double sig = sqrt(fmax(Am[tid * LD + tid], 0.0));
-    fj[tid] = sig > thr ? 1.0 - thr / sig : 0.0;
+    const double sig = sqrt(fmax(lam[tid], 0.0));
+    fj[tid] = (tid < T && sig > thr) ? 1.0 - thr / sig : 0.0;
   }
   __syncthreads();
-  // Wm = V diag(f) V^T
+  const int bi = tid >> 4, bj = tid & 15;
+  double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
   for (int k = 0; k < N; ++k) {
     const double f = fj[k];
     double a[4], b[4];
@@ -442,69 +522,68 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 4 * bi + u, j = 4 * bj + v;
-      if (i < T && j < T) {
-        Wm[i * T + j] = (float)acc[u][v];
-        Vg[i * T + j] = Vm[i * LD + j];
-      }
+      if (i < T && j < T) Wm[i * T + j] = (float)acc[u][v];
     }
-  if (tid == 0) *sweeps = sweep;
 }
 
-// Tn = (L + D) Wm per pixel, then D <- (L + D) - Tn (= D + L - Tn).  A
-// block takes 64 pixels at a time; its wave g computes the outputs of frames
-// 16g .. 16g + 15 from float4 rows of Wm in LDS (every lane reads the same
-// address) while it streams L + D of all frames; the four waves read the
-// same pixels, so HBM sees them once.
+// Tn = (L + D) Wm per pixel, then D <- (L + D) - Tn (= D + L - Tn): for 32
+// pixels at a time, Tn^T = Wm^T (L + D)^T is two 32 x 32 output tiles of
+// v_mfma_f32_32x32x2f32 over K = 64 frames.  Lane l supplies A[l%32][l/32]
+// and B[l/32][l%32] and holds D rows 8(r/4) + 4(l/32) + r%4, column l%32,
+// in register r.  The K order is free, so step kk gives lane half h frame
+// 8(kk/4) + 4h + kk%4: the frames a lane loads for B are then exactly the
+// output frames it holds, and D - Tn needs no exchange.  Wm^T stays in
+// registers; (L + D) is streamed once.
+__device__ __forceinline__ int svt_frame(int kk, int h) { return 8 * (kk >> 2) + 4 * h + (kk & 3); }
+
 __global__ __launch_bounds__(RB) void rp_svt_apply_kernel(RpArgs A) {
-  constexpr int MP = RP_MAX_FRAMES;
-  static_assert(RB == 4 * 64 && MP == 64, "four waves of 16 output frames");
-  __shared__ __attribute__((aligned(16))) float w[MP * MP];
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
   const int T = A.T;
-  for (int e = threadIdx.x; e < MP * MP; e += RB) {
-    const int s_ = e >> 6, t = e & (MP - 1);
-    w[e] = (s_ < T && t < T) ? A.Wm[s_ * T + t] : 0.f;
-  }
-  __syncthreads();
-  double lt2 = 0.0, dt2 = 0.0;
   const long npx = A.npx;
-  const int t0 = 16 * (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (t0 < T) {
-    for (long c = blockIdx.x; c * 64 < npx; c += gridDim.x) {
-      const long i = c * 64 + lane;
-      const bool valid = i < npx;
-      float acc[16];
+  const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
+  const long wave = (long)blockIdx.x * (RB / 64) + (threadIdx.x >> 6), nw = (long)gridDim.x * (RB / 64);
+  float wa[2][32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc[u] = 0.f;
-#pragma unroll 4
-      for (int s_ = 0; s_ < T; ++s_) {
-        const float m = valid ? A.L[(long)s_ * npx + i] + A.D[(long)s_ * npx + i] : 0.f;
-        const float4* wr = reinterpret_cast<const float4*>(&w[s_ * MP + t0]);
+  for (int tau = 0; tau < 2; ++tau)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float4 wv = wr[j];
-          acc[4 * j + 0] += m * wv.x;
-          acc[4 * j + 1] += m * wv.y;
-          acc[4 * j + 2] += m * wv.z;
-          acc[4 * j + 3] += m * wv.w;
-        }
-      }
-      if (!valid) continue;
+    for (int kk = 0; kk < 32; ++kk) {
+      const int s_ = svt_frame(kk, h), t = 32 * tau + j;
+      wa[tau][kk] = (s_ < T && t < T) ? A.Wm[s_ * T + t] : 0.f;
+    }
+  double lt2 = 0.0, dt2 = 0.0;
+  for (long g = wave; g * 32 < npx; g += nw) {
+    const long i = g * 32 + j;
+    const bool valid = i < npx;
+    float m[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = t0 + u;
+    for (int kk = 0; kk < 32; ++kk) {
+      const int s_ = svt_frame(kk, h);
+      m[kk] = (valid && s_ < T) ? A.L[(long)s_ * npx + i] + A.D[(long)s_ * npx + i] : 0.f;
+    }
+    f32x16 c0 = {}, c1 = {};
+#pragma unroll
+    for (int kk = 0; kk < 32; ++kk) {
+      c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[0][kk], m[kk], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[1][kk], m[kk], c1, 0, 0, 0);
+    }
+    if (!valid) continue;
+#pragma unroll
+    for (int tau = 0; tau < 2; ++tau)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int t = svt_frame(16 * tau + r, h);
         if (t < T) {
+          const float tn = tau == 0 ? c0[r] : c1[r];
           const long e = (long)t * npx + i;
-          const float l = A.L[e], m = l + A.D[e];
           if (A.record) {
-            const float d1 = l - acc[u], d2 = acc[u] - A.Tn[e];
+            const float d1 = A.L[e] - tn, d2 = tn - A.Tn[e];
             lt2 += (double)d1 * d1;
             dt2 += (double)d2 * d2;
           }
-          A.Tn[e] = acc[u];
-          A.D[e] = m - acc[u];
+          A.Tn[e] = tn;
+          A.D[e] = m[16 * tau + r] - tn;
         }
       }
-    }
   }
   if (A.record) {
     block_sum(lt2, A.partial + 2 * A.pstride + blockIdx.x);
@@ -611,8 +690,15 @@ hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double*
   return hipGetLastError();
 }
 
-hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, float* Wm, int* sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, thr, V, Wm, sweeps);
+hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2* rots, double* lam, float* Wm,
+                         int* sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, V, rots, lam, sweeps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rp_vrot_kernel, dim3(T), dim3(64), 0, s, T, rots, sweeps, V);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rp_wm_kernel, dim3(1), dim3(RB), 0, s, T, thr, V, lam, Wm);
   return hipGetLastError();
 }
 

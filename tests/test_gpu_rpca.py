@@ -84,6 +84,25 @@ def test_iterates_match_oracle(dev, T, shape, prox_iters, variant):
     assert abs(rep["r_dual"] - rr.r_dual) <= 2e-3 * max(rr.r_dual, 1e-3)
 
 
+@pytest.mark.parametrize("T,shape", [(40, (4, 6)), (64, (5, 7))])
+def test_many_frames_match_oracle(dev, T, shape):
+    """Up to the 64-frame limit: every output frame of the singular-value
+    threshold (all rows of both 32-frame product tiles) and the padded
+    eigensolve, 12 iterations against the oracle."""
+    Y = video(T, T, *shape)
+    kw = dict(lam=0.05, gam=0.3, kappa=0.3, mu=0.8, rho=1.2)
+    solver = A.Rpca(shape[1], shape[0], T, prox_iters=2, max_iter=12, check_every=4, eps=0.0, **kw)
+    S, L, rep = solver.solve(t(Y, dev))
+    pl = solver.planes()
+    torch.cuda.synchronize()
+    st, rr = ora.rpca_uotdf(Y, prox_iters=2, max_iter=12, eps=0.0, check_every=4, **kw)
+    close(S, st.S, "S")
+    close(L, st.L, "L")
+    for k, o in (("Tn", st.Tn), ("D", st.D), ("Z", st.Z), ("W", st.W)):
+        close(pl[k], o, k)
+    assert abs(rep["r_dual"] - rr.r_dual) <= 2e-3 * max(rr.r_dual, 1e-3)
+
+
 def test_converges_like_the_oracle(dev):
     """The paper's stopping rule at 1e-4 on a small synthetic video: the GPU
     stops within one check window of the oracle, at the same separation; the
