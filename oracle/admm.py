@@ -300,3 +300,176 @@ def rpca_objective(Y, S, L, kappa, mu, lam, gam, phi=None, balanced=False):
     for t in range(T - 1):
         f += kappa * beckmann_aniso(S[t], S[t + 1], mu=None if balanced else mu, balanced=balanced)
     return f
+
+
+# ---------------------------------------------------------------------------
+# RPCA+UOT-DF with a signed sparse part (Sec. IV-B, eq. RPCA_UOTDF_PN):
+#
+#   min_{S+, S-, L >= 0} 1/2 sum_t ||y_t - Phi_t (s+_t - s-_t + l_t)||^2
+#       + lam (||S+||_1 + ||S-||_1) + gam ||L||_*
+#       + kappa sum_{t<T} (V_mu(s+_t, s+_{t+1}) + V_mu(s-_t, s-_{t+1}))
+#
+# The paper states the objective and no algorithm.  This is Algorithm 3's
+# splitting with the sparse block in two signs: X = S+ - S- + L, Tn = L,
+# z+-_t = s+-_t, w+-_{t+1} = s+-_{t+1} (multipliers A, D, b+-, c+-), the
+# blocks minimised in the order S+, S-, L, X, Tn, the prox of every frame
+# pair of both signs, then the multipliers:
+#
+#   k+ = (x - l + s- + a) + wz (z+ + b+) + ww (w+ + c+),  s+ = max(k+/sig - lam/(rho sig), 0)
+#   k- = (l - x + s+ - a) + wz (z- + b-) + ww (w- + c-),  s- = max(k-/sig - lam/(rho sig), 0)
+#   L  = max((Tn - D + X - S+ + S- + A) / 2, 0)
+#   x  = (Phi^T y + rho (s+ - s- + l - a)) / (Phi^T Phi + rho)
+#   Tn = SVT_{gam/rho}(L + D)
+#   (z+-_t, w+-_{t+1}) = prox_{(kappa/rho) V_mu}(s+-_t - b+-_t, s+-_{t+1} - c+-_{t+1})
+#   A += X - S+ + S- - L,  D += L - Tn,  b+- += z+- - s+-,  c+- += w+- - s+-
+#
+# Residuals: primal ||[X - S+ + S- - L; L - Tn; z+- - s+-; w+- - s+-]||,
+# dual rho ||[dX; dTn; dz+-; dw+-]||.
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class RpcaPnState:
+    Sp: np.ndarray
+    Sm: np.ndarray
+    L: np.ndarray
+    X: np.ndarray
+    Tn: np.ndarray
+    A: np.ndarray
+    D: np.ndarray
+    bp: np.ndarray
+    cp: np.ndarray
+    bm: np.ndarray
+    cm: np.ndarray
+    prox_p: list
+    prox_m: list
+
+    @staticmethod
+    def _stack(prox, which, like):
+        return np.stack([getattr(p, which) for p in prox]) if prox else np.zeros((0,) + like.shape[1:])
+
+    @property
+    def S(self):
+        return self.Sp - self.Sm
+
+    @property
+    def Zp(self):
+        return self._stack(self.prox_p, "x0", self.Sp)
+
+    @property
+    def Wp(self):
+        return self._stack(self.prox_p, "x1", self.Sp)
+
+    @property
+    def Zm(self):
+        return self._stack(self.prox_m, "x0", self.Sm)
+
+    @property
+    def Wm(self):
+        return self._stack(self.prox_m, "x1", self.Sm)
+
+
+def rpca_pn_initial_state(shape, kappa, mu, rho, balanced=False, residual_p=1, bc=0) -> RpcaPnState:
+    T = shape[0]
+    z = np.zeros(shape)
+    zp = np.zeros((T - 1,) + shape[1:])
+    zf = np.zeros(shape[1:])
+
+    def fresh():
+        return [uot.initial_state(rpca_problem(zf, zf, kappa, mu, rho, balanced, residual_p, bc))
+                for _ in range(T - 1)]
+    return RpcaPnState(z.copy(), z.copy(), z.copy(), z.copy(), z.copy(), z.copy(), z.copy(), zp.copy(), zp.copy(),
+                       zp.copy(), zp.copy(), fresh(), fresh())
+
+
+def _pair_prox(S, b, c, prox, kappa, mu, rho, balanced, residual_p, bc, prox_iters, tau):
+    out = []
+    for t in range(S.shape[0] - 1):
+        prob = rpca_problem(S[t] - b[t], S[t + 1] - c[t], kappa, mu, rho, balanced, residual_p, bc)
+        t1, t2 = prob.default_steps() if tau is None else tau
+        pst = prox[t]
+        for _ in range(prox_iters):
+            pst = uot.iterate(prob, pst, t1, t2)
+        out.append(pst)
+    return out
+
+
+def rpca_pn_iterate(Y, st: RpcaPnState, kappa, mu, rho, lam, gam, phi=None, balanced=False, residual_p=1, bc=0,
+                    prox_iters=1, tau=None) -> RpcaPnState:
+    """One ADMM iteration of the signed RPCA+UOT-DF (see the comment above)."""
+    Y = np.asarray(Y, float)
+    T = Y.shape[0]
+    ph = np.ones_like(Y) if phi is None else np.asarray(phi, float)
+    sig = np.ones(Y.shape)
+    kp = st.X - st.L + st.Sm + st.A
+    if T > 1:
+        kp[:-1] += st.Zp + st.bp
+        kp[1:] += st.Wp + st.cp
+        sig[:-1] += 1.0
+        sig[1:] += 1.0
+    Sp = np.maximum(kp / sig - lam / (rho * sig), 0.0)
+    km = st.L - st.X + Sp - st.A
+    if T > 1:
+        km[:-1] += st.Zm + st.bm
+        km[1:] += st.Wm + st.cm
+    Sm = np.maximum(km / sig - lam / (rho * sig), 0.0)
+    L = np.maximum(0.5 * (st.Tn - st.D + st.X - Sp + Sm + st.A), 0.0)
+    X = (ph * Y + rho * (Sp - Sm + L - st.A)) / (ph * ph + rho)
+    Tn = svt(L + st.D, gam / rho)
+    prox_p = _pair_prox(Sp, st.bp, st.cp, st.prox_p, kappa, mu, rho, balanced, residual_p, bc, prox_iters, tau)
+    prox_m = _pair_prox(Sm, st.bm, st.cm, st.prox_m, kappa, mu, rho, balanced, residual_p, bc, prox_iters, tau)
+    nxt = RpcaPnState(Sp, Sm, L, X, Tn, st.A + X - Sp + Sm - L, st.D + L - Tn, st.bp, st.cp, st.bm, st.cm,
+                      prox_p, prox_m)
+    if T > 1:
+        nxt.bp = st.bp + (nxt.Zp - Sp[:-1])
+        nxt.cp = st.cp + (nxt.Wp - Sp[1:])
+        nxt.bm = st.bm + (nxt.Zm - Sm[:-1])
+        nxt.cm = st.cm + (nxt.Wm - Sm[1:])
+    return nxt
+
+
+def rpca_pn_residuals(prev: RpcaPnState, cur: RpcaPnState, rho):
+    rp2 = np.sum((cur.X - cur.Sp + cur.Sm - cur.L) ** 2) + np.sum((cur.L - cur.Tn) ** 2)
+    rd2 = np.sum((cur.X - prev.X) ** 2) + np.sum((cur.Tn - prev.Tn) ** 2)
+    if cur.prox_p:
+        for S, Z, W, Zo, Wo in ((cur.Sp, cur.Zp, cur.Wp, prev.Zp, prev.Wp), (cur.Sm, cur.Zm, cur.Wm, prev.Zm, prev.Wm)):
+            rp2 += np.sum((Z - S[:-1]) ** 2) + np.sum((W - S[1:]) ** 2)
+            rd2 += np.sum((Z - Zo) ** 2) + np.sum((W - Wo) ** 2)
+    return float(np.sqrt(rp2)), float(rho * np.sqrt(rd2))
+
+
+def rpca_pn_uotdf(Y, kappa, mu, rho, lam, gam, phi=None, balanced=False, residual_p=1, bc=0, prox_iters=1,
+                  max_iter=5000, eps=1e-4, check_every=1, tau=None, record=False):
+    """The signed RPCA+UOT-DF until both residuals are below eps (tested
+    every check_every iterations) or max_iter; returns (state, report)."""
+    Y = np.asarray(Y, float)
+    st = rpca_pn_initial_state(Y.shape, kappa, mu, rho, balanced, residual_p, bc)
+    rep = DfReport()
+    for k in range(1, max_iter + 1):
+        nxt = rpca_pn_iterate(Y, st, kappa, mu, rho, lam, gam, phi, balanced, residual_p, bc, prox_iters, tau)
+        if k % check_every == 0 or k == max_iter:
+            rp, rd = rpca_pn_residuals(st, nxt, rho)
+            rep.r_primal, rep.r_dual = rp, rd
+            if record:
+                rep.history.append((k, rp, rd))
+            if rp < eps and rd < eps:
+                rep.iters, rep.converged = k, True
+                return nxt, rep
+        st = nxt
+    rep.iters = max_iter
+    return st, rep
+
+
+def rpca_pn_objective(Y, Sp, Sm, L, kappa, mu, lam, gam, phi=None, balanced=False):
+    """The objective of eq. RPCA_UOTDF_PN with V from the linear program
+    (exact on grids one pixel high or wide)."""
+    from .lp import beckmann_aniso
+    Y = np.asarray(Y, float)
+    ph = np.ones_like(Y) if phi is None else np.asarray(phi, float)
+    T = Y.shape[0]
+    f = 0.5 * float(np.sum((Y - ph * (Sp - Sm + L)) ** 2)) + lam * float(np.sum(Sp) + np.sum(Sm))
+    f += gam * float(np.sum(np.linalg.svd(L.reshape(T, -1).T, compute_uv=False)))
+    for t in range(T - 1):
+        for P in (Sp, Sm):
+            f += kappa * beckmann_aniso(P[t], P[t + 1], mu=None if balanced else mu, balanced=balanced)
+    return f
