@@ -124,6 +124,14 @@ void uotdf_destroy(uotdf_handle *h);
  * matrix of L + D, whose eigenvectors a parallel Jacobi method finds,
  * started from the previous iteration's.
  *
+ * Signed sparse part (Sec. IV-B, eq. RPCA_UOTDF_PN; signed_sparse = 1):
+ * S = S+ - S- with S+, S- >= 0, an l1 term on each and an OT term for each
+ * sign, kappa sum_t (V_mu(s+_t, s+_{t+1}) + V_mu(s-_t, s-_{t+1})).  The paper
+ * gives no algorithm for it; the splitting is Algorithm 3's with the sparse
+ * block in two signs (X = S+ - S- + L, one z, w pair per sign), minimised in
+ * the order S+, S-, L, X, Tn, the prox of all 2 (T - 1) pairs as one batch,
+ * then the multipliers.  The stacked residuals include both signs.
+ *
  * Layout: frames packed back to back, frame t at element t * nx * ny; y and
  * phi hold T frames, S and L (outputs) T frames.  2 <= frames <= 64.
  */
@@ -138,6 +146,8 @@ typedef struct rpca_params {
   double eps;           /* residual threshold (the paper uses 1e-4); <= 0 runs max_iter      */
   uint32_t flags;       /* UOT_NO_GRAPH                                                      */
   double prox_tau_ratio;/* tau1 / tau2 of the prox passes (as in uotdf_params); 0 = 1       */
+  int32_t signed_sparse;/* 0: S >= 0 (Algorithm 3); 1: S = S+ - S- (eq. RPCA_UOTDF_PN)      */
+  int32_t reserved;
 } rpca_params;
 
 typedef struct rpca_report {
@@ -154,13 +164,18 @@ typedef struct rpca_handle rpca_handle;
 uot_status rpca_check_params(const rpca_params *prm);
 uot_status rpca_create(const rpca_params *prm, void *hip_stream, rpca_handle **out);
 /* y, phi (may be NULL): device, T frames; S, L (may be NULL): device outputs,
- * T frames.  Every variable starts at zero.  Synchronous. */
+ * T frames (S = S+ - S- with signed_sparse).  Every variable starts at zero.
+ * Synchronous. */
 uot_status rpca_solve(rpca_handle *h, const float *y, const float *phi, float *S, float *L, rpca_report *rep);
 /* Copies the split variables and multipliers after the last solve into
- * caller-owned device buffers (X, Tn, A, D: T frames; Z, W, B, C: T - 1
- * frames; any may be NULL).  Synchronous. */
+ * caller-owned device buffers (X, Tn, A, D: T frames; Z, W, B, C: the pair
+ * planes, T - 1 frames, or 2 (T - 1) with signed_sparse: the + pairs, then
+ * the - pairs; any may be NULL).  Synchronous. */
 uot_status rpca_copy_planes(rpca_handle *h, float *X, float *Tn, float *A, float *D, float *Z, float *W, float *B,
                             float *C);
+/* Copies S+ and S- (T frames each; S- is zero without signed_sparse) into
+ * caller-owned device buffers (either may be NULL).  Synchronous. */
+uot_status rpca_copy_sparse(rpca_handle *h, float *Sp, float *Sm);
 void rpca_destroy(rpca_handle *h);
 
 #ifdef __cplusplus

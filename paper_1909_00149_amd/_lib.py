@@ -72,7 +72,8 @@ class RpParams(ctypes.Structure):
                 ("lam", ctypes.c_double), ("gam", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("mu", ctypes.c_double), ("rho", ctypes.c_double), ("prox_iters", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("flags", ctypes.c_uint32), ("prox_tau_ratio", ctypes.c_double)]
+                ("flags", ctypes.c_uint32), ("prox_tau_ratio", ctypes.c_double),
+                ("signed_sparse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RpReport(ctypes.Structure):
@@ -135,6 +136,7 @@ SIGNATURES = {
     "rpca_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.POINTER(RpReport)]),
     "rpca_copy_planes": (ctypes.c_int, [ctypes.c_void_p] * 9),
+    "rpca_copy_sparse": (ctypes.c_int, [ctypes.c_void_p] * 3),
     "rpca_destroy": (None, [ctypes.c_void_p]),
     "uot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }

@@ -71,17 +71,19 @@ class UotDf:
 
 
 class Rpca:
-    """One RPCA+UOT-DF handle (Algorithm 3) for T frames of ny x nx pixels."""
+    """One RPCA+UOT-DF handle (Algorithm 3) for T frames of ny x nx pixels;
+    signed=True solves the signed variant S = S+ - S- (eq. RPCA_UOTDF_PN)."""
 
     PLANES = ("X", "Tn", "A", "D", "Z", "W", "B", "C")
 
     def __init__(self, nx, ny, frames, lam, gam, kappa, mu, rho, balanced=False, residual_p=1, bc=0, prox_iters=1,
-                 max_iter=5000, check_every=10, eps=1e-4, flags=0, prox_tau_ratio=0.0, stream=None):
+                 max_iter=5000, check_every=10, eps=1e-4, flags=0, prox_tau_ratio=0.0, signed=False, stream=None):
         self.lib = _lib.load()
         self.shape = (int(frames), int(ny), int(nx))
+        self.signed = bool(signed)
         self._c = _lib.RpParams(int(nx), int(ny), int(frames), int(balanced), int(residual_p), int(bc), float(lam),
                                 float(gam), float(kappa), float(mu), float(rho), int(prox_iters), int(max_iter),
-                                int(check_every), float(eps), int(flags), float(prox_tau_ratio))
+                                int(check_every), float(eps), int(flags), float(prox_tau_ratio), int(self.signed), 0)
         if stream is None:
             stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -93,7 +95,8 @@ class Rpca:
     @staticmethod
     def check(**kw) -> int:
         d = dict(nx=4, ny=4, frames=3, balanced=0, residual_p=1, bc=0, lam=0.1, gam=0.1, kappa=1.0, mu=1.0,
-                 rho=1.0, prox_iters=1, max_iter=10, check_every=1, eps=1e-4, flags=0, prox_tau_ratio=0.0)
+                 rho=1.0, prox_iters=1, max_iter=10, check_every=1, eps=1e-4, flags=0, prox_tau_ratio=0.0,
+                 signed_sparse=0, reserved=0)
         d.update(kw)
         c = _lib.RpParams(*[d[k] for k, _ in _lib.RpParams._fields_])
         return int(_lib.load().rpca_check_params(ctypes.byref(c)))
@@ -109,12 +112,26 @@ class Rpca:
         return S, L, rep.as_dict()
 
     def planes(self, device="cuda"):
+        """The split variables and multipliers; pair planes (Z, W, B, C) hold
+        the T - 1 pairs, and with signed=True also Zm, Wm, Bm, Cm (the -
+        pairs) and Sp, Sm."""
         T, ny, nx = self.shape
-        out = {k: torch.empty((T if k in ("X", "Tn", "A", "D") else T - 1, ny, nx), dtype=torch.float32,
+        npair = (2 if self.signed else 1) * (T - 1)
+        out = {k: torch.empty((T if k in ("X", "Tn", "A", "D") else npair, ny, nx), dtype=torch.float32,
                               device=device) for k in self.PLANES}
         rc = self.lib.rpca_copy_planes(self._h, *[_ptr(out[k]) for k in self.PLANES])
         if rc != 0:
             raise UOTError(rc, "rpca_copy_planes")
+        if self.signed:
+            for k in ("Z", "W", "B", "C"):
+                out[k + "m"] = out[k][T - 1:]
+                out[k] = out[k][:T - 1]
+            sp = torch.empty((T, ny, nx), dtype=torch.float32, device=device)
+            sm = torch.empty_like(sp)
+            rc = self.lib.rpca_copy_sparse(self._h, _ptr(sp), _ptr(sm))
+            if rc != 0:
+                raise UOTError(rc, "rpca_copy_sparse")
+            out["Sp"], out["Sm"] = sp, sm
         return out
 
     def close(self):

@@ -363,9 +363,11 @@ struct rpca_handle {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0, num_cu = 256;
-  long npx = 0, n = 0, np1 = 0;  // pixels per frame, of all frames, of the T - 1 pair frames
+  long npx = 0, n = 0, np1 = 0;  // pixels per frame, of all frames, of the pair frames
+  int npairs = 1;                // T - 1, or 2 (T - 1) with the signed sparse part (+ pairs, then - pairs)
   int resid = R_P1;
   float *S = nullptr, *L = nullptr, *X = nullptr, *Tn = nullptr, *A = nullptr, *D = nullptr;
+  float* Sm = nullptr;  // S- (signed sparse part only)
   float *B = nullptr, *C = nullptr, *P0 = nullptr, *P1 = nullptr, *zo = nullptr, *wo = nullptr;
   float* st[2][RP_NPLANES] = {};
   double *d_gpart = nullptr, *d_G = nullptr, *d_V = nullptr, *d_lam = nullptr;
@@ -392,7 +394,7 @@ struct rpca_handle {
   ~rpca_handle() {
     for (auto& g : graphs)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    for (float* q : {S, L, X, Tn, A, D, B, C, P0, P1, zo, wo, d_Wm})
+    for (float* q : {S, Sm, L, X, Tn, A, D, B, C, P0, P1, zo, wo, d_Wm})
       if (q) (void)hipFree(q);
     for (auto& c : st)
       for (float* q : c)
@@ -445,6 +447,8 @@ RpArgs rp_args(rpca_handle* h, const float* y, const float* phi, bool record) {
   a.partial = h->d_partial;
   a.Wm = h->d_Wm;
   a.pstride = h->pstride;
+  a.Sm = h->Sm;
+  a.mo = (long)(h->prm.frames - 1) * h->npx;
   return a;
 }
 
@@ -536,6 +540,7 @@ uot_status rpca_check_params(const rpca_params* p) {
   if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
   if (p->prox_iters < 1 || p->max_iter < 1 || p->check_every < 1) return UOT_ERR_ARG;
   if (!(p->prox_tau_ratio >= 0.0) || !std::isfinite(p->prox_tau_ratio)) return UOT_ERR_ARG;
+  if (p->signed_sparse != 0 && p->signed_sparse != 1) return UOT_ERR_ARG;
   return UOT_OK;
 }
 
@@ -549,7 +554,8 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
   h->prm = *prm;
   h->npx = (long)prm->nx * prm->ny;
   h->n = h->npx * prm->frames;
-  h->np1 = h->npx * (prm->frames - 1);
+  h->npairs = (prm->signed_sparse ? 2 : 1) * (prm->frames - 1);
+  h->np1 = h->npx * h->npairs;
   h->resid = prm->balanced ? R_BAL : (prm->residual_p == 2 ? R_P2 : R_P1);
   auto fail = [&](uot_status e) {
     delete h;
@@ -568,6 +574,7 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
   const size_t fb = (size_t)h->n * sizeof(float), pb = (size_t)h->np1 * sizeof(float);
   for (float** q : {&h->S, &h->L, &h->X, &h->Tn, &h->A, &h->D})
     if (hipMalloc((void**)q, fb) != hipSuccess) return fail(UOT_ERR_OOM);
+  if (prm->signed_sparse && hipMalloc((void**)&h->Sm, fb) != hipSuccess) return fail(UOT_ERR_OOM);
   for (float** q : {&h->B, &h->C, &h->P0, &h->P1, &h->zo, &h->wo})
     if (hipMalloc((void**)q, pb) != hipSuccess) return fail(UOT_ERR_OOM);
   for (int c = 0; c < 2; ++c)
@@ -599,9 +606,9 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
   }
   h->launches_per_iter = (prm->prox_iters + h->T - 1) / h->T;
   const int rows = h->shape >= 1000 ? h->shape % 1000 : h->shape % 100;
-  std::vector<PairInfo> pairs(Tf - 1);
+  std::vector<PairInfo> pairs(h->npairs);
   std::vector<Tile> tiles;
-  for (int b = 0; b < Tf - 1; ++b) {
+  for (int b = 0; b < h->npairs; ++b) {
     PairInfo& P = pairs[b];
     P.off = (int64_t)b * h->npx;
     P.nx = prm->nx;
@@ -618,7 +625,7 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
     P.pitch = prm->nx;
   }
   h->ntiles = (int)tiles.size();
-  std::vector<int32_t> ones(Tf - 1, 1);
+  std::vector<int32_t> ones(h->npairs, 1);
   if (hipMalloc((void**)&h->d_pairs, pairs.size() * sizeof(PairInfo)) != hipSuccess ||
       hipMalloc((void**)&h->d_tiles, tiles.size() * sizeof(Tile)) != hipSuccess ||
       hipMalloc((void**)&h->d_ntiles, sizeof(int32_t)) != hipSuccess ||
@@ -661,6 +668,7 @@ uot_status rpca_solve(rpca_handle* h, const float* y, const float* phi, float* S
   // every variable and the prox states start at zero; the eigenvectors at I
   const size_t fb = (size_t)h->n * sizeof(float), pb = (size_t)h->np1 * sizeof(float);
   for (float* q : {h->S, h->L, h->X, h->Tn, h->A, h->D}) DFCHK(hipMemsetAsync(q, 0, fb, h->stream));
+  if (h->Sm) DFCHK(hipMemsetAsync(h->Sm, 0, fb, h->stream));
   for (float* q : {h->B, h->C, h->P0, h->P1, h->zo, h->wo}) DFCHK(hipMemsetAsync(q, 0, pb, h->stream));
   for (auto& c : h->st)
     for (float* q : c) DFCHK(hipMemsetAsync(q, 0, pb, h->stream));
@@ -700,7 +708,8 @@ uot_status rpca_solve(rpca_handle* h, const float* y, const float* phi, float* S
     if (s != UOT_OK) return s;
   }
   DFCHK(hipEventRecord(h->e1, h->stream));
-  if (S_out) DFCHK(hipMemcpyAsync(S_out, h->S, fb, hipMemcpyDeviceToDevice, h->stream));
+  if (S_out && h->Sm) DFCHK(launch_rp_sub(h->n, h->S, h->Sm, S_out, h->stream));
+  else if (S_out) DFCHK(hipMemcpyAsync(S_out, h->S, fb, hipMemcpyDeviceToDevice, h->stream));
   if (L_out) DFCHK(hipMemcpyAsync(L_out, h->L, fb, hipMemcpyDeviceToDevice, h->stream));
   int sweeps = 0;
   DFCHK(hipMemcpyAsync(&sweeps, h->d_sweeps, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -725,6 +734,18 @@ uot_status rpca_copy_planes(rpca_handle* h, float* X, float* Tn, float* A, float
   float* dst[8] = {X, Tn, A, D, Z, W, B, C};
   for (int i = 0; i < 8; ++i)
     if (dst[i]) DFCHK(hipMemcpyAsync(dst[i], src[i], i < 4 ? fb : pb, hipMemcpyDeviceToDevice, h->stream));
+  DFCHK(hipStreamSynchronize(h->stream));
+  return UOT_OK;
+}
+
+uot_status rpca_copy_sparse(rpca_handle* h, float* Sp, float* Sm) {
+  if (!h) return UOT_ERR_ARG;
+  const size_t fb = (size_t)h->n * sizeof(float);
+  if (Sp) DFCHK(hipMemcpyAsync(Sp, h->S, fb, hipMemcpyDeviceToDevice, h->stream));
+  if (Sm) {
+    if (h->Sm) DFCHK(hipMemcpyAsync(Sm, h->Sm, fb, hipMemcpyDeviceToDevice, h->stream));
+    else DFCHK(hipMemsetAsync(Sm, 0, fb, h->stream));
+  }
   DFCHK(hipStreamSynchronize(h->stream));
   return UOT_OK;
 }

@@ -44,6 +44,8 @@ struct RpArgs {
                                // 2 ||L-Tn||^2, 3 ||dTn||^2, 4 ||dz||^2+||dw||^2
   const float* Wm;             // T x T matrix of the singular-value threshold (svt apply)
   int pstride;                 // partial slot j of block b at partial[j * pstride + b]
+  float* Sm;                   // S- of the signed sparse part (nullptr: S >= 0, Algorithm 3)
+  long mo;                     // offset of the - pairs in the pair planes (signed sparse part)
 };
 
 // Number of partials each residual slot holds after a recorded iteration.
@@ -62,6 +64,7 @@ hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2*
 hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s);
 hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s);  // grid bx x T
 hipError_t launch_rp_reduce(const double* partial, int pstride, const RpCounts& cnt, double* out, hipStream_t s);
+hipError_t launch_rp_sub(long n, const float* a, const float* b, float* out, hipStream_t s);
 hipError_t launch_rp_validate(long n, const float* y, const float* phi, double* partial, int blocks, hipStream_t s);
 hipError_t launch_df_sx(const DfArgs& a, hipStream_t s);
 hipError_t launch_df_ab(const DfArgs& a, hipStream_t s);

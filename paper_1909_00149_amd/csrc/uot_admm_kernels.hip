@@ -112,17 +112,24 @@ __global__ __launch_bounds__(RB) void df_validate_kernel(long n, const float* y,
 //   x = (phi y + rho (s + l - a)) / (phi^2 + rho)
 //   p0_t = s_t - b_t,  p1_{t-1} = s_t - c_{t-1}
 // with wz = 1 unless t is the last frame and ww = 1 unless t is the first.
+// With SGN (the sparse part S = S+ - S-, eq. RPCA_UOTDF_PN) S holds S+, Sm
+// holds S-, the pair planes hold the + pairs then the - pairs (offset mo),
+// and the blocks are minimised in the order S+, S-, L, X:
+//   k+ = (x - l + s- + a) + (+ pairs),  k- = (l - x + s+ - a) + (- pairs)
+//   l = max((Tn - D + x - s+ + s- + a) / 2, 0),  x = (phi y + rho (s+ - s- + l - a)) / (phi^2 + rho)
 // z and w are saved (zo, wo) only where the residual is recorded.
+template <bool SGN>
 __global__ __launch_bounds__(RB) void rp_sx_kernel(RpArgs A) {
   double dx2 = 0.0;
   const int t = blockIdx.y;
-  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx;
+  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx, mo = A.mo;
   const bool hz = t < A.T - 1, hw = t > 0;
   const float rho = A.rho, lam = A.lam;
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
-    const long e = fe + i;
+    const long e = fe + i, ew = fw + i;
     const float x = A.X[e], l = A.L[e], a = A.A[e];
     float k = x - l + a, sig = 1.f, z = 0.f, w = 0.f, bz = 0.f, cw = 0.f;
+    if (SGN) k += A.Sm[e];
     if (hz) {
       z = A.Z[e];
       bz = A.B[e];
@@ -130,25 +137,49 @@ __global__ __launch_bounds__(RB) void rp_sx_kernel(RpArgs A) {
       sig += 1.f;
     }
     if (hw) {
-      w = A.W[fw + i];
-      cw = A.C[fw + i];
+      w = A.W[ew];
+      cw = A.C[ew];
       k += w + cw;
       sig += 1.f;
     }
     const float s = fmaxf(k / sig - lam / (rho * sig), 0.f);
-    const float ln = fmaxf(0.5f * (A.Tn[e] - A.D[e] + x - s + a), 0.f);
+    float sm = 0.f, zm = 0.f, wm = 0.f, bm = 0.f, cm = 0.f;
+    if (SGN) {
+      float km = l - x + s - a;
+      if (hz) {
+        zm = A.Z[mo + e];
+        bm = A.B[mo + e];
+        km += zm + bm;
+      }
+      if (hw) {
+        wm = A.W[mo + ew];
+        cm = A.C[mo + ew];
+        km += wm + cm;
+      }
+      sm = fmaxf(km / sig - lam / (rho * sig), 0.f);
+    }
+    const float ln = fmaxf(0.5f * (A.Tn[e] - A.D[e] + x - s + sm + a), 0.f);
     const float ph = A.phi ? A.phi[e] : 1.f;
-    const float xn = (ph * A.y[e] + rho * (s + ln - a)) / (ph * ph + rho);
+    const float xn = (ph * A.y[e] + rho * (s - sm + ln - a)) / (ph * ph + rho);
     A.S[e] = s;
+    if (SGN) A.Sm[e] = sm;
     A.L[e] = ln;
     A.X[e] = xn;
     if (hz) A.P0[e] = s - bz;
-    if (hw) A.P1[fw + i] = s - cw;
+    if (hw) A.P1[ew] = s - cw;
+    if (SGN) {
+      if (hz) A.P0[mo + e] = sm - bm;
+      if (hw) A.P1[mo + ew] = sm - cm;
+    }
     if (A.record) {
       const float d = xn - x;
       dx2 += (double)d * d;
       if (hz) A.zo[e] = z;
-      if (hw) A.wo[fw + i] = w;
+      if (hw) A.wo[ew] = w;
+      if (SGN) {
+        if (hz) A.zo[mo + e] = zm;
+        if (hw) A.wo[mo + ew] = wm;
+      }
     }
   }
   if (A.record) block_sum(dx2, A.partial + 1 * A.pstride + blockIdx.y * gridDim.x + blockIdx.x);
@@ -593,35 +624,42 @@ __global__ __launch_bounds__(RB) void rp_svt_apply_kernel(RpArgs A) {
 
 // The multiplier steps, per pixel of frame t: A += X - S - L,
 // b_t += z_t - s_t (t below the last frame), c_{t-1} += w_{t-1} - s_t
-// (t above the first).
+// (t above the first); with SGN, A += X - S+ + S- - L and the - pairs'
+// multipliers follow S- the same way.
+template <bool SGN>
 __global__ __launch_bounds__(RB) void rp_dual_kernel(RpArgs A) {
   double rp2 = 0.0, dz2 = 0.0;
   const int t = blockIdx.y;
-  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx;
+  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx, mo = A.mo;
   const bool hz = t < A.T - 1, hw = t > 0;
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
-    const long e = fe + i;
+    const long e = fe + i, ew = fw + i;
     const float x = A.X[e], s = A.S[e], l = A.L[e];
-    const float u0 = x - s - l;
+    const float sm = SGN ? A.Sm[e] : 0.f;
+    const float u0 = SGN ? x - s + sm - l : x - s - l;
     A.A[e] = A.A[e] + u0;
     if (A.record) rp2 += (double)u0 * u0;
-    if (hz) {
-      const float z = A.Z[e];
-      A.B[e] = A.B[e] + (z - s);
-      if (A.record) {
-        const float u = z - s, v = z - A.zo[e];
-        rp2 += (double)u * u;
-        dz2 += (double)v * v;
+#pragma unroll
+    for (int g = 0; g < (SGN ? 2 : 1); ++g) {
+      const long o = g ? mo : 0;
+      const float sv = g ? sm : s;
+      if (hz) {
+        const float z = A.Z[o + e];
+        A.B[o + e] = A.B[o + e] + (z - sv);
+        if (A.record) {
+          const float u = z - sv, v = z - A.zo[o + e];
+          rp2 += (double)u * u;
+          dz2 += (double)v * v;
+        }
       }
-    }
-    if (hw) {
-      const long pw = fw + i;
-      const float w = A.W[pw];
-      A.C[pw] = A.C[pw] + (w - s);
-      if (A.record) {
-        const float u = w - s, v = w - A.wo[pw];
-        rp2 += (double)u * u;
-        dz2 += (double)v * v;
+      if (hw) {
+        const float w = A.W[o + ew];
+        A.C[o + ew] = A.C[o + ew] + (w - sv);
+        if (A.record) {
+          const float u = w - sv, v = w - A.wo[o + ew];
+          rp2 += (double)u * u;
+          dz2 += (double)v * v;
+        }
       }
     }
   }
@@ -630,6 +668,11 @@ __global__ __launch_bounds__(RB) void rp_dual_kernel(RpArgs A) {
     block_sum(rp2, A.partial + 0 * A.pstride + b);
     block_sum(dz2, A.partial + 4 * A.pstride + b);
   }
+}
+
+// out = a - b (the signed sparse part S+ - S-).
+__global__ __launch_bounds__(RB) void rp_sub_kernel(long n, const float* a, const float* b, float* out) {
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) out[i] = a[i] - b[i];
 }
 
 // out[j] = sum of the first count[j] partials of slot j (one block, fixed order).
@@ -675,7 +718,8 @@ hipError_t launch_df_validate(long n, const float* y, const float* phi, const fl
 }
 
 hipError_t launch_rp_sx(const RpArgs& a, int bx, hipStream_t s) {
-  hipLaunchKernelGGL(rp_sx_kernel, dim3(bx, a.T), dim3(RB), 0, s, a);
+  if (a.Sm) hipLaunchKernelGGL(rp_sx_kernel<true>, dim3(bx, a.T), dim3(RB), 0, s, a);
+  else hipLaunchKernelGGL(rp_sx_kernel<false>, dim3(bx, a.T), dim3(RB), 0, s, a);
   return hipGetLastError();
 }
 
@@ -708,7 +752,13 @@ hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s) {
 }
 
 hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s) {
-  hipLaunchKernelGGL(rp_dual_kernel, dim3(bx, a.T), dim3(RB), 0, s, a);
+  if (a.Sm) hipLaunchKernelGGL(rp_dual_kernel<true>, dim3(bx, a.T), dim3(RB), 0, s, a);
+  else hipLaunchKernelGGL(rp_dual_kernel<false>, dim3(bx, a.T), dim3(RB), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rp_sub(long n, const float* a, const float* b, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(rp_sub_kernel, dim3(df_blocks(n)), dim3(RB), 0, s, n, a, b, out);
   return hipGetLastError();
 }
 

@@ -91,7 +91,8 @@ def test_uotdf_check_params(kw, ok):
                                    (dict(frames=64), True), (dict(kappa=0.0), False), (dict(gam=-1.0), False),
                                    (dict(lam=0.0, gam=0.0), True), (dict(mu=0.0), False),
                                    (dict(mu=0.0, balanced=1), True), (dict(prox_iters=0), False),
-                                   (dict(prox_tau_ratio=0.01), True), (dict(prox_tau_ratio=-1.0), False)])
+                                   (dict(prox_tau_ratio=0.01), True), (dict(prox_tau_ratio=-1.0), False),
+                                   (dict(signed_sparse=1), True), (dict(signed_sparse=2), False)])
 def test_rpca_check_params(kw, ok):
     from paper_1909_00149_amd.admm import Rpca
     assert (Rpca.check(**kw) == 0) == ok

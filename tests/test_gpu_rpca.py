@@ -138,6 +138,81 @@ def test_graph_replay_equals_direct_launches(dev, prox_iters, check_every):
     assert r1["r_primal"] == r2["r_primal"] and r1["r_dual"] == r2["r_dual"]
 
 
+def signed_video(seed, T, ny, nx):
+    """Foreground both lighter and darker than the background."""
+    rng = np.random.default_rng(seed)
+    mask = rng.uniform(0, 1, (T, ny, nx))
+    S = (rng.uniform(0.5, 1.5, (T, ny, nx)) * ((mask < 0.05).astype(float) - (mask > 0.95).astype(float)))
+    u = rng.uniform(0, 1, (ny, nx))
+    v = rng.uniform(0.5, 1, T)
+    L = v[:, None, None] * u[None]
+    return (S + L + rng.normal(0, 1e-3, S.shape)).astype(np.float32)
+
+
+@pytest.mark.parametrize("T,shape", [(2, (9, 14)), (5, (12, 20)), (7, (8, 70)), (40, (4, 6))])
+@pytest.mark.parametrize("prox_iters", [1, 3])
+@pytest.mark.parametrize("variant", ["plain", "masked", "p2"])
+def test_signed_iterates_match_oracle(dev, T, shape, prox_iters, variant):
+    """The signed sparse part (eq. RPCA_UOTDF_PN): S+, S-, L and every split
+    variable and multiplier of both signs after 17 iterations (windows of 5
+    and a tail of 2), stopping off."""
+    Y = signed_video(T + prox_iters, T, *shape)
+    kw = dict(lam=0.05, gam=0.3, kappa=0.3, mu=0.8, rho=1.2, balanced=False, residual_p=1)
+    phi = None
+    if variant == "masked":
+        rng = np.random.default_rng(8)
+        phi = (rng.uniform(0.3, 1.5, Y.shape) * (rng.uniform(0, 1, Y.shape) > 0.15)).astype(np.float32)
+    elif variant == "p2":
+        kw["residual_p"] = 2
+    iters = 17
+    solver = A.Rpca(shape[1], shape[0], T, prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0,
+                    signed=True, **kw)
+    S, L, rep = solver.solve(t(Y, dev), None if phi is None else t(phi, dev))
+    pl = solver.planes()
+    torch.cuda.synchronize()
+    assert rep["iters"] == iters and rep["converged"] == 0
+    st, rr = ora.rpca_pn_uotdf(Y, phi=phi, prox_iters=prox_iters, max_iter=iters, eps=0.0, check_every=5, **kw)
+    close(S, st.S, "S")
+    close(L, st.L, "L")
+    for k, o in (("Sp", st.Sp), ("Sm", st.Sm), ("X", st.X), ("Tn", st.Tn), ("A", st.A), ("D", st.D),
+                 ("Z", st.Zp), ("W", st.Wp), ("B", st.bp), ("C", st.cp), ("Zm", st.Zm), ("Wm", st.Wm),
+                 ("Bm", st.bm), ("Cm", st.cm)):
+        close(pl[k], o, k)
+    assert abs(rep["r_primal"] - rr.r_primal) <= 2e-3 * max(rr.r_primal, 1e-3)
+    assert abs(rep["r_dual"] - rr.r_dual) <= 2e-3 * max(rr.r_dual, 1e-3)
+
+
+def test_signed_converges_like_the_oracle(dev):
+    Y = signed_video(9, 6, 16, 16)
+    kw = dict(lam=0.05, gam=0.2, kappa=0.3, mu=1.0, rho=1.0)
+    solver = A.Rpca(16, 16, 6, prox_iters=2, max_iter=5000, check_every=10, eps=1e-4, signed=True, **kw)
+    S, L, rep = solver.solve(t(Y, dev))
+    torch.cuda.synchronize()
+    st, rr = ora.rpca_pn_uotdf(Y, prox_iters=2, max_iter=5000, eps=1e-4, check_every=10, **kw)
+    assert rep["converged"] == 1 and rr.converged
+    assert abs(rep["iters"] - rr.iters) <= 10
+    np.testing.assert_allclose(S.double().cpu().numpy(), st.S, atol=2e-3)
+    np.testing.assert_allclose(L.double().cpu().numpy(), st.L, atol=2e-3)
+    assert float(S.min()) < -0.1  # the dark foreground is found
+
+
+def test_signed_graph_replay_equals_direct_launches(dev):
+    Y = signed_video(3, 5, 20, 40)
+    out = []
+    for flags in (0, G.UOT_NO_GRAPH):
+        solver = A.Rpca(40, 20, 5, lam=0.05, gam=0.3, kappa=0.3, mu=0.8, rho=1.0, prox_iters=3, max_iter=17,
+                        check_every=4, eps=0.0, flags=flags, signed=True)
+        S, L, rep = solver.solve(t(Y, dev))
+        pl = solver.planes()
+        torch.cuda.synchronize()
+        out.append((S, L, pl, rep))
+    (S1, L1, p1, r1), (S2, L2, p2, r2) = out
+    assert torch.equal(S1, S2) and torch.equal(L1, L2)
+    for k in p1:
+        assert torch.equal(p1[k], p2[k]), k
+    assert r1["r_primal"] == r2["r_primal"] and r1["r_dual"] == r2["r_dual"]
+
+
 def test_input_checks(dev):
     Y = video(1, 3, 8, 8)
     Y[1, 2, 3] = np.inf
