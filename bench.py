@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--warm-pairs", type=int, default=64,
                     help="held-out 256x256 pairs for the warm-vs-cold time to 1e-4 (0: skip)")
     ap.add_argument("--prox-iters", default=None,
-                    help="rpca: comma-separated prox passes per ADMM iteration to study (default: all)")
+                    help="rpca, rpca_signed: comma-separated prox passes per ADMM iteration to study (default: all)")
     ap.add_argument("--tau-ratios", default=None,
                     help="rpca: comma-separated tau1/tau2 of the prox passes (default: 1,0.01)")
     args = ap.parse_args()
@@ -207,6 +207,9 @@ def main():
         return
     if args.workload == "rpca":
         run_rpca(args, dev)
+        return
+    if args.workload == "rpca_signed":
+        run_rpca_signed(args, dev)
         return
     if args.workload == "copy":
         n = (1 << 30) // 4
@@ -476,6 +479,67 @@ def run_rpca(args, dev):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = rpca_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+RPCA_SIGNED_KW = dict(lam=0.02, gam=4.0, kappa=0.02, mu=2.0, rho=1.0, prox_tau_ratio=0.01)
+
+
+def run_rpca_signed(args, dev):
+    """The signed RPCA+UOT-DF (eq. RPCA_UOTDF_PN) at the size of the paper's
+    video experiment (60 frames of 95x160) on a synthetic video whose
+    foreground is lighter and darker than the background: ADMM iterations to
+    1e-4 (checked every 10), device time per iteration and the separation
+    error, with Phi = I and with a random half of the pixels observed (a
+    diagonal stand-in for the paper's dense random projections, which this
+    build does not support), for 1, 3 and 10 prox passes.  `value` is ADMM
+    iterations per second with Phi = I and 3 prox passes."""
+    import torch
+    from paper_1909_00149_amd import admm as A
+    from paper_1909_00149_amd import synth
+
+    S0, L0, Y = synth.video_frames_signed(0)
+    T, ny, nx = Y.shape
+    rng = np.random.default_rng(1)
+    mask = (rng.uniform(0, 1, Y.shape) < 0.5).astype(np.float32)
+    ty = torch.from_numpy(Y).to(dev)
+    tym = torch.from_numpy(Y * mask).to(dev)
+    tmask = torch.from_numpy(mask).to(dev)
+    ks = (1, 3, 10) if args.prox_iters is None else tuple(int(v) for v in args.prox_iters.split(","))
+    rows = []
+    for phi_name, yy, phi in (("identity", ty, None), ("half the pixels", tym, tmask)):
+        for k in ks:
+            solver = A.Rpca(nx, ny, T, prox_iters=k, max_iter=5000, check_every=10, eps=1e-4, signed=True,
+                            **RPCA_SIGNED_KW)
+            if not rows:
+                for _ in range(args.warmup):
+                    solver.solve(yy, phi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S, L, rep = solver.solve(yy, phi)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            Sn, Ln = S.double().cpu().numpy(), L.double().cpu().numpy()
+            rows.append({"phi": phi_name, "prox_iters": k, "admm_iters": rep["iters"],
+                         "converged": bool(rep["converged"]), "ms_per_iter": round(rep["ms_per_iter"], 4),
+                         "wall_s": round(wall, 3),
+                         "rmse_S": round(float(np.sum((Sn - S0) ** 2) / np.sum(S0.astype(np.float64) ** 2)), 5),
+                         "rmse_L": round(float(np.sum((Ln - L0) ** 2) / np.sum(L0.astype(np.float64) ** 2)), 5),
+                         "dark_recall": round(float(np.mean(Sn[S0 < -0.1] < -0.05)), 4)})
+            solver.close()
+            print(f"# rpca_signed phi {phi_name} prox_iters {k}: {rep['iters']} ADMM iterations, "
+                  f"{rep['ms_per_iter']:.3f} ms each", file=sys.stderr, flush=True)
+    head = next((r for r in rows if r["phi"] == "identity" and r["prox_iters"] == 3), rows[0])
+    out = {
+        "metric": "signed RPCA+UOT-DF ADMM iterations/s, 60 frames of 95x160 (eq. RPCA_UOTDF_PN)",
+        "value": 1e3 / head["ms_per_iter"], "unit": "ADMM-iters/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": head["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rpca_signed", "description": "60 frames of 95x160, 12 blobs of either sign "
+                   "(amplitude 0.3-0.8, 0-2 px/frame) over a rank-3 background, noise 1e-3; lam 0.02, gam 4, "
+                   "kappa 0.02, mu 2, rho 1, prox tau1/tau2 0.01, eps 1e-4, check every 10"},
+        "study": rows,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -152,6 +152,34 @@ def video_frames(seed: int, frames: int = 64, side: int = 256, nblobs: int = 30,
     return S.astype(np.float32), L.astype(np.float32), Y.astype(np.float32)
 
 
+def video_frames_signed(seed: int, frames: int = 60, ny: int = 95, nx: int = 160, nblobs: int = 12, rank: int = 3):
+    """Synthetic video whose foreground is both lighter and darker than the
+    background (the situation of the signed sparse part): blobs of amplitude
+    +-U[0.3, 0.8] (sign per blob, sigma U[2, 5] px) moving at 0-2 px/frame
+    over a rank-3 smooth background of mean about 0.5, plus N(0, 0.001^2).
+    Returns float32 (S, L, Y) of shape (frames, ny, nx)."""
+    rng = np.random.default_rng(seed)
+    sig = rng.uniform(2.0, 5.0, nblobs)
+    amp = rng.uniform(0.3, 0.8, nblobs) * np.where(rng.uniform(0, 1, nblobs) < 0.5, -1.0, 1.0)
+    x0 = rng.uniform(0.0, nx, nblobs)
+    y0 = rng.uniform(0.0, ny, nblobs)
+    speed = rng.uniform(0.0, 2.0, nblobs)
+    ang = rng.uniform(0.0, 2.0 * math.pi, nblobs)
+    vx, vy = speed * np.cos(ang), speed * np.sin(ang)
+    S = np.zeros((frames, ny, nx), np.float64)
+    for t in range(frames):
+        rasterise(ny, nx, x0 + t * vx, y0 + t * vy, sig, amp, out=S[t])
+    ky, kx = np.fft.fftfreq(ny), np.fft.fftfreq(nx)
+    filt = np.outer(np.exp(-0.5 * (2.0 * math.pi * ky * 16.0) ** 2), np.exp(-0.5 * (2.0 * math.pi * kx * 16.0) ** 2))
+    L = np.zeros_like(S)
+    for _ in range(rank):
+        u = np.real(np.fft.ifft2(np.fft.fft2(rng.uniform(0.0, 1.0, (ny, nx))) * filt))
+        v = rng.uniform(0.5, 1.0, frames)
+        L += v[:, None, None] * u[None] / (0.75 * rank)
+    Y = S + L + rng.normal(0.0, 1e-3, S.shape)
+    return S.astype(np.float32), L.astype(np.float32), Y.astype(np.float32)
+
+
 def random_state(seed: int, ny: int, nx: int, scale: float = 0.1):
     """A random (Mx, My, r, a, x0, x1) state for warm-start and property tests."""
     rng = np.random.default_rng(seed)
