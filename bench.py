@@ -75,7 +75,8 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # for a 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid
 # only for the kernel sources they were taken on: any change to them makes
 # the figure unknown (null) until the counters are taken again.
-TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_kernels.hip", "paper_1909_00149_amd/csrc/uot_internal.hpp")
+TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
+                   "paper_1909_00149_amd/csrc/uot_internal.hpp")
 TRAFFIC_SHA256 = "2bf8a516c2635978de478ae86aa7fd236451dd6cd780c9219fad653f7803386a"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch

@@ -115,7 +115,17 @@ typedef struct uot_params {
   int32_t pitch;        /* row stride of uot_solve's planes in elements; 0 = nx.  A
                            pitch rounded up to a multiple of 4 puts every row on a
                            16-byte boundary; the padding is never read or written   */
+  int32_t norm;         /* flux norm: UOT_NORM_ISO (0) the paper's l2,1 sum of
+                           per-pixel ||(Mx, My)||_2 (eq. Unbal_OT_beckman);
+                           UOT_NORM_ANISO (1) the l1,1 sum of |Mx| + |My| (the
+                           anisotropic variant: grid min-cost flow).  Changes the
+                           flux prox (group vs component shrink), the flux norm in
+                           objectives and the dual feasibility (||.||_2 vs ||.||_inf)
+                           of the certified bounds                                   */
+  int32_t reserved;
 } uot_params;
+
+enum { UOT_NORM_ISO = 0, UOT_NORM_ANISO = 1 };
 
 /* Device planes of one state.  Required planes by mode:
  *   DIST: Mx, My, a (+ r unless balanced)      PROX: + x0, x1     PROX_FIXED: + x1

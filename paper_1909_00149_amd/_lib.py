@@ -26,7 +26,8 @@ class Params(ctypes.Structure):
                 ("tau1", ctypes.c_double), ("tau2", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("tile_rows", ctypes.c_int32), ("pitch", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("norm", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):

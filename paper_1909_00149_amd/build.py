@@ -33,8 +33,16 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["uot_kernels.hip", "uot_poisson.hip", "uot_host.cpp", "uot_admm_kernels.hip", "uot_admm_host.cpp",
-           "uotnet_kernels.hip", "uotnet_host.cpp"]
+# (source, object name, extra defines); the fused-iteration kernels are
+# instantiated once per mode from one source, so the three sets compile in
+# parallel
+SOURCES = [("uot_iter_mode.hip", "uot_iter_mode0", ["-DUOT_MODE=0"]),
+           ("uot_iter_mode.hip", "uot_iter_mode1", ["-DUOT_MODE=1"]),
+           ("uot_iter_mode.hip", "uot_iter_mode2", ["-DUOT_MODE=2"]),
+           ("uot_kernels.hip", "uot_kernels", []), ("uot_poisson.hip", "uot_poisson", []),
+           ("uot_host.cpp", "uot_host", []), ("uot_admm_kernels.hip", "uot_admm_kernels", []),
+           ("uot_admm_host.cpp", "uot_admm_host", []), ("uotnet_kernels.hip", "uotnet_kernels", []),
+           ("uotnet_host.cpp", "uotnet_host", [])]
 
 
 def hipcc():
@@ -44,10 +52,11 @@ def hipcc():
     return exe
 
 
-def _compile(src):
-    out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+def _compile(entry):
+    src, name, defs = entry
+    out = os.path.join(OBJ, name + ".o")
     lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
-    cmd = [hipcc(), *lang, *FLAGS, "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [hipcc(), *lang, *FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -56,7 +65,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

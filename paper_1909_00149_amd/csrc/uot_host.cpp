@@ -252,6 +252,7 @@ uot_status uot_check_params(const uot_params* p) {
   if (p->balanced != 0 && p->balanced != 1) return UOT_ERR_ARG;
   if (!p->balanced && p->residual_p != 1 && p->residual_p != 2) return UOT_ERR_ARG;
   if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
+  if (p->norm != UOT_NORM_ISO && p->norm != UOT_NORM_ANISO) return UOT_ERR_ARG;
   if (!p->balanced && !(p->mu > 0.0 && std::isfinite(p->mu))) return UOT_ERR_ARG;
   if (p->mode != UOT_DIST && !(p->rho > 0.0 && std::isfinite(p->rho))) return UOT_ERR_ARG;
   if (!(p->tau1 >= 0.0 && p->tau2 >= 0.0) || !std::isfinite(p->tau1) || !std::isfinite(p->tau2)) return UOT_ERR_ARG;
@@ -332,6 +333,10 @@ Planes planes_of(const uot_state& s) { return Planes{s.Mx, s.My, s.r, s.a, s.x0,
 
 // Grid of the persistent iteration kernel: enough resident blocks to fill
 // every CU, rounded to a multiple of the 8 XCDs.
+// Template code of the fused kernels and the check: bit 0 the boundary
+// reading, bit 1 the anisotropic flux norm.
+int bcn_of(const uot_params& p) { return p.bc | (p.norm == UOT_NORM_ANISO ? 2 : 0); }
+
 int iter_grid(uot_handle* h, int mode, int resid, int bc, int ty, int ntiles) {
   int occ = 0;
   if (iter_occupancy(mode, resid, bc, ty, &occ) != hipSuccess || occ <= 0) occ = 4;
@@ -394,7 +399,7 @@ uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* 
   if (ty == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
-    auto it = g_tune_cache.find(tune_key(p.mode, resid, p.bc, npx));
+    auto it = g_tune_cache.find(tune_key(p.mode, resid, bcn_of(p), npx));
     if (cached) *cached = it != g_tune_cache.end();
     ty = it != g_tune_cache.end() ? it->second : heuristic_shape(npx);
   }
@@ -616,9 +621,9 @@ hipError_t launch_steps(uot_handle* h, int resid, int shape, int steps, int grid
                         IterArgs a) {
   const uot_params& p = h->prm;
   if (steps <= 1 || shape_steps(shape) == 1)
-    return launch_iter(p.mode, resid, p.bc, shape_single(shape), grid_single, a, h->stream);
+    return launch_iter(p.mode, resid, bcn_of(p), shape_single(shape), grid_single, a, h->stream);
   a.steps = steps;
-  return launch_iter(p.mode, resid, p.bc, shape, grid_multi, a, h->stream);
+  return launch_iter(p.mode, resid, bcn_of(p), shape, grid_multi, a, h->stream);
 }
 
 uot_status enqueue_window(Launch& L, int W, bool check) {
@@ -628,7 +633,7 @@ uot_status enqueue_window(Launch& L, int W, bool check) {
   for (size_t i = 0; i < sched.size(); ++i)
     HIPCHK(launch_steps(h, L.resid, L.J->shape, sched[i], L.grid_iter, L.grid_single, (i & 1) ? L.bwd : L.fwd));
   if (check) {
-    HIPCHK(launch_check(p.mode, L.resid, p.bc, L.grid_aux, L.chk, h->stream));
+    HIPCHK(launch_check(p.mode, L.resid, bcn_of(p), L.grid_aux, L.chk, h->stream));
     HIPCHK(launch_reduce_decide(L.dec, h->d_partial, h->stream));
   }
   return UOT_OK;
@@ -737,7 +742,8 @@ uot_status balanced_primal(uot_handle* h, const Job& J, const float* src, const 
     s = poisson_grid(h, P.nx, P.ny, 0.0, h->pw[3], h->pw[2]);
     if (s != UOT_OK) return s;
     const int nb = repaired_norm_blocks(P.nx, P.ny);
-    HIPCHK(launch_repaired_norm(st->Mx + o, st->My + o, h->pw[2], P.nx, P.ny, P.pitch, h->d_pp, h->stream));
+    HIPCHK(launch_repaired_norm(st->Mx + o, st->My + o, h->pw[2], P.nx, P.ny, P.pitch, h->prm.norm, h->d_pp,
+                                h->stream));
     HIPCHK(hipMemcpyAsync(h->h_pp, h->d_pp, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     double acc = 0.0;
@@ -781,7 +787,7 @@ uot_status autotune(uot_handle* h, const Layout& L, const float* src, const floa
     s = upload_live(h, Jt, ones.data());
     if (s != UOT_OK) break;
     const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
-    const int grid = iter_grid(h, p.mode, resid, p.bc, Jt.shape, (int)Jt.tiles.size());
+    const int grid = iter_grid(h, p.mode, resid, bcn_of(p), Jt.shape, (int)Jt.tiles.size());
     const int T = shape_steps(Jt.shape);
     for (int i = 0; i < 2; ++i) HIPCHK(launch_steps(h, resid, Jt.shape, T, grid, grid, fwd));
     HIPCHK(hipEventRecord(e0, h->stream));
@@ -801,7 +807,7 @@ uot_status autotune(uot_handle* h, const Layout& L, const float* src, const floa
   if (s != UOT_OK) return s;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(p.mode, resid, p.bc, J.npx)] = best_ty;
+    g_tune_cache[tune_key(p.mode, resid, bcn_of(p), J.npx)] = best_ty;
     tune_store_locked();
   }
   s = plan(h, L, J, best_ty, nullptr, J.vec_ok);
@@ -881,8 +887,8 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   L.h = h;
   L.J = &J;
   L.resid = resid;
-  L.grid_iter = iter_grid(h, p.mode, resid, p.bc, J.shape, (int)J.tiles.size());
-  L.grid_single = iter_grid(h, p.mode, resid, p.bc, shape_single(J.shape), (int)J.tiles.size());
+  L.grid_iter = iter_grid(h, p.mode, resid, bcn_of(p), J.shape, (int)J.tiles.size());
+  L.grid_single = iter_grid(h, p.mode, resid, bcn_of(p), shape_single(J.shape), (int)J.tiles.size());
   L.grid_aux = aux_grid(h, (int)J.tiles.size());
   const Planes A = planes_of(*st), Bp = shadow_planes(h);
   const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
@@ -957,7 +963,7 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   if (p.max_iter == 0) fin.B = A;  // no iteration ran: no previous iterate
   fin.swap_active = odd ? 1 : 0;
   fin.all_pairs = 1;
-  HIPCHK(launch_check(p.mode, resid, p.bc, L.grid_aux, fin, h->stream));
+  HIPCHK(launch_check(p.mode, resid, bcn_of(p), L.grid_aux, fin, h->stream));
   DecideArgs fd = L.dec;
   fd.W = check ? (run_tail ? tail : 0) : (done_iters + (run_tail ? tail : 0));
   fd.check = 1;
@@ -1032,7 +1038,7 @@ uot_status time_core(uot_handle* h, const Layout& L, const float* src, const flo
   s = upload_live(h, J, h->h_i32);
   if (s != UOT_OK) return s;
   const int resid = resid_of(p);
-  const int grid = iter_grid(h, p.mode, resid, p.bc, J.shape, (int)J.tiles.size());
+  const int grid = iter_grid(h, p.mode, resid, bcn_of(p), J.shape, (int)J.tiles.size());
   const Planes A = planes_of(*st), Bp = shadow_planes(h);
   const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
   const IterArgs fwd{A, Bp, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
@@ -1179,7 +1185,7 @@ uot_status uot_objective(uot_handle* h, const float* src, const float* dst, cons
     const uot_state* q = prev ? prev : st;
     CheckArgs ck{planes_of(*st), planes_of(*q), 0, 1, p.mode == UOT_DIST ? h->cplane : nullptr, src, dst,
                  h->d_pairs, h->d_tiles, (int32_t)J.tiles.size(), J.ty, h->d_i32, h->d_partial};
-    HIPCHK(launch_check(p.mode, resid_of(p), p.bc, aux_grid(h, ck.ntiles), ck, h->stream));
+    HIPCHK(launch_check(p.mode, resid_of(p), bcn_of(p), aux_grid(h, ck.ntiles), ck, h->stream));
     HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, kMaxSlotsCheck, h->d_sums, h->stream));
     HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));

@@ -137,6 +137,17 @@ struct DualArgs {
   double* partial;
 };
 
+// Per-mode instantiations (uot_iter_mode.hip compiled with UOT_MODE = 0, 1, 2).
+hipError_t launch_iter_mode0(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
+hipError_t launch_iter_mode1(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
+hipError_t launch_iter_mode2(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
+hipError_t iter_occupancy_mode0(int resid, int bcn, int ty, int* n);
+hipError_t iter_occupancy_mode1(int resid, int bcn, int ty, int* n);
+hipError_t iter_occupancy_mode2(int resid, int bcn, int ty, int* n);
+hipError_t launch_check_mode0(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s);
+hipError_t launch_check_mode1(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s);
+hipError_t launch_check_mode2(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s);
+
 hipError_t launch_iter(int mode, int resid, int bc, int ty, int grid, const IterArgs& a,
                        hipStream_t s);
 hipError_t launch_check(int mode, int resid, int bc, int grid, const CheckArgs& a, hipStream_t s);
@@ -169,5 +180,5 @@ hipError_t launch_infeasibility(const float* Mx, const float* My, const float* s
                                 int nx, int ny, int pitch, hipStream_t s);
 int repaired_norm_blocks(int nx, int ny);
 hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, int pitch,
-                                double* partial, hipStream_t s);
+                                int aniso, double* partial, hipStream_t s);
 }  // namespace uot

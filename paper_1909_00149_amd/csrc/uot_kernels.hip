@@ -1,804 +1,11 @@
-// HIP kernels (gfx950) of the unbalanced Beckmann OT prox solver.
-//
-// cp_iter: one fused pass of Algorithm 1 (Sec. III-B) per launch:
-//   M  <- group-shrink_{tau1}(M - tau1 D* a)          (eq. Prox_UOT_M_prox)
-//   x  <- max(theta p + (1-theta)(x - tau1 A^T a), 0)   (PROX modes)
-//   r  <- shrink_{mu tau1}(r + tau1 a)  |  (r + tau1 a)/(1 + 2 mu tau1)
-//   a  <- a + tau2 (2 K(z_new) - K(z_old)),   K(z) = D M - x0 + x1 - r
-// A workgroup owns a 64 x TY tile.  a^k is staged in LDS with a one-pixel
-// halo on every side, the old flux with a halo on the low sides; the new
-// flux is computed for the tile plus its low-side halo (so D M_new needs no
-// second launch), then each pixel forms K_old, K_new and the dual step.
-// Input and output states are different buffers (ping-pong), so no pixel
-// reads a value another workgroup may already have overwritten.
-//
-// The tile list is walked by a fixed grid; blocks are mapped so that each
-// of the 8 XCDs (which own separate L2 caches and receive workgroups
-// round-robin) walks one contiguous eighth of the list, keeping vertically
-// neighbouring tiles, which share halo rows, in one L2.
-#include "uot_internal.hpp"
-
-#include <cmath>
+// HIP kernels (gfx950) of the solver that are not instantiated per mode:
+// input validation and set-up, the per-pair reduction with the stopping
+// decision, the copy of live pairs and the dual (Poisson) kernel, plus the
+// dispatch to the per-mode instantiations of the fused Algorithm-1 kernels
+// and the check (uot_iter_mode.hip, compiled once per mode).
+#include "uot_iter_impl.hpp"
 
 namespace uot {
-
-namespace {
-
-__device__ __forceinline__ float shrink1f(float v, float s) {
-  float m = fabsf(v) - s;
-  return m > 0.f ? copysignf(m, v) : 0.f;
-}
-
-template <int MODE>
-__device__ __forceinline__ constexpr int n_id_blocks(int resid) {
-  return (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (resid == R_BAL ? 1 : 0);
-}
-
-// Chunked, XCD-aware walk of the tile list: returns the range of list
-// indices this block visits as (first, stride, end).
-__device__ __forceinline__ void xcd_chunk(int ntiles, long& first, long& stride, long& end) {
-  const int G = gridDim.x;              // multiple of 8
-  const int xcd = blockIdx.x & 7;
-  const int slot = blockIdx.x >> 3;
-  const int per = (G - xcd + 7) >> 3;  // blocks on this XCD
-  const long cb = (long)ntiles * xcd / 8;
-  end = (long)ntiles * (xcd + 1) / 8;
-  first = cb + slot;
-  stride = per;
-}
-
-}  // namespace
-
-template <int MODE, int RES, int BC, int TY>
-__global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
-  constexpr int PPT = TY / 4;
-  __shared__ float sa[TY + 2][TX + 2];
-  __shared__ float smx[TY + 1][TX + 1];
-  __shared__ float smy[TY + 1][TX + 1];
-  __shared__ float snx[TY + 1][TX + 1];
-  __shared__ float sny[TY + 1][TX + 1];
-
-  const int tid = threadIdx.x;
-  const int lx = tid & 63;
-  const int wv = tid >> 6;
-  long t, stride, tend;
-  xcd_chunk(*A.ntiles, t, stride, tend);
-
-  for (; t < tend; t += stride) {
-    const Tile tl = A.tiles[t];
-    if (!A.active[tl.pair]) continue;  // uniform over the block
-    const PairInfo P = A.pairs[tl.pair];
-    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
-    const int gx0 = tl.x0, gy0 = tl.y0;
-    const long off = P.off;
-    const float tau1 = P.tau1, tau2 = P.tau2;
-
-    __syncthreads();  // LDS of the previous tile is no longer read
-
-    // ---- stage a^k (rows -1..TY, cols -1..TX) and old M (low halo) ----
-    const float* __restrict__ a_in = A.in.a + off;
-    for (int idx = tid; idx < (TY + 2) * (TX + 2); idx += BLOCK) {
-      const int ry = idx / (TX + 2), rx = idx - ry * (TX + 2);
-      const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
-      float v = 0.f;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = a_in[(long)gy * pitch + gx];
-      sa[ry][rx] = v;
-    }
-    const float* __restrict__ mx_in = A.in.Mx + off;
-    const float* __restrict__ my_in = A.in.My + off;
-    for (int idx = tid; idx < (TY + 1) * (TX + 1); idx += BLOCK) {
-      const int ry = idx / (TX + 1), rx = idx - ry * (TX + 1);
-      const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
-      float vx = 0.f, vy = 0.f;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        const long o = (long)gy * pitch + gx;
-        vx = mx_in[o];
-        vy = my_in[o];
-        if (BC == 0) {
-          if (gx == nx - 1) vx = 0.f;
-          if (gy == ny - 1) vy = 0.f;
-        }
-      }
-      smx[ry][rx] = vx;
-      smy[ry][rx] = vy;
-    }
-    // own pixels: element-wise planes straight to registers
-    float r_o[PPT], c0[PPT], c1[PPT], x0_o[PPT], x1_o[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int gx = gx0 + lx, gy = gy0 + wv + 4 * k;
-      r_o[k] = c0[k] = c1[k] = x0_o[k] = x1_o[k] = 0.f;
-      if (gx < nx && gy < ny) {
-        const long o = off + (long)gy * pitch + gx;
-        if (RES != R_BAL) r_o[k] = A.in.r[o];
-        if (MODE == 0) {
-          c0[k] = A.c[o];
-        } else {
-          c0[k] = A.src[o];
-          c1[k] = A.dst[o];
-          if (MODE == 1) x0_o[k] = A.in.x0[o];
-          x1_o[k] = A.in.x1[o];
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- new flux over the tile and its low-side halo ----
-    const float t2 = tau1 * tau1;
-    for (int idx = tid; idx < (TY + 1) * (TX + 1); idx += BLOCK) {
-      const int ry = idx / (TX + 1), rx = idx - ry * (TX + 1);
-      const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
-      float nxv = 0.f, nyv = 0.f;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        const float ac = sa[ry][rx];
-        float gxx = ac - sa[ry][rx + 1];
-        float gyy = ac - sa[ry + 1][rx];
-        if (BC == 0) {
-          if (gx == nx - 1) gxx = 0.f;
-          if (gy == ny - 1) gyy = 0.f;
-        }
-        const float vx = smx[ry][rx] - tau1 * gxx;
-        const float vy = smy[ry][rx] - tau1 * gyy;
-        const float n2 = vx * vx + vy * vy;
-        const float s = n2 > t2 ? 1.f - tau1 * rsqrtf(n2) : 0.f;
-        nxv = s * vx;
-        nyv = s * vy;
-      }
-      snx[ry][rx] = nxv;
-      sny[ry][rx] = nyv;
-    }
-    __syncthreads();
-
-    // ---- element-wise steps and the dual update ----
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int ly = wv + 4 * k;
-      const int gx = gx0 + lx, gy = gy0 + ly;
-      if (gx >= nx || gy >= ny) continue;
-      const int ry = ly + 1, rx = lx + 1;
-      const float dmn = snx[ry][rx] - snx[ry][rx - 1] + sny[ry][rx] - sny[ry - 1][rx];
-      const float dmo = smx[ry][rx] - smx[ry][rx - 1] + smy[ry][rx] - smy[ry - 1][rx];
-      const float a = sa[ry][rx];
-      float kold, knew;
-      float x0n = 0.f, x1n = 0.f, rn = 0.f;
-      if (RES == R_P1) rn = shrink1f(r_o[k] + tau1 * a, P.mutau);
-      if (RES == R_P2) rn = (r_o[k] + tau1 * a) * P.inv2mt;
-      if (MODE == 0) {
-        kold = dmo + c0[k];
-        knew = dmn + c0[k];
-      } else if (MODE == 1) {
-        const float th = P.theta;
-        x0n = fmaxf(th * c0[k] + (1.f - th) * (x0_o[k] + tau1 * a), 0.f);
-        x1n = fmaxf(th * c1[k] + (1.f - th) * (x1_o[k] - tau1 * a), 0.f);
-        kold = dmo - x0_o[k] + x1_o[k];
-        knew = dmn - x0n + x1n;
-      } else {
-        const float th = P.theta;
-        x1n = fmaxf(th * c1[k] + (1.f - th) * (x1_o[k] - tau1 * a), 0.f);
-        kold = dmo - c0[k] + x1_o[k];
-        knew = dmn - c0[k] + x1n;
-      }
-      if (RES != R_BAL) {
-        kold -= r_o[k];
-        knew -= rn;
-      }
-      const float an = a + tau2 * (2.f * knew - kold);
-      const long o = off + (long)gy * pitch + gx;
-      A.out.Mx[o] = snx[ry][rx];
-      A.out.My[o] = sny[ry][rx];
-      A.out.a[o] = an;
-      if (RES != R_BAL) A.out.r[o] = rn;
-      if (MODE == 1) A.out.x0[o] = x0n;
-      if (MODE != 0) A.out.x1[o] = x1n;
-    }
-  }
-}
-
-// Vectorised form of cp_iter_kernel: 16 threads per row, each owning 4
-// consecutive pixels (a quad), so every global access of the tile body is
-// one 16-byte load or store.  Rows need not start on a 16-byte boundary:
-// the accesses only need 4-byte alignment, which the memory system serves
-// at full width.  A quad that runs past the end of its row (nx not a
-// multiple of 4) is read and written pixel by pixel, so nothing outside the
-// pair's rows is touched.  LDS rows keep the tile body 16-byte aligned at
-// column 4 (x = 0) with the left halo at column 3 (x = -1) and, for a, the
-// right halo at column 68 (x = 64).  The arithmetic per pixel is that of
-// cp_iter_kernel.
-//
-// NT: the outputs are written with non-temporal stores, which pays once the
-// state no longer fits the Infinity Cache (measured: about +5% at 4096^2 and
-// 8192^2, -15% at 2048^2).  Issuing the next tile's loads before computing
-// the current one was measured too and brought nothing.
-typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
-
-// Quad load: n = number of the 4 pixels inside the row (>= 4: all); pixels
-// past the row end read as 0 and are never dereferenced.
-__device__ __forceinline__ float4 ld4(const float* p, int n) {
-  if (n >= 4) {
-    const f32x4u v = *reinterpret_cast<const f32x4u*>(p);
-    return make_float4(v.x, v.y, v.z, v.w);
-  }
-  float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (n > 0) r.x = p[0];
-  if (n > 1) r.y = p[1];
-  if (n > 2) r.z = p[2];
-  return r;
-}
-
-// Sets component j (0..3) of v to zero; no-op for other j.
-__device__ __forceinline__ void zero_at(float4& v, int j) {
-  if (j == 0) v.x = 0.f;
-  if (j == 1) v.y = 0.f;
-  if (j == 2) v.z = 0.f;
-  if (j == 3) v.w = 0.f;
-}
-
-template <int MODE, int RES, int BC, int TY>
-struct VecStage {
-  static constexpr int NA = (TY + 2 + 15) / 16, NM = (TY + 1 + 15) / 16, PR = TY / 16;
-  float4 a[NA], mx[NM], my[NM];
-  float ha, hmx, hmy;
-  float4 r[PR], c0[PR], c1[PR], x0[PR], x1[PR];
-};
-
-template <int MODE, int RES, int BC, int TY>
-__device__ __forceinline__ void vec_fetch(const IterArgs& A, const PairInfo& P, const Tile& tl,
-                                          VecStage<MODE, RES, BC, TY>& S) {
-  using St = VecStage<MODE, RES, BC, TY>;
-  const int tid = threadIdx.x, q = tid & 15, rr = tid >> 4;
-  const int nx = P.nx, ny = P.ny, pitch = P.pitch, gx0 = tl.x0, gy0 = tl.y0;
-  const long off = P.off;
-  const int gxq = gx0 + 4 * q;
-  const int nin = nx - gxq;  // pixels of this quad inside the row (>= 4: all)
-  const bool quad_in = nin > 0;
-  const float* __restrict__ a_in = A.in.a + off;
-  const float* __restrict__ mx_in = A.in.Mx + off;
-  const float* __restrict__ my_in = A.in.My + off;
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-  for (int i = 0; i < St::NA; ++i) {
-    const int ry = rr + 16 * i, gy = gy0 - 1 + ry;
-    S.a[i] = z;
-    if (ry < TY + 2 && gy >= 0 && gy < ny && quad_in) S.a[i] = ld4(a_in + (long)gy * pitch + gxq, nin);
-  }
-#pragma unroll
-  for (int i = 0; i < St::NM; ++i) {
-    const int ry = rr + 16 * i, gy = gy0 - 1 + ry;
-    S.mx[i] = S.my[i] = z;
-    if (ry < TY + 1 && gy >= 0 && gy < ny && quad_in) {
-      const long o = (long)gy * pitch + gxq;
-      S.mx[i] = ld4(mx_in + o, nin);
-      S.my[i] = ld4(my_in + o, nin);
-      if (BC == 0) {
-        zero_at(S.mx[i], nx - 1 - gxq);
-        if (gy == ny - 1) S.my[i] = z;
-      }
-    }
-  }
-  S.ha = S.hmx = S.hmy = 0.f;
-  if (tid < 2 * (TY + 2)) {  // halo columns of a: x = -1 and x = 64
-    const int ry = tid >> 1, side = tid & 1;
-    const int gx = side ? gx0 + 64 : gx0 - 1, gy = gy0 - 1 + ry;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) S.ha = a_in[(long)gy * pitch + gx];
-  } else if (tid >= 128 && tid < 128 + TY + 1) {  // halo column of M: x = -1
-    const int ry = tid - 128, gx = gx0 - 1, gy = gy0 - 1 + ry;
-    if (gx >= 0 && gy >= 0 && gy < ny) {
-      const long o = (long)gy * pitch + gx;
-      S.hmx = mx_in[o];  // gx < nx - 1 here: never the structurally zero column
-      S.hmy = (BC == 0 && gy == ny - 1) ? 0.f : my_in[o];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < St::PR; ++k) {
-    const int gy = gy0 + rr + 16 * k;
-    S.r[k] = S.c0[k] = S.c1[k] = S.x0[k] = S.x1[k] = z;
-    if (quad_in && gy < ny) {
-      const long o = off + (long)gy * pitch + gxq;
-      if (RES != R_BAL) S.r[k] = ld4(A.in.r + o, nin);
-      if (MODE == 0) {
-        S.c0[k] = ld4(A.c + o, nin);
-      } else {
-        S.c0[k] = ld4(A.src + o, nin);
-        S.c1[k] = ld4(A.dst + o, nin);
-        if (MODE == 1) S.x0[k] = ld4(A.in.x0 + o, nin);
-        S.x1[k] = ld4(A.in.x1 + o, nin);
-      }
-    }
-  }
-}
-
-// Quad store of the first n (>= 4: all) pixels of v.
-template <bool NT>
-__device__ __forceinline__ void st4(float* p, float4 v, int n) {
-  if (n >= 4) {
-    const f32x4u w = {v.x, v.y, v.z, v.w};
-    if (NT)
-      __builtin_nontemporal_store(w, reinterpret_cast<f32x4u*>(p));
-    else
-      *reinterpret_cast<f32x4u*>(p) = w;
-    return;
-  }
-  if (n > 0) p[0] = v.x;
-  if (n > 1) p[1] = v.y;
-  if (n > 2) p[2] = v.z;
-}
-
-template <int MODE, int RES, int BC, int TY, bool NT>
-__global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
-  static_assert(TY % 16 == 0, "16 rows per pass");
-  using St = VecStage<MODE, RES, BC, TY>;
-  constexpr int LA = 72, LM = 68, PR = St::PR;
-  __shared__ __attribute__((aligned(16))) float sa[TY + 2][LA];
-  __shared__ __attribute__((aligned(16))) float smx[TY + 1][LM];
-  __shared__ __attribute__((aligned(16))) float smy[TY + 1][LM];
-  __shared__ __attribute__((aligned(16))) float snx[TY + 1][LM];
-  __shared__ __attribute__((aligned(16))) float sny[TY + 1][LM];
-  const int tid = threadIdx.x;
-  const int q = tid & 15, rr = tid >> 4;
-  long t, stride, tend;
-  xcd_chunk(*A.ntiles, t, stride, tend);
-
-  St cur;
-  for (; t < tend; t += stride) {
-    const Tile tl = A.tiles[t];
-    if (!A.active[tl.pair]) continue;  // uniform over the block
-    const PairInfo P = A.pairs[tl.pair];
-    vec_fetch<MODE, RES, BC, TY>(A, P, tl, cur);
-    {
-      const int nx = P.nx, ny = P.ny, pitch = P.pitch;
-      const int gx0 = tl.x0, gy0 = tl.y0;
-      const long off = P.off;
-      const float tau1 = P.tau1, tau2 = P.tau2;
-      const int gxq = gx0 + 4 * q;
-      const int nin = nx - gxq;
-      const bool quad_in = nin > 0;
-
-      __syncthreads();  // LDS of the previous tile is no longer read
-#pragma unroll
-      for (int i = 0; i < St::NA; ++i)
-        if (rr + 16 * i < TY + 2) *reinterpret_cast<float4*>(&sa[rr + 16 * i][4 + 4 * q]) = cur.a[i];
-#pragma unroll
-      for (int i = 0; i < St::NM; ++i)
-        if (rr + 16 * i < TY + 1) {
-          *reinterpret_cast<float4*>(&smx[rr + 16 * i][4 + 4 * q]) = cur.mx[i];
-          *reinterpret_cast<float4*>(&smy[rr + 16 * i][4 + 4 * q]) = cur.my[i];
-        }
-      if (tid < 2 * (TY + 2)) {
-        sa[tid >> 1][(tid & 1) ? 68 : 3] = cur.ha;
-      } else if (tid >= 128 && tid < 128 + TY + 1) {
-        smx[tid - 128][3] = cur.hmx;
-        smy[tid - 128][3] = cur.hmy;
-      }
-      __syncthreads();
-
-      // ---- new flux over the tile and its low-side halo ----
-      const float t2 = tau1 * tau1;
-      auto shrink = [&](float ac, float ar, float au, float mx, float my, int gx, int gy, float& ox, float& oy) {
-        if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) {
-          ox = oy = 0.f;
-          return;
-        }
-        float gxx = ac - ar, gyy = ac - au;
-        if (BC == 0) {
-          if (gx == nx - 1) gxx = 0.f;
-          if (gy == ny - 1) gyy = 0.f;
-        }
-        const float vx = mx - tau1 * gxx;
-        const float vy = my - tau1 * gyy;
-        const float n2 = vx * vx + vy * vy;
-        const float s = n2 > t2 ? 1.f - tau1 * rsqrtf(n2) : 0.f;
-        ox = s * vx;
-        oy = s * vy;
-      };
-      for (int ry = rr; ry < TY + 1; ry += 16) {
-        const int gy = gy0 - 1 + ry;
-        const int c = 4 + 4 * q;
-        const float4 ac = *reinterpret_cast<const float4*>(&sa[ry][c]);
-        const float4 au = *reinterpret_cast<const float4*>(&sa[ry + 1][c]);
-        const float ar4 = sa[ry][c + 4];
-        const float4 mx = *reinterpret_cast<const float4*>(&smx[ry][c]);
-        const float4 my = *reinterpret_cast<const float4*>(&smy[ry][c]);
-        float4 ox, oy;
-        shrink(ac.x, ac.y, au.x, mx.x, my.x, gxq + 0, gy, ox.x, oy.x);
-        shrink(ac.y, ac.z, au.y, mx.y, my.y, gxq + 1, gy, ox.y, oy.y);
-        shrink(ac.z, ac.w, au.z, mx.z, my.z, gxq + 2, gy, ox.z, oy.z);
-        shrink(ac.w, ar4, au.w, mx.w, my.w, gxq + 3, gy, ox.w, oy.w);
-        *reinterpret_cast<float4*>(&snx[ry][c]) = ox;
-        *reinterpret_cast<float4*>(&sny[ry][c]) = oy;
-      }
-      if (tid < TY + 1) {  // halo column x = -1
-        const int ry = tid;
-        float ox, oy;
-        shrink(sa[ry][3], sa[ry][4], sa[ry + 1][3], smx[ry][3], smy[ry][3], gx0 - 1, gy0 - 1 + ry, ox, oy);
-        snx[ry][3] = ox;
-        sny[ry][3] = oy;
-      }
-      __syncthreads();
-
-      // ---- element-wise steps and the dual update, 4 pixels per thread ----
-#pragma unroll
-      for (int k = 0; k < PR; ++k) {
-        const int ly = rr + 16 * k;
-        const int gy = gy0 + ly;
-        if (!quad_in || gy >= ny) continue;
-        const int ry = ly + 1, c = 4 + 4 * q;
-        const float4 nxc = *reinterpret_cast<const float4*>(&snx[ry][c]);
-        const float nxl = snx[ry][c - 1];
-        const float4 nyc = *reinterpret_cast<const float4*>(&sny[ry][c]);
-        const float4 nyd = *reinterpret_cast<const float4*>(&sny[ry - 1][c]);
-        const float4 mxc = *reinterpret_cast<const float4*>(&smx[ry][c]);
-        const float mxl = smx[ry][c - 1];
-        const float4 myc = *reinterpret_cast<const float4*>(&smy[ry][c]);
-        const float4 myd = *reinterpret_cast<const float4*>(&smy[ry - 1][c]);
-        const float4 a4 = *reinterpret_cast<const float4*>(&sa[ry][c]);
-        const float nxv[5] = {nxl, nxc.x, nxc.y, nxc.z, nxc.w};
-        const float mxv[5] = {mxl, mxc.x, mxc.y, mxc.z, mxc.w};
-        const float nyv[4] = {nyc.x, nyc.y, nyc.z, nyc.w}, nydv[4] = {nyd.x, nyd.y, nyd.z, nyd.w};
-        const float myv[4] = {myc.x, myc.y, myc.z, myc.w}, mydv[4] = {myd.x, myd.y, myd.z, myd.w};
-        const float av[4] = {a4.x, a4.y, a4.z, a4.w};
-        const float rv[4] = {cur.r[k].x, cur.r[k].y, cur.r[k].z, cur.r[k].w};
-        const float c0v[4] = {cur.c0[k].x, cur.c0[k].y, cur.c0[k].z, cur.c0[k].w};
-        const float c1v[4] = {cur.c1[k].x, cur.c1[k].y, cur.c1[k].z, cur.c1[k].w};
-        const float x0v[4] = {cur.x0[k].x, cur.x0[k].y, cur.x0[k].z, cur.x0[k].w};
-        const float x1v[4] = {cur.x1[k].x, cur.x1[k].y, cur.x1[k].z, cur.x1[k].w};
-        float an[4], rn[4], x0n[4], x1n[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float dmn = nxv[e + 1] - nxv[e] + nyv[e] - nydv[e];
-          const float dmo = mxv[e + 1] - mxv[e] + myv[e] - mydv[e];
-          const float a = av[e];
-          float kold, knew;
-          x0n[e] = x1n[e] = rn[e] = 0.f;
-          if (RES == R_P1) rn[e] = shrink1f(rv[e] + tau1 * a, P.mutau);
-          if (RES == R_P2) rn[e] = (rv[e] + tau1 * a) * P.inv2mt;
-          if (MODE == 0) {
-            kold = dmo + c0v[e];
-            knew = dmn + c0v[e];
-          } else if (MODE == 1) {
-            const float th = P.theta;
-            x0n[e] = fmaxf(th * c0v[e] + (1.f - th) * (x0v[e] + tau1 * a), 0.f);
-            x1n[e] = fmaxf(th * c1v[e] + (1.f - th) * (x1v[e] - tau1 * a), 0.f);
-            kold = dmo - x0v[e] + x1v[e];
-            knew = dmn - x0n[e] + x1n[e];
-          } else {
-            const float th = P.theta;
-            x1n[e] = fmaxf(th * c1v[e] + (1.f - th) * (x1v[e] - tau1 * a), 0.f);
-            kold = dmo - c0v[e] + x1v[e];
-            knew = dmn - c0v[e] + x1n[e];
-          }
-          if (RES != R_BAL) {
-            kold -= rv[e];
-            knew -= rn[e];
-          }
-          an[e] = a + tau2 * (2.f * knew - kold);
-        }
-        const long o = off + (long)gy * pitch + gxq;
-        st4<NT>(A.out.Mx + o, nxc, nin);
-        st4<NT>(A.out.My + o, nyc, nin);
-        st4<NT>(A.out.a + o, make_float4(an[0], an[1], an[2], an[3]), nin);
-        if (RES != R_BAL) st4<NT>(A.out.r + o, make_float4(rn[0], rn[1], rn[2], rn[3]), nin);
-        if (MODE == 1) st4<NT>(A.out.x0 + o, make_float4(x0n[0], x0n[1], x0n[2], x0n[3]), nin);
-        if (MODE != 0) st4<NT>(A.out.x1 + o, make_float4(x1n[0], x1n[1], x1n[2], x1n[3]), nin);
-      }
-    }
-  }
-}
-
-// Temporally blocked form: one launch runs `steps` (<= T) iterations with
-// the per-pixel arithmetic of the kernels above.  A workgroup loads its
-// 64 x TH tile with a halo of T pixels on every side (a, Mx, My into LDS, the
-// element-wise planes into registers) and repeats the flux phase and the
-// dual phase over the whole region.  One iteration couples a pixel only to
-// pixels at distance one (D* a looks one pixel up and right, D M one pixel
-// down and left, so a^{k+1} depends on a^k within distance one), so after s
-// steps every value is exact except within s pixels of the region's edge,
-// and a halo of T keeps the owned tile exact for up to T steps.  Pixels
-// outside the grid hold zero and are never updated, as in the single-step
-// kernels.  K(z^k) of each pixel is carried in a register from one step to
-// the next (it is the K(z^{k+1}) of the step before), so the old flux is not
-// needed again and the flux is updated in place.  The last iteration before
-// a convergence check runs in a single-step kernel, which leaves both
-// iterates the check compares in the ping-pong buffers.
-template <int MODE, int RES, int BC, int TH, int T>
-__global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
-  constexpr int RW = TX + 2 * T, RH = TH + 2 * T, NCELL = RW * RH;
-  constexpr int NC = (NCELL + BLOCK - 1) / BLOCK;
-  // LDS rows of RW cells plus a zero border; the rows past the region hold
-  // the cells of the last pass that fall outside it (always written zero)
-  constexpr int LW = RW + 2, LH = (NC * BLOCK + RW - 1) / RW + 2;
-  constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4, F_OWN = 8;  // per-cell flags
-  __shared__ float sa[LH * LW];
-  __shared__ float smx[LH * LW];
-  __shared__ float smy[LH * LW];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < LH * LW; i += BLOCK) sa[i] = smx[i] = smy[i] = 0.f;
-  const int steps = A.steps;
-  long t, stride, tend;
-  xcd_chunk(*A.ntiles, t, stride, tend);
-
-  for (; t < tend; t += stride) {
-    const Tile tl = A.tiles[t];
-    if (!A.active[tl.pair]) continue;  // uniform over the block
-    const PairInfo P = A.pairs[tl.pair];
-    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
-    const long off = P.off;
-    const float tau1 = P.tau1, tau2 = P.tau2, t2 = tau1 * tau1;
-    const int bx = tl.x0 - T, by = tl.y0 - T;  // grid position of region cell (0, 0)
-    int l_[NC], f_[NC];                        // LDS index and flags of each cell
-    float r_[NC], c0_[NC], c1_[NC], x0_[NC], x1_[NC], kp_[NC];
-
-    __syncthreads();  // LDS of the previous tile is no longer read
-    // ---- stage the region ----
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int idx = tid + k * BLOCK;
-      const int ry = idx / RW, rx = idx - ry * RW;
-      const int gx = bx + rx, gy = by + ry;
-      const bool in = ry < RH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-      const int l = (ry + 1) * LW + rx + 1;
-      l_[k] = l;
-      f_[k] = (in ? F_IN : 0) | (BC == 0 && gx == nx - 1 ? F_ZX : 0) | (BC == 0 && gy == ny - 1 ? F_ZY : 0) |
-              (rx >= T && rx < T + TX && ry >= T && ry < T + TH ? F_OWN : 0);
-      float a = 0.f, mx = 0.f, my = 0.f;
-      r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
-      if (in) {
-        const long o = off + (long)gy * pitch + gx;
-        a = A.in.a[o];
-        mx = (BC == 0 && gx == nx - 1) ? 0.f : A.in.Mx[o];
-        my = (BC == 0 && gy == ny - 1) ? 0.f : A.in.My[o];
-        if (RES != R_BAL) r_[k] = A.in.r[o];
-        if (MODE == 0) {
-          c0_[k] = A.c[o];
-        } else {
-          c0_[k] = A.src[o];
-          c1_[k] = A.dst[o];
-          if (MODE == 1) x0_[k] = A.in.x0[o];
-          x1_[k] = A.in.x1[o];
-        }
-      }
-      sa[l] = a;
-      smx[l] = mx;
-      smy[l] = my;
-    }
-    __syncthreads();
-
-    // ---- K(z^k) of every cell ----
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int l = l_[k];
-      const float dmo = smx[l] - smx[l - 1] + smy[l] - smy[l - LW];
-      float kold;
-      if (MODE == 0) kold = dmo + c0_[k];
-      else if (MODE == 1) kold = dmo - x0_[k] + x1_[k];
-      else kold = dmo - c0_[k] + x1_[k];
-      if (RES != R_BAL) kold -= r_[k];
-      kp_[k] = kold;
-    }
-    __syncthreads();  // the flux phase overwrites M, which the neighbours read above
-
-    for (int st = 0; st < steps; ++st) {
-      // ---- new flux: read every cell's inputs, then compute and write ----
-      float ac_[NC], ar_[NC], au_[NC], mx_[NC], my_[NC];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int l = l_[k];
-        ac_[k] = sa[l];
-        ar_[k] = sa[l + 1];
-        au_[k] = sa[l + LW];
-        mx_[k] = smx[l];
-        my_[k] = smy[l];
-      }
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        float gxx = ac_[k] - ar_[k];
-        float gyy = ac_[k] - au_[k];
-        if (BC == 0) {
-          if (f_[k] & F_ZX) gxx = 0.f;
-          if (f_[k] & F_ZY) gyy = 0.f;
-        }
-        const float vx = mx_[k] - tau1 * gxx;
-        const float vy = my_[k] - tau1 * gyy;
-        const float n2 = vx * vx + vy * vy;
-        const float sc = n2 > t2 ? 1.f - tau1 * rsqrtf(n2) : 0.f;
-        const bool in = f_[k] & F_IN;
-        smx[l_[k]] = in ? sc * vx : 0.f;
-        smy[l_[k]] = in ? sc * vy : 0.f;
-      }
-      __syncthreads();
-      // ---- element-wise steps and the dual update ----
-      float nc_[NC], nl_[NC], yc_[NC], yd_[NC], a_[NC];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int l = l_[k];
-        nc_[k] = smx[l];
-        nl_[k] = smx[l - 1];
-        yc_[k] = smy[l];
-        yd_[k] = smy[l - LW];
-        a_[k] = sa[l];
-      }
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const float dmn = nc_[k] - nl_[k] + yc_[k] - yd_[k];
-        const float a = a_[k];
-        float knew, x0n = 0.f, x1n = 0.f, rn = 0.f;
-        if (RES == R_P1) rn = shrink1f(r_[k] + tau1 * a, P.mutau);
-        if (RES == R_P2) rn = (r_[k] + tau1 * a) * P.inv2mt;
-        if (MODE == 0) {
-          knew = dmn + c0_[k];
-        } else if (MODE == 1) {
-          const float th = P.theta;
-          x0n = fmaxf(th * c0_[k] + (1.f - th) * (x0_[k] + tau1 * a), 0.f);
-          x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
-          knew = dmn - x0n + x1n;
-        } else {
-          const float th = P.theta;
-          x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
-          knew = dmn - c0_[k] + x1n;
-        }
-        if (RES != R_BAL) knew -= rn;
-        const bool in = f_[k] & F_IN;
-        sa[l_[k]] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
-        kp_[k] = knew;
-        r_[k] = rn;
-        x0_[k] = x0n;
-        x1_[k] = x1n;
-      }
-      __syncthreads();
-    }
-
-    // ---- write the owned tile ----
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      if ((f_[k] & (F_IN | F_OWN)) != (F_IN | F_OWN)) continue;
-      const int l = l_[k];
-      const int idx = tid + k * BLOCK;
-      const int ry = idx / RW, rx = idx - ry * RW;
-      const long o = off + (long)(by + ry) * pitch + (bx + rx);
-      A.out.Mx[o] = smx[l];
-      A.out.My[o] = smy[l];
-      A.out.a[o] = sa[l];
-      if (RES != R_BAL) A.out.r[o] = r_[k];
-      if (MODE == 1) A.out.x0[o] = x0_[k];
-      if (MODE != 0) A.out.x1[o] = x1_[k];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Block reduction of NS double slots into one partial row (and, if fin is
-// given, into that LDS row too, visible to the whole block on return).
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst,
-                                                   double* fin = nullptr) {
-  __shared__ double red[BLOCK / 64][NS];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    double v = acc[s];
-    const bool mx = (max_mask >> s) & 1u;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double w = __shfl_xor(v, o, 64);
-      v = mx ? fmax(v, w) : v + w;
-    }
-    if (lane == 0) red[wv][s] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NS) {
-    const int s = threadIdx.x;
-    const bool mx = (max_mask >> s) & 1u;
-    double v = red[0][s];
-    for (int w = 1; w < BLOCK / 64; ++w) v = mx ? fmax(v, red[w][s]) : v + red[w][s];
-    dst[s] = v;
-    if (fin) fin[s] = v;
-  }
-  __syncthreads();
-}
-
-// Residuals and certificate terms of the current iterate (K2).  Direct
-// global loads; neighbours come from the L2.  Per-pixel terms in FP32,
-// sums over pixels in FP64.  Runs once per check window.
-template <int MODE, int RES, int BC>
-__global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
-  const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr float nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
-  for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
-    const Tile tl = A.tiles[t];
-    const bool act = A.active[tl.pair] != 0;
-    if (!act && !A.all_pairs) continue;  // uniform
-    const PairInfo P = A.pairs[tl.pair];
-    const bool swap = A.swap_active && act;
-    const Planes C = swap ? A.B : A.A;
-    const Planes Q = swap ? A.A : A.B;  // previous iterate
-    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
-    const float it1 = 1.f / P.tau1;
-    double acc[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-    for (int ly = wv; ly < A.tile_rows; ly += 4) {
-      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
-      if (gx >= nx || gy >= ny) continue;
-      const long o = P.off + (long)gy * pitch + gx;
-      const bool hasR = gx + 1 < nx, hasU = gy + 1 < ny;
-      const bool hasL = gx > 0, hasD = gy > 0;
-      const float a = C.a[o], ap = Q.a[o];
-      const float aR = hasR ? C.a[o + 1] : 0.f, apR = hasR ? Q.a[o + 1] : 0.f;
-      const float aU = hasU ? C.a[o + pitch] : 0.f, apU = hasU ? Q.a[o + pitch] : 0.f;
-      float gxx = a - aR, gyy = a - aU;
-      float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
-      const bool zx = (BC == 0 && gx == nx - 1), zy = (BC == 0 && gy == ny - 1);
-      if (zx) gxx = dgx = 0.f;
-      if (zy) gyy = dgy = 0.f;
-      const float mx = zx ? 0.f : C.Mx[o], my = zy ? 0.f : C.My[o];
-      const float mxp = zx ? 0.f : Q.Mx[o], myp = zy ? 0.f : Q.My[o];
-      const float mxl = hasL ? C.Mx[o - 1] : 0.f;
-      const float myd = hasD ? C.My[o - pitch] : 0.f;
-      const float dm = (mx - mxl) + (my - myd);
-      float x0 = 0.f, x1 = 0.f, e;
-      if (MODE == 0) {
-        e = dm + A.c[o];
-      } else if (MODE == 1) {
-        x0 = C.x0[o];
-        x1 = C.x1[o];
-        e = dm - x0 + x1;
-      } else {
-        x1 = C.x1[o];
-        e = dm - A.src[o] + x1;
-      }
-      float r = 0.f, rp = 0.f;
-      if (RES != R_BAL) {
-        r = C.r[o];
-        rp = Q.r[o];
-      }
-      const float kz = e - r;
-      const float da = ap - a;
-      const float sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
-      float st2 = sx * sx + sy * sy;
-      if (RES != R_BAL) {
-        const float sr = (rp - r) * it1 + da;
-        st2 += sr * sr;
-      }
-      if (MODE == 1) {
-        const float s0 = (Q.x0[o] - x0) * it1 + da;
-        st2 += s0 * s0;
-      }
-      if (MODE != 0) {
-        const float s1 = (Q.x1[o] - x1) * it1 - da;
-        st2 += s1 * s1;
-      }
-      const float g2 = gxx * gxx + gyy * gyy;
-      acc[S_PRES2] += kz * kz;
-      acc[S_STAT2] += st2;
-      acc[S_KA2] += g2 + nid * a * a;
-      acc[S_X0SQ] += x0 * x0;
-      acc[S_X1SQ] += x1 * x1;
-      acc[S_MNORM] += sqrtf(mx * mx + my * my);
-      if (RES == R_P1) {
-        acc[S_RPEN] += fabsf(r);
-        acc[S_EPEN] += fabsf(e);
-      } else if (RES == R_P2) {
-        acc[S_RPEN] += r * r;
-        acc[S_EPEN] += e * e;
-      }
-      if (MODE == 0) acc[S_LIN] += a * A.c[o];
-      if (MODE == 2) acc[S_LIN] -= a * A.src[o];
-      if (MODE == 1) {
-        const float d0 = x0 - A.src[o], d1 = x1 - A.dst[o];
-        acc[S_QUAD] += d0 * d0 + d1 * d1;
-      }
-      if (MODE == 2) {
-        const float d1 = x1 - A.dst[o];
-        acc[S_QUAD] += d1 * d1;
-      }
-      acc[S_MAXG] = fmax(acc[S_MAXG], (double)sqrtf(g2));
-      acc[S_MAXA] = fmax(acc[S_MAXA], (double)fabsf(a));
-      const bool fin = isfinite(a) && isfinite(mx) && isfinite(my) && isfinite(r) && isfinite(x0) &&
-                       isfinite(x1);
-      acc[S_NONFIN] += fin ? 0.0 : 1.0;
-      acc[S_A2] += a * a;
-      acc[S_SUMA] += a;
-    }
-    block_reduce_store(acc, kMaxSlotsCheck, A.partial + (long)t * NS);
-  }
-}
 
 // Input validation, c = q - p, and state initialisation (K8).
 __global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
@@ -985,121 +192,31 @@ __global__ __launch_bounds__(BLOCK) void dual_kernel(DualArgs A) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Launchers
 
-namespace {
-template <int MODE, int RES, int BC>
-hipError_t iter_by_ty(int ty, int grid, const IterArgs& a, hipStream_t s) {
-  switch (ty) {
-    case 4: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 16>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((cp_iter_kernel<MODE, RES, BC, 32>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 116: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 16, false>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 132: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 32, false>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 316: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 16, true>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 332: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 32, true>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 4008: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 8, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 2016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 2>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 8016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 4016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 4032: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 32, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    case 8032: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 32, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <int MODE, int RES, int BC>
-hipError_t occ_by_ty(int ty, int* n) {
-  switch (ty) {
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 4>, BLOCK, 0);
-    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 8>, BLOCK, 0);
-    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 16>, BLOCK, 0);
-    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_kernel<MODE, RES, BC, 32>, BLOCK, 0);
-    case 116: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 16, false>, BLOCK, 0);
-    case 132: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 32, false>, BLOCK, 0);
-    case 316: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 16, true>, BLOCK, 0);
-    case 332: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 32, true>, BLOCK, 0);
-    case 4008: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 8, 4>, BLOCK, 0);
-    case 2016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 2>, BLOCK, 0);
-    case 8016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 8>, BLOCK, 0);
-    case 4016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 4>, BLOCK, 0);
-    case 4032: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 32, 4>, BLOCK, 0);
-    case 8032: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 32, 8>, BLOCK, 0);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int MODE, int RES>
-hipError_t iter_bc(int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
-  return bc == 0 ? iter_by_ty<MODE, RES, 0>(ty, grid, a, s) : iter_by_ty<MODE, RES, 1>(ty, grid, a, s);
-}
-template <int MODE>
-hipError_t iter_res(int res, int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
-  switch (res) {
-    case R_BAL: return iter_bc<MODE, R_BAL>(bc, ty, grid, a, s);
-    case R_P1: return iter_bc<MODE, R_P1>(bc, ty, grid, a, s);
-    case R_P2: return iter_bc<MODE, R_P2>(bc, ty, grid, a, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int MODE, int RES>
-hipError_t occ_bc(int bc, int ty, int* n) {
-  return bc == 0 ? occ_by_ty<MODE, RES, 0>(ty, n) : occ_by_ty<MODE, RES, 1>(ty, n);
-}
-template <int MODE>
-hipError_t occ_res(int res, int bc, int ty, int* n) {
-  switch (res) {
-    case R_BAL: return occ_bc<MODE, R_BAL>(bc, ty, n);
-    case R_P1: return occ_bc<MODE, R_P1>(bc, ty, n);
-    case R_P2: return occ_bc<MODE, R_P2>(bc, ty, n);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int MODE, int RES>
-hipError_t check_bc(int bc, int grid, const CheckArgs& a, hipStream_t s) {
-  if (bc == 0) hipLaunchKernelGGL((check_kernel<MODE, RES, 0>), dim3(grid), dim3(BLOCK), 0, s, a);
-  else hipLaunchKernelGGL((check_kernel<MODE, RES, 1>), dim3(grid), dim3(BLOCK), 0, s, a);
-  return hipGetLastError();
-}
-template <int MODE>
-hipError_t check_res(int res, int bc, int grid, const CheckArgs& a, hipStream_t s) {
-  switch (res) {
-    case R_BAL: return check_bc<MODE, R_BAL>(bc, grid, a, s);
-    case R_P1: return check_bc<MODE, R_P1>(bc, grid, a, s);
-    case R_P2: return check_bc<MODE, R_P2>(bc, grid, a, s);
-  }
-  return hipErrorInvalidValue;
-}
-}  // namespace
 
 hipError_t launch_iter(int mode, int resid, int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
   switch (mode) {
-    case 0: return iter_res<0>(resid, bc, ty, grid, a, s);
-    case 1: return iter_res<1>(resid, bc, ty, grid, a, s);
-    case 2: return iter_res<2>(resid, bc, ty, grid, a, s);
+    case 0: return launch_iter_mode0(resid, bc, ty, grid, a, s);
+    case 1: return launch_iter_mode1(resid, bc, ty, grid, a, s);
+    case 2: return launch_iter_mode2(resid, bc, ty, grid, a, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* n) {
   switch (mode) {
-    case 0: return occ_res<0>(resid, bc, ty, n);
-    case 1: return occ_res<1>(resid, bc, ty, n);
-    case 2: return occ_res<2>(resid, bc, ty, n);
+    case 0: return iter_occupancy_mode0(resid, bc, ty, n);
+    case 1: return iter_occupancy_mode1(resid, bc, ty, n);
+    case 2: return iter_occupancy_mode2(resid, bc, ty, n);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_check(int mode, int resid, int bc, int grid, const CheckArgs& a, hipStream_t s) {
   switch (mode) {
-    case 0: return check_res<0>(resid, bc, grid, a, s);
-    case 1: return check_res<1>(resid, bc, grid, a, s);
-    case 2: return check_res<2>(resid, bc, grid, a, s);
+    case 0: return launch_check_mode0(resid, bc, grid, a, s);
+    case 1: return launch_check_mode1(resid, bc, grid, a, s);
+    case 2: return launch_check_mode2(resid, bc, grid, a, s);
   }
   return hipErrorInvalidValue;
 }

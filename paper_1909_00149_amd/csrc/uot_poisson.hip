@@ -151,9 +151,9 @@ __global__ void infeasibility_kernel(const float* Mx, const float* My, const flo
 }
 
 // Partial sums of ||(M - D* phi)_i||: the flux norm of the repaired flux
-// (phi contiguous, M with row stride pitch).
+// (phi contiguous, M with row stride pitch); aniso: |.|_1 per pixel.
 __global__ __launch_bounds__(256) void repaired_norm_kernel(const float* Mx, const float* My, const float* phi,
-                                                            int nx, int ny, int pitch, double* partial) {
+                                                            int nx, int ny, int pitch, int aniso, double* partial) {
   __shared__ double red[256];
   const long n = (long)nx * ny;
   double acc = 0.0;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void repaired_norm_kernel(const float* Mx, con
     const float gy = j < ny - 1 ? phi[e] - phi[e + nx] : 0.f;
     const float mx = (i < nx - 1 ? Mx[g] : 0.f) - gx;
     const float my = (j < ny - 1 ? My[g] : 0.f) - gy;
-    acc += sqrtf(mx * mx + my * my);
+    acc += aniso ? fabsf(mx) + fabsf(my) : sqrtf(mx * mx + my * my);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -217,9 +217,9 @@ hipError_t launch_infeasibility(const float* Mx, const float* My, const float* s
 int repaired_norm_blocks(int nx, int ny) { return std::min(1024, elem_grid((long)nx * ny)); }
 
 hipError_t launch_repaired_norm(const float* Mx, const float* My, const float* phi, int nx, int ny, int pitch,
-                                double* partial, hipStream_t s) {
+                                int aniso, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(repaired_norm_kernel, dim3(repaired_norm_blocks(nx, ny)), dim3(256), 0, s, Mx, My, phi, nx,
-                     ny, pitch, partial);
+                     ny, pitch, aniso, partial);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ from ._lib import (UOT_WARM_START, UOT_ALLOW_SIGNED, UOT_UNSAFE_STEPS, UOT_NO_GR
                    UOT_AUTOTUNE, UOT_ADAPTIVE_STEPS)
 
 DIST, PROX, PROX_FIXED = 0, 1, 2
+NORM_ISO, NORM_ANISO = 0, 1
 PLANES = ("Mx", "My", "r", "a", "x0", "x1")
 
 
@@ -45,6 +46,8 @@ class Params:
     flags: int = 0
     tile_rows: int = 0
     pitch: int = 0
+    norm: int = 0          # NORM_ISO (the paper's l2,1) or NORM_ANISO (l1,1)
+    reserved: int = 0
 
     def to_c(self):
         return _lib.Params(**{f.name: (int(getattr(self, f.name)) if f.type in ("int", "bool")

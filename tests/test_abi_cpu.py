@@ -59,6 +59,9 @@ def test_status_strings():
     (dict(nx=10, ny=10, pitch=9), _lib.UOT_ERR_SHAPE),
     (dict(flags=_lib.UOT_ALLOW_SIGNED, mode=PROX), _lib.UOT_ERR_ARG),
     (dict(nx=-1), _lib.UOT_ERR_SHAPE),
+    (dict(norm=1), 0),
+    (dict(norm=1, bc=1, mode=PROX), 0),
+    (dict(norm=2), _lib.UOT_ERR_ARG),
 ])
 def test_check_params_codes(kw, code):
     base = dict(nx=16, ny=16, mu=1.0)
