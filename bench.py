@@ -104,14 +104,16 @@ def measured_traffic(name, shape):
     return int(round((rec[1] * FETCH_SCALE + rec[2] * WRITE_SCALE) * 1024))
 
 
-def kernel_name(mode, balanced, shape, residual_p=1):
-    """Instantiated name of the fused kernel for a tile_rows code."""
+def kernel_name(mode, balanced, shape, residual_p=1, norm=0):
+    """Instantiated name of the fused kernel for a tile_rows code (the third
+    template argument is the boundary code: bit 1 the anisotropic norm)."""
     resid = 0 if balanced else residual_p
+    bcn = 2 * norm
     if shape >= 1000:
-        return f"cp_iter_tb_kernel<{mode}, {resid}, 0, {shape % 1000}, {shape // 1000}>"
+        return f"cp_iter_tb_kernel<{mode}, {resid}, {bcn}, {shape % 1000}, {shape // 1000}>"
     if shape >= 100:
-        return f"cp_iter_vec_kernel<{mode}, {resid}, 0, {shape % 100}, {'true' if shape >= 300 else 'false'}>"
-    return f"cp_iter_kernel<{mode}, {resid}, 0, {shape}>"
+        return f"cp_iter_vec_kernel<{mode}, {resid}, {bcn}, {shape % 100}, {'true' if shape >= 300 else 'false'}>"
+    return f"cp_iter_kernel<{mode}, {resid}, {bcn}, {shape}>"
 
 def workload(name):
     from paper_1909_00149_amd import synth
@@ -127,6 +129,12 @@ def workload(name):
                          "l2 source term (p=2), stop at rel_res<=1e-4 or 2000 iterations",
                     pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
                     adaptive=True, residual_p=2)
+    if name == "pair512aniso":
+        p, q = synth.unbalanced_pair(0, side=512)
+        return dict(desc="single unbalanced pair 512x512, 20 blobs, Poisson-noised target, mu=8, anisotropic "
+                         "l1,1 flux norm, stop at rel_res<=1e-4 or 2000 iterations",
+                    pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
+                    adaptive=True, norm=1)
     if name == "balanced64":
         p, q = synth.balanced_pair(0)
         return dict(desc="single balanced pair 64x64, 3 blobs, exactly 500 iterations",
@@ -161,7 +169,8 @@ def cpu_baseline(W, budget_s=20.0):
     from oracle import uot as ora
     p, q = W["pairs"][0]
     prob = ora.Problem(p.astype(np.float64), q.astype(np.float64), mode=W["mode"],
-                       balanced=W["balanced"], mu=W["mu"], rho=W["rho"], residual_p=W.get("residual_p", 1))
+                       balanced=W["balanced"], mu=W["mu"], rho=W["rho"], residual_p=W.get("residual_p", 1),
+                       norm=["iso", "aniso"][W.get("norm", 0)])
     t1, t2 = prob.default_steps()
     with threadpool_limits(limits=1):
         st = ora.initial_state(prob)
@@ -245,14 +254,15 @@ def main():
         src, nx, ny, pitch, offs = G.pack_pitched(imgs_p, align=64)
         dst, _, _, _, _ = G.pack_pitched(imgs_q, align=64)
         prm = G.Params(mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"], tol=W["tol"],
-                       max_iter=W["max_iter"], check_every=20, flags=flags, residual_p=W.get("residual_p", 1))
+                       max_iter=W["max_iter"], check_every=20, flags=flags, residual_p=W.get("residual_p", 1),
+                       norm=W.get("norm", 0))
         state = G.new_state(W["mode"], W["balanced"], src.numel(), dev)
     else:
         src, dst = imgs_p[0], imgs_q[0]
         ny0, nx0 = src.shape
         prm = G.Params(nx=nx0, ny=ny0, mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"],
                        tol=W["tol"], max_iter=W["max_iter"], check_every=20, flags=flags,
-                       residual_p=W.get("residual_p", 1))
+                       residual_p=W.get("residual_p", 1), norm=W.get("norm", 0))
         state = G.new_state(W["mode"], W["balanced"], src.shape, dev)
     solver = G.Solver(prm)
     npx = [int(p.size) for p, _ in pairs]
@@ -298,7 +308,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_vs_algorithmic": round(traffic / alg_bytes, 4) if traffic else None,
-                "kernel": kernel_name(W["mode"], W["balanced"], shape, W.get("residual_p", 1)), "tile_rows": shape,
+                "kernel": kernel_name(W["mode"], W["balanced"], shape, W.get("residual_p", 1), W.get("norm", 0)), "tile_rows": shape,
                 "iterations_per_launch": T, "bytes_per_pixel_iter": bpp, "pixels_per_launch": px_launch,
                 "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5),
                 "alu": {"achieved": round(flops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -319,7 +329,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "pairs": len(pairs),
                    "pixels": int(sum(npx)), "mode": ["DIST", "PROX", "PROX_FIXED"][W["mode"]],
-                   "balanced": W["balanced"], "residual_p": W.get("residual_p", 1)},
+                   "balanced": W["balanced"], "residual_p": W.get("residual_p", 1),
+                   "flux_norm": ["l2,1", "l1,1"][W.get("norm", 0)]},
         "effective_hbm_frac_step": round(value * bpp / (HBM_PEAK_GBS * 1e9), 4),
         "iters_per_step": [int(r["iters"]) for r in reps][:8],
         "time_to_tol_ms": round(1e3 * secs / args.steps, 3),

@@ -680,26 +680,36 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
 // ---------------------------------------------------------------------------
 // Block reduction of NS double slots into one partial row (and, if fin is
 // given, into that LDS row too, visible to the whole block on return).
+// Transposed through LDS: every thread stores its NS values, 16 threads per
+// slot each combine 16 threads' values, then one thread per slot combines
+// the 16 results, all in a fixed order (the result does not depend on
+// timing).  Slots in max_mask are max-reduced, the others summed.
 __device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst,
                                                    double* fin = nullptr) {
-  __shared__ double red[BLOCK / 64][NS];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  static_assert(NS == 16 && BLOCK == 256, "16 slots x 16 groups of 16 threads");
+  __shared__ double buf[NS][BLOCK + 1];
+  __shared__ double red[NS][17];
+  const int tid = threadIdx.x;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    double v = acc[s];
+  for (int s = 0; s < NS; ++s) buf[s][tid] = acc[s];
+  __syncthreads();
+  {
+    const int s = tid >> 4, g = tid & 15;
     const bool mx = (max_mask >> s) & 1u;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double w = __shfl_xor(v, o, 64);
+    double v = buf[s][16 * g];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+      const double w = buf[s][16 * g + k];
       v = mx ? fmax(v, w) : v + w;
     }
-    if (lane == 0) red[wv][s] = v;
+    red[s][g] = v;
   }
   __syncthreads();
-  if (threadIdx.x < NS) {
-    const int s = threadIdx.x;
+  if (tid < NS) {
+    const int s = tid;
     const bool mx = (max_mask >> s) & 1u;
-    double v = red[0][s];
-    for (int w = 1; w < BLOCK / 64; ++w) v = mx ? fmax(v, red[w][s]) : v + red[w][s];
+    double v = red[s][0];
+    for (int g = 1; g < 16; ++g) v = mx ? fmax(v, red[s][g]) : v + red[s][g];
     dst[s] = v;
     if (fin) fin[s] = v;
   }

@@ -117,19 +117,37 @@ __global__ __launch_bounds__(BLOCK) void pair_reduce_kernel(const PairInfo* pair
   const PairInfo P = pairs[b];
   // uniform: a stopped pair keeps its record; the final pass still sums it
   if (do_decide && !dec.active[b] && !dec.final_pass) return;
-  double acc[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-  for (int t = threadIdx.x; t < P.tile_count; t += BLOCK) {
-    const double* row = partial + (long)(P.tile_begin + t) * NS;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const bool mx = (max_mask >> s) & 1u;
-      acc[s] = mx ? fmax(acc[s], row[s]) : acc[s] + row[s];
-    }
-  }
+  // thread (group g, slot s): slot s of the pair's tiles g, g + 16, ..., so a
+  // wave reads four whole partial rows per step
+  static_assert(NS == 16 && BLOCK == 256, "16 slots x 16 groups");
+  __shared__ double red[16][NS + 1];
   __shared__ double fin[NS];
-  block_reduce_store(acc, max_mask, sums + (long)b * NS, fin);
+  const int s = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const bool mx = (max_mask >> s) & 1u;
+  double v = 0.0;
+  const double* row = partial + (long)P.tile_begin * NS + s;
+  int t = g;
+  // eight loads in flight per thread, combined in tile order
+  for (; t + 16 * 7 < P.tile_count; t += 16 * 8) {
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = row[(long)(t + 16 * u) * NS];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v = mx ? fmax(v, w[u]) : v + w[u];
+  }
+  for (; t < P.tile_count; t += 16) {
+    const double w = row[(long)t * NS];
+    v = mx ? fmax(v, w) : v + w;
+  }
+  red[g][s] = v;
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    double u = red[0][s];
+    for (int k = 1; k < 16; ++k) u = mx ? fmax(u, red[k][s]) : u + red[k][s];
+    sums[(long)b * NS + s] = u;
+    fin[s] = u;
+  }
+  __syncthreads();
   if (do_decide && threadIdx.x == 0) decide_pair(dec, b, fin);
 }
 
