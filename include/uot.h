@@ -198,6 +198,34 @@ uot_status uot_solve_batched_pitched(uot_handle *h, int32_t B, const int32_t *nx
 uot_status uot_objective(uot_handle *h, const float *src, const float *dst, const uot_state *st,
                          const uot_state *prev, uot_report *out);
 
+/* Douglas-Rachford splitting of the same problem: a projection-based
+ * alternative to Algorithm 1 (Sec. II-B lists Douglas-Rachford among the
+ * proximal first-order methods; the paper builds on the primal-dual one).  With G the separable terms of the
+ * objective (flux norm, residual penalty, the prox quadratic and x >= 0)
+ * and the constraint K z = b (K z = D M - x0 + x1 - r over the terms of the
+ * mode; DIST: b = p - q; PROX_FIXED: b = s), one iteration is
+ *   z = prox_{gamma G}(w),  y = P(2 z - w),  w <- w + y - z,
+ * with P the exact projection onto {K z = b}: y = u - K^T phi,
+ * (n I + D D*) phi = K u - b, n the identity blocks of K, solved by the
+ * orthonormal DCT-II of the zero-flux grid (the pseudo-inverse when n = 0).
+ * One grid (uot_params nx, ny, contiguous rows), zero-flux boundary only
+ * (bc = 0); mode, balanced, residual_p, norm, mu, rho, max_iter,
+ * check_every, tol and UOT_NO_GRAPH as for uot_solve; w starts at zero.
+ * Stops when ||y - z|| <= tol max(1, ||z||) at a check or at max_iter.
+ * st receives z (the planes the mode needs; a is not used).  gamma > 0 is
+ * the DR step.  Synchronous. */
+typedef struct uot_dr_report {
+  int32_t iters, status;    /* UOT_CONVERGED / UOT_MAX_ITER / UOT_DIVERGED          */
+  double fixed_point_res;   /* ||y - z|| / max(1, ||z||) at the last check         */
+  double objective;         /* G(z)                                                */
+  double infeasibility;     /* ||K z - b||                                         */
+  double seconds;           /* wall time of the call                               */
+  double ms_per_iter;       /* device time per iteration                           */
+} uot_dr_report;
+
+uot_status uot_dr_solve(uot_handle *h, const float *src, const float *dst, uot_state *st, double gamma,
+                        uot_dr_report *rep);
+
 /* Neumann-Poisson solve (alpha I + D D*) phi = rhs on an nx x ny grid with
  * the zero-flux boundary (D D* is the grid Laplacian with Neumann ends; the
  * orthonormal DCT-II diagonalises it, eigenvalues 4 sin^2(pi kx/(2 nx)) +

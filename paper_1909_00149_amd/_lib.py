@@ -34,6 +34,18 @@ class State(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("Mx", "My", "r", "a", "x0", "x1")]
 
 
+class DrReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("fixed_point_res", ctypes.c_double), ("objective", ctypes.c_double),
+                ("infeasibility", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("ms_per_iter", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status_name"] = STATUS_NAMES.get(self.status, str(self.status))
+        return d
+
+
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("rel_gap", ctypes.c_double),
@@ -115,6 +127,8 @@ SIGNATURES = {
                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State),
                                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_int32)]),
+    "uot_dr_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_double, ctypes.c_void_p]),
     "uot_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "uot_init_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,

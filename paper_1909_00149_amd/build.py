@@ -40,6 +40,7 @@ SOURCES = [("uot_iter_mode.hip", "uot_iter_mode0", ["-DUOT_MODE=0"]),
            ("uot_iter_mode.hip", "uot_iter_mode1", ["-DUOT_MODE=1"]),
            ("uot_iter_mode.hip", "uot_iter_mode2", ["-DUOT_MODE=2"]),
            ("uot_kernels.hip", "uot_kernels", []), ("uot_poisson.hip", "uot_poisson", []),
+           ("uot_dr.hip", "uot_dr", []),
            ("uot_host.cpp", "uot_host", []), ("uot_admm_kernels.hip", "uot_admm_kernels", []),
            ("uot_admm_host.cpp", "uot_admm_host", []), ("uotnet_kernels.hip", "uotnet_kernels", []),
            ("uotnet_host.cpp", "uotnet_host", [])]

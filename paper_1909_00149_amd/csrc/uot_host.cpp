@@ -200,6 +200,16 @@ struct uot_handle {
   size_t cap_pw[4] = {0, 0, 0, 0};
   double* d_pp = nullptr;
   size_t cap_pp = 0;
+
+  // Douglas-Rachford: w and u planes (5 each), its partial sums, its graph
+  float* drbuf = nullptr;
+  size_t cap_drbuf = 0;
+  double* d_drp = nullptr;
+  size_t cap_drp = 0;
+  double* h_drp = nullptr;
+  hipGraphExec_t drexec = nullptr;
+  int dr_w = 0;
+  const void* dr_key[4] = {};
   double* h_pp = nullptr;       // pinned
 
   // cached graph of one check window
@@ -208,6 +218,10 @@ struct uot_handle {
 
   ~uot_handle() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (drexec) (void)hipGraphExecDestroy(drexec);
+    if (drbuf) (void)hipFree(drbuf);
+    if (d_drp) (void)hipFree(d_drp);
+    if (h_drp) (void)hipHostFree(h_drp);
     for (auto& p : B)
       if (p) (void)hipFree(p);
     void* dev[] = {cplane, d_tiles, d_live, d_nlive, d_partial, d_pairs, d_sums, d_i32, d_f64, d_invs};
@@ -1205,6 +1219,201 @@ uot_status uot_objective(uot_handle* h, const float* src, const float* dst, cons
     Reporter::fill(p, J.pairs[0], sums.data(), xn, out, need_dual ? duals[0] : 0.0, need_dual, bal[0]);
     out->status = (sums[S_NONFIN] > 0) ? UOT_DIVERGED : UOT_MAX_ITER;
     out->seconds = timer.seconds();
+    return UOT_OK;
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_dr_solve(uot_handle* h, const float* src, const float* dst, uot_state* st, double gamma,
+                        uot_dr_report* rep) {
+  if (!h || !src || !dst || !st || !rep || !(gamma > 0.0) || !std::isfinite(gamma)) return UOT_ERR_ARG;
+  const uot_params& p = h->prm;
+  if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
+  if (p.bc != 0 || (p.pitch != 0 && p.pitch != p.nx)) return UOT_ERR_ARG;
+  if (p.max_iter < 0 || p.check_every < 1) return UOT_ERR_ARG;
+  const int resid = resid_of(p);
+  if (!st->Mx || !st->My || (resid != R_BAL && !st->r) || (p.mode == UOT_PROX && (!st->x0 || !st->x1)) ||
+      (p.mode == UOT_PROX_FIXED && !st->x1))
+    return UOT_ERR_ARG;
+  std::memset(rep, 0, sizeof(*rep));
+  try {
+    Timer timer;
+    const int32_t nx = p.nx, ny = p.ny, pitch = p.nx;
+    const int64_t off = 0;
+    Job J;
+    uot_status s = plan(h, Layout{1, &nx, &ny, &pitch, &off}, J);
+    if (s != UOT_OK) return s;
+    if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+    s = ensure_workspace(h, J);
+    if (s != UOT_OK) return s;
+    HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                          h->stream));
+    // input checks only (the state is neither read nor written here)
+    SetupArgs sa{};
+    sa.src = src;
+    sa.dst = dst;
+    sa.c = h->cplane;
+    sa.st = planes_of(*st);
+    sa.mode = p.mode;
+    sa.resid = resid;
+    sa.bc = p.bc;
+    sa.warm = 0;
+    sa.write_state = 0;
+    sa.write_c = 0;
+    sa.pairs = h->d_pairs;
+    sa.tiles = h->d_tiles;
+    sa.ntiles = (int32_t)J.tiles.size();
+    sa.tile_rows = J.ty;
+    sa.partial = h->d_partial;
+    HIPCHK(launch_setup(aux_grid(h, sa.ntiles), sa, h->stream));
+    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, 0u, h->d_sums, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    s = check_setup_sums(h, J, false);
+    if (s != UOT_OK) return s;
+
+    const long n = (long)nx * ny;
+    s = ensure_poisson(h, (size_t)n);
+    if (s != UOT_OK) return s;
+    const float *cx = nullptr, *cy = nullptr;
+    if ((s = get_dct(h, nx, &cx)) != UOT_OK || (s = get_dct(h, ny, &cy)) != UOT_OK) return s;
+    HIPCHK(grow(&h->drbuf, &h->cap_drbuf, (size_t)n * 10));
+    const int nb = dr_blocks(n);
+    HIPCHK(grow(&h->d_drp, &h->cap_drp, (size_t)3 * nb));
+    if (!h->h_drp) HIPCHK(hipHostMalloc((void**)&h->h_drp, 3 * 256 * sizeof(double), hipHostMallocDefault));
+    DrArgs a{};
+    float* wb = h->drbuf;
+    float* ub = h->drbuf + 5 * n;
+    a.z = planes_of(*st);
+    a.z.a = nullptr;
+    if (resid == R_BAL) a.z.r = nullptr;
+    if (p.mode == UOT_DIST) a.z.x0 = a.z.x1 = nullptr;
+    if (p.mode == UOT_PROX_FIXED) a.z.x0 = nullptr;
+    a.w = Planes{wb, wb + n, a.z.r ? wb + 2 * n : nullptr, nullptr, a.z.x0 ? wb + 3 * n : nullptr,
+                 a.z.x1 ? wb + 4 * n : nullptr};
+    a.u = Planes{ub, ub + n, a.z.r ? ub + 2 * n : nullptr, nullptr, a.z.x0 ? ub + 3 * n : nullptr,
+                 a.z.x1 ? ub + 4 * n : nullptr};
+    a.src = src;
+    a.dst = dst;
+    a.nx = nx;
+    a.ny = ny;
+    a.mode = p.mode;
+    a.resid = resid;
+    a.aniso = p.norm == UOT_NORM_ANISO ? 1 : 0;
+    a.gamma = (float)gamma;
+    a.mu = (float)p.mu;
+    a.rho = (float)p.rho;
+    // identity blocks of K among the variables: K K^T = D D* + nid I
+    const int nid = (a.z.r ? 1 : 0) + (a.z.x0 ? 1 : 0) + (a.z.x1 ? 1 : 0);
+    float* e = h->pw[3];
+    float* phi = h->pw[2];
+    HIPCHK(hipMemsetAsync(h->drbuf, 0, (size_t)n * 5 * sizeof(float), h->stream));
+    auto iteration = [&](bool record) -> uot_status {
+      HIPCHK(launch_dr_prox(a, h->stream));
+      HIPCHK(launch_dr_rhs(a, 0, e, nullptr, h->stream));
+      HIPCHK(poisson_solve(cx, cy, nx, ny, (float)nid, e, phi, h->pw[0], h->pw[1], h->stream));
+      HIPCHK(launch_dr_update(a, phi, record ? 1 : 0, h->d_drp, h->stream));
+      return UOT_OK;
+    };
+    const bool use_graph = !(p.flags & UOT_NO_GRAPH);
+    const int W = p.check_every;
+    const void* key[4] = {src, dst, st->Mx, (const void*)(intptr_t)n};
+    if (use_graph && (!h->drexec || h->dr_w != W || std::memcmp(key, h->dr_key, sizeof(key)) != 0 ||
+                      p.max_iter / W == 0)) {
+      if (h->drexec) (void)hipGraphExecDestroy(h->drexec);
+      h->drexec = nullptr;
+    }
+    int k = 0;
+    bool conv = false;
+    double res = std::nan("");
+    auto test = [&]() -> uot_status {
+      HIPCHK(hipMemcpyAsync(h->h_drp, h->d_drp, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      double d2 = 0.0, z2 = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        d2 += h->h_drp[2 * b];
+        z2 += h->h_drp[2 * b + 1];
+      }
+      res = std::sqrt(d2) / std::max(1.0, std::sqrt(z2));
+      if (!std::isfinite(res)) return UOT_OK;
+      if (p.tol > 0.0 && res <= p.tol) conv = true;
+      return UOT_OK;
+    };
+    struct Events {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      ~Events() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+      }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.e0));
+    HIPCHK(hipEventCreate(&ev.e1));
+    HIPCHK(hipEventRecord(ev.e0, h->stream));
+    while (k + W <= p.max_iter && !conv) {
+      if (use_graph) {
+        if (!h->drexec) {
+          hipGraph_t g = nullptr;
+          HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+          uot_status cs = UOT_OK;
+          for (int i = 0; i < W && cs == UOT_OK; ++i) cs = iteration(i == W - 1);
+          hipError_t ce = hipStreamEndCapture(h->stream, &g);
+          if (cs != UOT_OK || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs != UOT_OK ? cs : UOT_ERR_DEVICE;
+          }
+          hipError_t ie = hipGraphInstantiate(&h->drexec, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (ie != hipSuccess) return UOT_ERR_DEVICE;
+          h->dr_w = W;
+          std::memcpy(h->dr_key, key, sizeof(key));
+        }
+        HIPCHK(hipGraphLaunch(h->drexec, h->stream));
+      } else {
+        for (int i = 0; i < W; ++i) {
+          s = iteration(i == W - 1);
+          if (s != UOT_OK) return s;
+        }
+      }
+      k += W;
+      if ((s = test()) != UOT_OK) return s;
+      if (!std::isfinite(res)) break;
+    }
+    if (!conv && std::isfinite(res) && k < p.max_iter) {
+      const int tail = p.max_iter - k;
+      for (int i = 0; i < tail; ++i) {
+        s = iteration(i == tail - 1);
+        if (s != UOT_OK) return s;
+      }
+      k = p.max_iter;
+      if ((s = test()) != UOT_OK) return s;
+    }
+    HIPCHK(hipEventRecord(ev.e1, h->stream));
+    // objective of z and its constraint violation
+    HIPCHK(launch_dr_objective(a, h->d_drp, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_drp, h->d_drp, 3 * nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double fm = 0.0, pen = 0.0, quad = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      fm += h->h_drp[3 * b];
+      pen += h->h_drp[3 * b + 1];
+      quad += h->h_drp[3 * b + 2];
+    }
+    HIPCHK(launch_dr_rhs(a, 1, nullptr, h->d_drp, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_drp, h->d_drp, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double f2 = 0.0;
+    for (int b = 0; b < nb; ++b) f2 += h->h_drp[b];
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    rep->iters = k;
+    rep->status = !std::isfinite(res) ? UOT_DIVERGED : (conv ? UOT_CONVERGED : UOT_MAX_ITER);
+    rep->fixed_point_res = res;
+    rep->objective = fm + (resid != R_BAL ? p.mu * pen : 0.0) + (p.mode == UOT_DIST ? 0.0 : quad / (2.0 * p.rho));
+    rep->infeasibility = std::sqrt(f2);
+    rep->ms_per_iter = k > 0 ? (double)ms / k : 0.0;
+    rep->seconds = timer.seconds();
     return UOT_OK;
   } catch (...) {
     return UOT_ERR_OOM;

@@ -137,6 +137,20 @@ struct DualArgs {
   double* partial;
 };
 
+// Douglas-Rachford splitting (uot_dr.hip): planes of w (iterate), z (the
+// prox of w, the caller's state) and u = 2 z - w; one contiguous grid.
+struct DrArgs {
+  Planes w, z, u;
+  const float *src, *dst;  // p0/p (x0's centre, DIST source), p1/q
+  int32_t nx, ny, mode, resid, aniso;
+  float gamma, mu, rho;
+};
+int dr_blocks(long n);
+hipError_t launch_dr_prox(const DrArgs& a, hipStream_t s);
+hipError_t launch_dr_rhs(const DrArgs& a, int of_z, float* out, double* partial, hipStream_t s);
+hipError_t launch_dr_update(const DrArgs& a, const float* phi, int record, double* partial, hipStream_t s);
+hipError_t launch_dr_objective(const DrArgs& a, double* partial, hipStream_t s);
+
 // Per-mode instantiations (uot_iter_mode.hip compiled with UOT_MODE = 0, 1, 2).
 hipError_t launch_iter_mode0(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
 hipError_t launch_iter_mode1(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);

@@ -217,6 +217,19 @@ class Solver:
             raise UOTError(rc, "uot_time_iterations_batched")
         return ms.value, shape.value
 
+    def dr_solve(self, src, dst, gamma=1.0, state=None):
+        """uot_dr_solve: Douglas-Rachford splitting with the DCT projection on
+        images of shape (ny, nx); returns (z state, report)."""
+        p = self.params
+        if state is None:
+            state = new_state(p.mode, p.balanced, src.shape, src.device)
+        cs = _cstate(state)
+        rep = _lib.DrReport()
+        rc = self.lib.uot_dr_solve(self._h, _ptr(src), _ptr(dst), ctypes.byref(cs), float(gamma), ctypes.byref(rep))
+        if rc != 0:
+            raise UOTError(rc, "uot_dr_solve")
+        return state, rep.as_dict()
+
     def objective(self, src, dst, state, prev=None):
         cs = _cstate(state)
         cp = _cstate(prev) if prev is not None else None
