@@ -171,7 +171,7 @@ __global__ __launch_bounds__(DB) void dr_objective_kernel(DrArgs A, double* part
   }
 }
 
-int dr_blocks(long n) { return (int)std::min<long>(256, std::max<long>(1, (n + DB - 1) / DB)); }
+int dr_blocks(long n) { return (int)std::min<long>(DR_MAX_BLOCKS, std::max<long>(1, (n + DB - 1) / DB)); }
 
 hipError_t launch_dr_prox(const DrArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(dr_prox_kernel, dim3(dr_blocks((long)a.nx * a.ny)), dim3(DB), 0, s, a);

@@ -1282,7 +1282,8 @@ uot_status uot_dr_solve(uot_handle* h, const float* src, const float* dst, uot_s
     HIPCHK(grow(&h->drbuf, &h->cap_drbuf, (size_t)n * 10));
     const int nb = dr_blocks(n);
     HIPCHK(grow(&h->d_drp, &h->cap_drp, (size_t)3 * nb));
-    if (!h->h_drp) HIPCHK(hipHostMalloc((void**)&h->h_drp, 3 * 256 * sizeof(double), hipHostMallocDefault));
+    if (!h->h_drp)
+      HIPCHK(hipHostMalloc((void**)&h->h_drp, 3 * DR_MAX_BLOCKS * sizeof(double), hipHostMallocDefault));
     DrArgs a{};
     float* wb = h->drbuf;
     float* ub = h->drbuf + 5 * n;

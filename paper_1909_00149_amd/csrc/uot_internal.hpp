@@ -145,6 +145,7 @@ struct DrArgs {
   int32_t nx, ny, mode, resid, aniso;
   float gamma, mu, rho;
 };
+constexpr int DR_MAX_BLOCKS = 1024;  // blocks of the DR kernels (partials per block: 3 at most)
 int dr_blocks(long n);
 hipError_t launch_dr_prox(const DrArgs& a, hipStream_t s);
 hipError_t launch_dr_rhs(const DrArgs& a, int of_z, float* out, double* partial, hipStream_t s);

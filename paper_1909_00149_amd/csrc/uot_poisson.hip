@@ -3,9 +3,10 @@
 // the orthonormal DCT-II diagonalises it with eigenvalues
 //     4 sin^2(pi kx / (2 nx)) + 4 sin^2(pi ky / (2 ny)).
 // The 2-D transform is separable: T = Cy c Cx^T, divide by the eigenvalues,
-// phi = Cy^T T Cx, i.e. four dense products with the DCT matrices, done by
-// an LDS-tiled FP32 GEMM.  Also the kernels that use phi: the Poisson-flux
-// warm start and the feasibility repair of the balanced certificate.
+// phi = Cy^T T Cx, i.e. four dense products with the DCT matrices, done on
+// the FP32 matrix cores (v_mfma_f32_32x32x2f32).  Also the kernels that use
+// phi: the Poisson-flux warm start and the feasibility repair of the
+// balanced certificate.
 #include "uot_internal.hpp"
 
 #include <algorithm>
@@ -13,76 +14,108 @@
 namespace uot {
 
 namespace {
-constexpr int GT = 64;   // output tile
-constexpr int GK = 16;   // k step
+constexpr int GT = 32;   // output tile of one workgroup
+constexpr int GK = 32;   // K slab of one wave
 }  // namespace
 
 // C[M x N] = op(A) op(B), row-major FP32.  op(A) is M x K: A[m*lda+k], or
 // A[k*lda+m] when TA.  op(B) is K x N: B[k*ldb+n], or B[n*ldb+k] when TB.
-// 256 threads, each owning a 4 x 4 block of the 64 x 64 output tile.
+// On v_mfma_f32_32x32x2f32: a workgroup of four waves owns a 32 x 32 output
+// tile, wave w takes the K slabs w, w + 4, ... (32 wide), stages each slab
+// of op(A) and op(B) in its own LDS buffers with global reads along the
+// contiguous dimension, and the four partial tiles are added in a fixed
+// order at the end.  Lane l supplies A[l%32][l/32] and B[l/32][l%32] of
+// each K = 2 step and holds C rows 8(r/4) + 4(l/32) + r%4, column l%32, in
+// accumulator register r.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void sgemm_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
                                                     const float* __restrict__ B, int ldb, float* __restrict__ C,
                                                     int ldc) {
-  __shared__ float As[GK][GT + 4];
-  __shared__ float Bs[GK][GT + 4];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  constexpr int LT = GT + 1;
+  __shared__ float As[4][GK][LT];  // [wave][k][m]
+  __shared__ float Bs[4][GK][LT];  // [wave][k][n]
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    for (int idx = tid; idx < GT * GK; idx += 256) {
-      int mm, kk;
-      if (TA) {
-        kk = idx / GT;
-        mm = idx - kk * GT;
-      } else {
-        mm = idx / GK;
-        kk = idx - mm * GK;
+  f32x16 acc = {};
+  // slab loads: 32 x 32 of op(A) and of op(B) as 256 quads each, four per
+  // lane, along the contiguous dimension; whole quads are read with one
+  // 16-byte load where the leading dimension allows it
+  const bool qa = (lda & 3) == 0 && ((uintptr_t)A & 15) == 0;
+  const bool qb = (ldb & 3) == 0 && ((uintptr_t)B & 15) == 0;
+  float ra[4][4], rb[4][4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = l + 64 * q, major = idx >> 3, c = 4 * (idx & 7);
+      // op(A): !TA rows m = m0 + major, k = k0 + c..c+3; TA rows k = k0 + major, m = m0 + c..c+3
+      {
+        const int r0 = TA ? k0 + major : m0 + major, c0 = TA ? m0 + c : k0 + c;
+        const int rl = TA ? K : M, cl = TA ? M : K;
+        const float* src = A + (long)r0 * lda + c0;
+        if (qa && r0 < rl && c0 + 3 < cl) {
+          const float4 v = *reinterpret_cast<const float4*>(src);
+          ra[q][0] = v.x, ra[q][1] = v.y, ra[q][2] = v.z, ra[q][3] = v.w;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) ra[q][t] = (r0 < rl && c0 + t < cl) ? src[t] : 0.f;
+        }
       }
-      const int m = m0 + mm, k = k0 + kk;
-      float v = 0.f;
-      if (m < M && k < K) v = TA ? A[(long)k * lda + m] : A[(long)m * lda + k];
-      As[kk][mm] = v;
-    }
-    for (int idx = tid; idx < GT * GK; idx += 256) {
-      int nn, kk;
-      if (TB) {
-        nn = idx / GK;
-        kk = idx - nn * GK;
-      } else {
-        kk = idx / GT;
-        nn = idx - kk * GT;
+      // op(B): !TB rows k = k0 + major, n = n0 + c..c+3; TB rows n = n0 + major, k = k0 + c..c+3
+      {
+        const int r0 = TB ? n0 + major : k0 + major, c0 = TB ? k0 + c : n0 + c;
+        const int rl = TB ? N : K, cl = TB ? K : N;
+        const float* src = B + (long)r0 * ldb + c0;
+        if (qb && r0 < rl && c0 + 3 < cl) {
+          const float4 v = *reinterpret_cast<const float4*>(src);
+          rb[q][0] = v.x, rb[q][1] = v.y, rb[q][2] = v.z, rb[q][3] = v.w;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) rb[q][t] = (r0 < rl && c0 + t < cl) ? src[t] : 0.f;
+        }
       }
-      const int n = n0 + nn, k = k0 + kk;
-      float v = 0.f;
-      if (n < N && k < K) v = TB ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
-      Bs[kk][nn] = v;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = l + 64 * q, major = idx >> 3, c = 4 * (idx & 7);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (TA) As[wv][major][c + t] = ra[q][t];
+        else As[wv][c + t][major] = ra[q][t];
+        if (TB) Bs[wv][c + t][major] = rb[q][t];
+        else Bs[wv][major][c + t] = rb[q][t];
+      }
+    }
+  };
+  load(wv * GK);
+  for (int kb = 0; kb < K; kb += 4 * GK) {  // the same trip count for every wave
+    store();
     __syncthreads();
+    if (kb + 4 * GK < K) load(kb + 4 * GK + wv * GK);  // next slab in flight during the products
 #pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    for (int s2 = 0; s2 < GK / 2; ++s2) {
+      const int k = 2 * s2 + (l >> 5);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[wv][k][l & 31], Bs[wv][k][l & 31], acc, 0, 0, 0);
     }
     __syncthreads();
   }
+  // the four partial tiles, added in wave order
+  float* part = &As[0][0][0];  // 4 x 32 x 33 floats, free after the loop
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + ty + 16 * i;
-    if (m >= M) continue;
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), col = l & 31;
+    part[(wv * GT + row) * LT + col] = acc[r];
+  }
+  __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tx + 16 * j;
-      if (n < N) C[(long)m * ldc + n] = acc[i][j];
-    }
+  for (int q = 0; q < GT * GT / 256; ++q) {
+    const int idx = threadIdx.x + 256 * q, row = idx >> 5, col = idx & 31;
+    const float v = ((part[(0 * GT + row) * LT + col] + part[(1 * GT + row) * LT + col]) +
+                     part[(2 * GT + row) * LT + col]) + part[(3 * GT + row) * LT + col];
+    const int m = m0 + row, n = n0 + col;
+    if (m < M && n < N) C[(long)m * ldc + n] = v;
   }
 }
 
