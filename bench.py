@@ -386,10 +386,11 @@ def run_uotdf(args, dev):
         solver.close()
     r512 = next(r for r in rows if r["side"] == 512)
     value = 512 * 512 / (r512["ms_per_iter"] * 1e-3)
-    # per ADMM iteration at 512^2: the s/x/centre step streams 9 planes, the
-    # multiplier step 7, the prox pass 48 bytes per pixel (one-argument-fixed,
-    # unbalanced): 112 algorithmic bytes per pixel
-    bpp = 112
+    # per ADMM iteration at 512^2 inside a check window: the multiplier step
+    # fused with the next s/x/centre step streams 11 planes (reads x s z a b
+    # y, writes a b s x p), the prox pass 48 bytes per pixel (one-argument-
+    # fixed, unbalanced): 92 algorithmic bytes per pixel
+    bpp = 92
     achieved = bpp * 512 * 512 / (r512["ms_per_iter"] * 1e-3) / 1e9
     out = {
         "metric": "UOT-DF ADMM pixel-iterations/s at 512^2 (Algorithm 2 run-time study)",
@@ -401,7 +402,7 @@ def run_uotdf(args, dev):
         "sizes": rows,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "one ADMM iteration (df_sx_kernel + cp_iter_vec_kernel<2,1,0,16,false> + df_ab_kernel)",
+                     "kernel": "one ADMM iteration (df_absx_kernel + cp_iter_vec_kernel<2,1,0,16,false>)",
                      "bytes_per_pixel_iter": bpp},
     }
     if not args.no_cpu_baseline:

@@ -91,12 +91,16 @@ Planes prox_planes(uotdf_handle* h, int c) {
   return Planes{q[0], q[1], h->prm.balanced ? nullptr : q[2], q[3], nullptr, q[4]};
 }
 
-// One ADMM iteration (see the file comment); record: leave residual partials.
-uot_status enqueue_iteration(uotdf_handle* h, const float* y, const float* phi, const float* s0, bool record) {
+DfArgs df_args(uotdf_handle* h, const float* y, const float* phi, bool record) {
   const uotdf_params& P = h->prm;
-  DfArgs A{h->n, y, phi, h->s, h->x, h->a, h->b, h->p, h->zo, h->st[h->parity][4], (float)P.rho,
-           (float)(P.lam / (2.0 * P.rho)), record ? 1 : 0, h->d_partial};
-  DFCHK(launch_df_sx(A, h->stream));
+  return DfArgs{h->n, y, phi, h->s, h->x, h->a, h->b, h->p, h->zo, h->st[h->parity][4], (float)P.rho,
+                (float)(P.lam / (2.0 * P.rho)), record ? 1 : 0, h->d_partial};
+}
+
+// The prox passes of one ADMM iteration (Algorithm 1 in the one-argument-
+// fixed mode, warm-started from the state copy of the current parity).
+uot_status enqueue_prox(uotdf_handle* h, const float* s0) {
+  const uotdf_params& P = h->prm;
   for (int left = P.prox_iters; left > 0;) {
     const int k = std::min(h->T, left);
     IterArgs it{prox_planes(h, h->parity), prox_planes(h, h->parity ^ 1), nullptr, s0, h->p, h->d_pair,
@@ -105,17 +109,21 @@ uot_status enqueue_iteration(uotdf_handle* h, const float* y, const float* phi, 
     h->parity ^= 1;
     left -= k;
   }
-  A.z = h->st[h->parity][4];
-  DFCHK(launch_df_ab(A, h->stream));
   return UOT_OK;
 }
 
 // W ADMM iterations with residual partials on the last, then the reduction
 // and the copy of the three sums to the host (not waited for).
 uot_status enqueue_window(uotdf_handle* h, int W, const float* y, const float* phi, const float* s0) {
+  // s- and x-steps of the first iteration; then per iteration the prox
+  // passes and the multiplier steps, fused with the next iteration's s- and
+  // x-steps inside the window
+  DFCHK(launch_df_sx(df_args(h, y, phi, W == 1), h->stream));
   for (int i = 0; i < W; ++i) {
-    uot_status s = enqueue_iteration(h, y, phi, s0, i == W - 1);
+    uot_status s = enqueue_prox(h, s0);
     if (s != UOT_OK) return s;
+    if (i + 1 < W) DFCHK(launch_df_absx(df_args(h, y, phi, i + 2 == W), h->stream));
+    else DFCHK(launch_df_ab(df_args(h, y, phi, true), h->stream));
   }
   DFCHK(launch_df_reduce(h->d_partial, h->nblocks, h->d_sums, h->stream));
   DFCHK(hipMemcpyAsync(h->h_sums, h->d_sums, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -68,6 +68,7 @@ hipError_t launch_rp_sub(long n, const float* a, const float* b, float* out, hip
 hipError_t launch_rp_validate(long n, const float* y, const float* phi, double* partial, int blocks, hipStream_t s);
 hipError_t launch_df_sx(const DfArgs& a, hipStream_t s);
 hipError_t launch_df_ab(const DfArgs& a, hipStream_t s);
+hipError_t launch_df_absx(const DfArgs& a, hipStream_t s);  // df_ab of one iteration + df_sx of the next
 hipError_t launch_df_reduce(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_df_validate(long n, const float* y, const float* phi, const float* s0, double* partial,
                               hipStream_t s);
