@@ -460,10 +460,15 @@ RpArgs rp_args(rpca_handle* h, const float* y, const float* phi, bool record) {
   return a;
 }
 
-uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, bool record) {
+// One ADMM iteration, i-th of a window of W.  The S-, L- and X-steps of
+// the first iteration run alone; the multiplier steps of every other
+// iteration run fused with the next iteration's S-, L- and X-steps, and
+// the window's last multiplier steps alone with the residual partials.
+uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, int i, int W) {
   const rpca_params& P = h->prm;
+  const bool record = i == W - 1;
   RpArgs a = rp_args(h, y, phi, record);
-  DFCHK(launch_rp_sx(a, h->bx, h->stream));
+  if (i == 0) DFCHK(launch_rp_sx(a, h->bx, h->stream));
   DFCHK(launch_rp_gram(a, h->gblocks, h->d_gpart, h->stream));
   DFCHK(launch_rp_gram_reduce(h->d_gpart, h->gblocks, P.frames, h->d_G, h->stream));
   DFCHK(launch_rp_eig(h->d_G, P.frames, P.gam / P.rho, h->d_V, h->d_rot, h->d_lam, h->d_Wm, h->d_sweeps,
@@ -479,7 +484,12 @@ uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, bool r
   }
   a.Z = h->st[h->parity][4];
   a.W = h->st[h->parity][5];
-  DFCHK(launch_rp_dual(a, h->bx, h->stream));
+  if (record) {
+    DFCHK(launch_rp_dual(a, h->bx, h->stream));
+  } else {
+    a.record = i + 1 == W - 1 ? 1 : 0;  // the next iteration's S/L/X part
+    DFCHK(launch_rp_dualsx(a, h->bx, h->stream));
+  }
   return UOT_OK;
 }
 
@@ -492,7 +502,7 @@ RpCounts rp_counts(const rpca_handle* h) {
 
 uot_status rp_window(rpca_handle* h, int W, const float* y, const float* phi) {
   for (int i = 0; i < W; ++i) {
-    uot_status s = rp_iteration(h, y, phi, i == W - 1);
+    uot_status s = rp_iteration(h, y, phi, i, W);
     if (s != UOT_OK) return s;
   }
   DFCHK(launch_rp_reduce(h->d_partial, h->pstride, rp_counts(h), h->d_sums, h->stream));

@@ -64,6 +64,7 @@ hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2*
 hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s);
 hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s);  // grid bx x T
 hipError_t launch_rp_reduce(const double* partial, int pstride, const RpCounts& cnt, double* out, hipStream_t s);
+hipError_t launch_rp_dualsx(const RpArgs& a, int bx, hipStream_t s);  // rp_dual + the next rp_sx
 hipError_t launch_rp_sub(long n, const float* a, const float* b, float* out, hipStream_t s);
 hipError_t launch_rp_validate(long n, const float* y, const float* phi, double* partial, int blocks, hipStream_t s);
 hipError_t launch_df_sx(const DfArgs& a, hipStream_t s);

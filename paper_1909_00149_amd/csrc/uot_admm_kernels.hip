@@ -700,6 +700,93 @@ __global__ __launch_bounds__(RB) void rp_dual_kernel(RpArgs A) {
   }
 }
 
+// The multiplier steps of one iteration fused with the S-, L- and X-steps
+// of the next (within a check window): A, b, c (and the - pairs' b, c)
+// updated as in rp_dual_kernel, then the next iteration's steps as in
+// rp_sx_kernel from the updated multipliers, with the same expressions (the
+// iterates are the same bit for bit) and each plane streamed once.
+// record: the next iteration is the last of its window.
+template <bool SGN>
+__global__ __launch_bounds__(RB) void rp_dualsx_kernel(RpArgs A) {
+  double dx2 = 0.0;
+  const int t = blockIdx.y;
+  const long npx = A.npx, fe = (long)t * npx, fw = (long)(t - 1) * npx, mo = A.mo;
+  const bool hz = t < A.T - 1, hw = t > 0;
+  const float rho = A.rho, lam = A.lam;
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < npx; i += (long)gridDim.x * RB) {
+    const long e = fe + i, ew = fw + i;
+    const float x = A.X[e], so = A.S[e], l = A.L[e];
+    const float smo = SGN ? A.Sm[e] : 0.f;
+    // multiplier steps of the finished iteration
+    const float a = A.A[e] + (SGN ? x - so + smo - l : x - so - l);
+    A.A[e] = a;
+    float z = 0.f, w = 0.f, bz = 0.f, cw = 0.f, zm = 0.f, wm = 0.f, bm = 0.f, cm = 0.f;
+    if (hz) {
+      z = A.Z[e];
+      bz = A.B[e] + (z - so);
+      A.B[e] = bz;
+      if (SGN) {
+        zm = A.Z[mo + e];
+        bm = A.B[mo + e] + (zm - smo);
+        A.B[mo + e] = bm;
+      }
+    }
+    if (hw) {
+      w = A.W[ew];
+      cw = A.C[ew] + (w - so);
+      A.C[ew] = cw;
+      if (SGN) {
+        wm = A.W[mo + ew];
+        cm = A.C[mo + ew] + (wm - smo);
+        A.C[mo + ew] = cm;
+      }
+    }
+    // S-, L-, X-steps of the next iteration
+    float k = x - l + a, sig = 1.f;
+    if (SGN) k += smo;
+    if (hz) {
+      k += z + bz;
+      sig += 1.f;
+    }
+    if (hw) {
+      k += w + cw;
+      sig += 1.f;
+    }
+    const float s = fmaxf(k / sig - lam / (rho * sig), 0.f);
+    float sm = 0.f;
+    if (SGN) {
+      float km = l - x + s - a;
+      if (hz) km += zm + bm;
+      if (hw) km += wm + cm;
+      sm = fmaxf(km / sig - lam / (rho * sig), 0.f);
+    }
+    const float ln = fmaxf(0.5f * (A.Tn[e] - A.D[e] + x - s + sm + a), 0.f);
+    const float ph = A.phi ? A.phi[e] : 1.f;
+    const float xn = (ph * A.y[e] + rho * (s - sm + ln - a)) / (ph * ph + rho);
+    A.S[e] = s;
+    if (SGN) A.Sm[e] = sm;
+    A.L[e] = ln;
+    A.X[e] = xn;
+    if (hz) A.P0[e] = s - bz;
+    if (hw) A.P1[ew] = s - cw;
+    if (SGN) {
+      if (hz) A.P0[mo + e] = sm - bm;
+      if (hw) A.P1[mo + ew] = sm - cm;
+    }
+    if (A.record) {
+      const float d = xn - x;
+      dx2 += (double)d * d;
+      if (hz) A.zo[e] = z;
+      if (hw) A.wo[ew] = w;
+      if (SGN) {
+        if (hz) A.zo[mo + e] = zm;
+        if (hw) A.wo[mo + ew] = wm;
+      }
+    }
+  }
+  if (A.record) block_sum(dx2, A.partial + 1 * A.pstride + blockIdx.y * gridDim.x + blockIdx.x);
+}
+
 // out = a - b (the signed sparse part S+ - S-).
 __global__ __launch_bounds__(RB) void rp_sub_kernel(long n, const float* a, const float* b, float* out) {
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) out[i] = a[i] - b[i];
@@ -789,6 +876,12 @@ hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s) {
 hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s) {
   if (a.Sm) hipLaunchKernelGGL(rp_dual_kernel<true>, dim3(bx, a.T), dim3(RB), 0, s, a);
   else hipLaunchKernelGGL(rp_dual_kernel<false>, dim3(bx, a.T), dim3(RB), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rp_dualsx(const RpArgs& a, int bx, hipStream_t s) {
+  if (a.Sm) hipLaunchKernelGGL(rp_dualsx_kernel<true>, dim3(bx, a.T), dim3(RB), 0, s, a);
+  else hipLaunchKernelGGL(rp_dualsx_kernel<false>, dim3(bx, a.T), dim3(RB), 0, s, a);
   return hipGetLastError();
 }
 
