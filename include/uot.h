@@ -86,6 +86,10 @@ enum { UOT_CONVERGED = 0, UOT_MAX_ITER = 1, UOT_DIVERGED = 2 };
 #define UOT_NO_GRAPH     0x10u /* launch kernels directly instead of replaying graphs */
 #define UOT_AUTOTUNE     0x20u /* time the tile shapes on first use of a size class   */
 #define UOT_ADAPTIVE_STEPS 0x40u /* rebalance tau1/tau2 at each check (needs tol > 0)  */
+#define UOT_RECORD_HISTORY 0x80u /* keep (iterations, rel_res) of every check of the last
+                                    solve, per pair (uot_history); the checks then run
+                                    every window even with tol <= 0, and the host waits
+                                    for each window                                      */
 
 typedef struct uot_params {
   int32_t nx, ny;       /* grid of uot_solve (ignored by uot_solve_batched)           */
@@ -197,6 +201,14 @@ uot_status uot_solve_batched_pitched(uot_handle *h, int32_t B, const int32_t *nx
  * Uses the handle's grid. */
 uot_status uot_objective(uot_handle *h, const float *src, const float *dst, const uot_state *st,
                          const uot_state *prev, uot_report *out);
+
+/* The convergence history of the last uot_solve / uot_solve_batched on this
+ * handle made with UOT_RECORD_HISTORY: for pair `pair`, the iteration count
+ * and rel_res (as in uot_report) at every check while the pair was running,
+ * the final evaluation included.  Writes min(n, cap) records into the host
+ * arrays iters and rel_res (either may be NULL) and the total into *n.
+ * UOT_ERR_ARG for a pair outside the last solve or no recorded solve. */
+uot_status uot_history(uot_handle *h, int32_t pair, int32_t *iters, double *rel_res, int32_t cap, int32_t *n);
 
 /* Douglas-Rachford splitting of the same problem: a projection-based
  * alternative to Algorithm 1 (Sec. II-B lists Douglas-Rachford among the

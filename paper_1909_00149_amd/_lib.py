@@ -16,6 +16,7 @@ UOT_UNSAFE_STEPS = 0x8
 UOT_NO_GRAPH = 0x10
 UOT_AUTOTUNE = 0x20
 UOT_ADAPTIVE_STEPS = 0x40
+UOT_RECORD_HISTORY = 0x80
 
 
 class Params(ctypes.Structure):
@@ -127,6 +128,8 @@ SIGNATURES = {
                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State),
                                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_int32)]),
+    "uot_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "uot_dr_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_double, ctypes.c_void_p]),
     "uot_poisson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,

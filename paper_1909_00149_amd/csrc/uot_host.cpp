@@ -201,6 +201,11 @@ struct uot_handle {
   double* d_pp = nullptr;
   size_t cap_pp = 0;
 
+  // per-pair (iterations, rel_res) at every check of the last solve with
+  // UOT_RECORD_HISTORY
+  std::vector<std::vector<std::pair<int32_t, double>>> hist;
+  bool have_hist = false;
+
   // Douglas-Rachford: w and u planes (5 each), its partial sums, its graph
   float* drbuf = nullptr;
   size_t cap_drbuf = 0;
@@ -910,7 +915,8 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   L.bwd = IterArgs{Bp, A, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, d_active};
   L.chk = CheckArgs{A, Bp, 0, 0, cptr, src, dst, h->d_pairs, h->d_tiles, (int32_t)J.tiles.size(), J.ty, d_active,
                     h->d_partial};
-  const bool check = p.tol > 0.0;
+  const bool record = (p.flags & UOT_RECORD_HISTORY) != 0;
+  const bool check = p.tol > 0.0 || record;
   int W = std::max(2, p.check_every > 0 ? p.check_every : 20);
   W += W & 1;
   const bool adaptive = check && (p.flags & UOT_ADAPTIVE_STEPS);
@@ -929,7 +935,12 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     if (s != UOT_OK) return s;
   }
   // windows: the device decides convergence; the host polls every few windows
-  const int poll = std::max(1, 256 / W);
+  // (every window when the history is recorded)
+  const int poll = record ? 1 : std::max(1, 256 / W);
+  h->have_hist = record;
+  h->hist.assign(record ? B : 0, {});
+  std::vector<double> hrel(record ? B : 0);
+  std::vector<int32_t> hprev_active(record ? B : 0);
   int done_iters = 0;  // iterations of pairs that never stop early (fixed mode)
   int w = 0;
   while (w < nwin && n_active > 0) {
@@ -944,9 +955,16 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     w += burst;
     done_iters += burst * W;
     if (check) {
+      if (record) {
+        for (int b = 0; b < B; ++b) hprev_active[b] = h_active[b];
+        HIPCHK(hipMemcpyAsync(hrel.data(), d_rel, B * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      }
       HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                             h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
+      if (record)
+        for (int b = 0; b < B; ++b)
+          if (hprev_active[b]) h->hist[b].emplace_back(h->h_i32[B + b], hrel[b]);
       int now = 0;
       for (int b = 0; b < B; ++b) now += h_active[b] ? 1 : 0;
       if (now == 0) {
@@ -1021,6 +1039,9 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     r.seconds = secs;
     r.tile_rows = J.shape;
     if (r.status == UOT_CONVERGED && relres[b] == 0.0) r.rel_res = 0.0;
+    // the final evaluation, unless the pair stopped at an earlier check
+    if (record && (h->hist[b].empty() || h->hist[b].back().first != r.iters))
+      h->hist[b].emplace_back(r.iters, r.rel_res);
   }
   return UOT_OK;
 }
@@ -1223,6 +1244,18 @@ uot_status uot_objective(uot_handle* h, const float* src, const float* dst, cons
   } catch (...) {
     return UOT_ERR_OOM;
   }
+}
+
+uot_status uot_history(uot_handle* h, int32_t pair, int32_t* iters, double* rel_res, int32_t cap, int32_t* n) {
+  if (!h || !n || cap < 0 || !h->have_hist || pair < 0 || pair >= (int32_t)h->hist.size()) return UOT_ERR_ARG;
+  const auto& v = h->hist[pair];
+  *n = (int32_t)v.size();
+  const int32_t m = std::min<int32_t>(cap, (int32_t)v.size());
+  for (int32_t i = 0; i < m; ++i) {
+    if (iters) iters[i] = v[i].first;
+    if (rel_res) rel_res[i] = v[i].second;
+  }
+  return UOT_OK;
 }
 
 uot_status uot_dr_solve(uot_handle* h, const float* src, const float* dst, uot_state* st, double gamma,

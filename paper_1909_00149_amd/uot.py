@@ -13,7 +13,7 @@ import torch
 
 from . import _lib
 from ._lib import (UOT_WARM_START, UOT_ALLOW_SIGNED, UOT_UNSAFE_STEPS, UOT_NO_GRAPH,  # noqa: F401
-                   UOT_AUTOTUNE, UOT_ADAPTIVE_STEPS)
+                   UOT_AUTOTUNE, UOT_ADAPTIVE_STEPS, UOT_RECORD_HISTORY)
 
 DIST, PROX, PROX_FIXED = 0, 1, 2
 NORM_ISO, NORM_ANISO = 0, 1
@@ -216,6 +216,22 @@ class Solver:
         if rc != 0:
             raise UOTError(rc, "uot_time_iterations_batched")
         return ms.value, shape.value
+
+    def history(self, pair=0):
+        """uot_history: (iterations, rel_res) at every check of the last solve
+        made with UOT_RECORD_HISTORY, for one pair; two numpy arrays."""
+        import numpy as np
+        n = ctypes.c_int32(0)
+        rc = self.lib.uot_history(self._h, int(pair), None, None, 0, ctypes.byref(n))
+        if rc != 0:
+            raise UOTError(rc, "uot_history")
+        it = np.zeros(n.value, np.int32)
+        rr = np.zeros(n.value, np.float64)
+        rc = self.lib.uot_history(self._h, int(pair), it.ctypes.data_as(ctypes.c_void_p),
+                                  rr.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n))
+        if rc != 0:
+            raise UOTError(rc, "uot_history")
+        return it, rr
 
     def dr_solve(self, src, dst, gamma=1.0, state=None):
         """uot_dr_solve: Douglas-Rachford splitting with the DCT projection on

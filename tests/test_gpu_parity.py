@@ -366,3 +366,31 @@ def test_objective_entry_point(dev):
     assert rel(obj["objective"], rep["objective"]) <= 1e-12
     assert rel(obj["primal"], rep["primal"]) <= 1e-12
     assert rel(obj["dual"], rep["dual"]) <= 1e-9
+
+
+def test_recorded_history_matches_the_oracle(dev):
+    """UOT_RECORD_HISTORY: rel_res at every check (here every 20 iterations,
+    tol 0 so all 200 iterations run) equals the oracle's relative residuals
+    at the same iterations, and the last record is the report's."""
+    p, q = pair_inputs((31, 45), 77, DIST)
+    prm = G.Params(nx=45, ny=31, mode=DIST, mu=1.3, max_iter=200, check_every=20, tol=0.0,
+                   flags=G.UOT_RECORD_HISTORY)
+    s = G.Solver(prm)
+    st, rep = s.solve(to_dev(p, dev), to_dev(q, dev))
+    torch.cuda.synchronize()
+    it, rr = s.history(0)
+    assert list(it) == list(range(20, 201, 20))
+    assert rr[-1] == rep["rel_res"]
+    prob = ora.Problem(p.astype(np.float64), q.astype(np.float64), mode=DIST, mu=1.3)
+    t1, t2 = prob.default_steps()
+    ref = ora.initial_state(prob)
+    prev = ref
+    k = 0
+    for target, got in zip(it, rr):
+        while k < target:
+            prev, ref = ref, ora.iterate(prob, ref, np.float32(t1), np.float32(t2))
+            k += 1
+        want = max(ora.relative_residuals(prob, prev, ref, np.float32(t1)))
+        assert abs(got - want) <= 1e-3 * max(want, 1e-12), (target, got, want)
+    with pytest.raises(G.UOTError):
+        s.history(1)
