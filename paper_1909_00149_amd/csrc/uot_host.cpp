@@ -218,11 +218,14 @@ struct uot_handle {
   double* h_pp = nullptr;       // pinned
 
   // cached graph of one check window
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;    // one check window
   std::vector<unsigned char> gkey;
+  hipGraphExec_t gexec_n = nullptr;  // a burst of several windows between host polls
+  std::vector<unsigned char> gkey_n;
 
   ~uot_handle() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gexec_n) (void)hipGraphExecDestroy(gexec_n);
     if (drexec) (void)hipGraphExecDestroy(drexec);
     if (drbuf) (void)hipFree(drbuf);
     if (d_drp) (void)hipFree(d_drp);
@@ -658,8 +661,10 @@ uot_status enqueue_window(Launch& L, int W, bool check) {
   return UOT_OK;
 }
 
-uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
+uot_status get_graph(Launch& L, int W, bool check, int reps, hipGraphExec_t* out) {
   uot_handle* h = L.h;
+  hipGraphExec_t& slot = reps == 1 ? h->gexec : h->gexec_n;
+  std::vector<unsigned char>& skey = reps == 1 ? h->gkey : h->gkey_n;
   std::vector<unsigned char> key;
   auto put = [&](const void* d, size_t n) {
     const unsigned char* c = (const unsigned char*)d;
@@ -669,22 +674,24 @@ uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
   put(&L.chk, sizeof(L.chk));
   put(&L.dec, sizeof(L.dec));
   put(&W, sizeof(W));
+  put(&reps, sizeof(reps));
   int c = check;
   put(&c, sizeof(c));
   put(&L.grid_iter, sizeof(int));
   put(&L.J->shape, sizeof(int));
   put(&h->prm, sizeof(h->prm));
-  if (h->gexec && key == h->gkey) {
-    *out = h->gexec;
+  if (slot && key == skey) {
+    *out = slot;
     return UOT_OK;
   }
-  if (h->gexec) {
-    (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
+  if (slot) {
+    (void)hipGraphExecDestroy(slot);
+    slot = nullptr;
   }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  uot_status st = enqueue_window(L, W, check);
+  uot_status st = UOT_OK;
+  for (int r = 0; r < reps && st == UOT_OK; ++r) st = enqueue_window(L, W, check);
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (st != UOT_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -695,8 +702,8 @@ uot_status get_graph(Launch& L, int W, bool check, hipGraphExec_t* out) {
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIPCHK(e);
-  h->gexec = ex;
-  h->gkey = key;
+  slot = ex;
+  skey = key;
   *out = ex;
   return UOT_OK;
 }
@@ -929,14 +936,20 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   const int nwin = p.max_iter / W;
   const int tail = p.max_iter % W;
   const bool use_graph = !(p.flags & UOT_NO_GRAPH);
-  hipGraphExec_t gx = nullptr;
-  if (n_active > 0 && nwin > 0 && use_graph) {
-    s = get_graph(L, W, check, &gx);
-    if (s != UOT_OK) return s;
-  }
   // windows: the device decides convergence; the host polls every few windows
-  // (every window when the history is recorded)
-  const int poll = record ? 1 : std::max(1, 256 / W);
+  // (every window when the history is recorded).  A full burst of windows
+  // between polls replays one captured graph; a shorter last burst replays
+  // the one-window graph.
+  const int poll = record ? 1 : std::min(32, std::max(1, 256 / W));
+  hipGraphExec_t gx = nullptr, gxn = nullptr;
+  if (n_active > 0 && nwin > 0 && use_graph) {
+    s = get_graph(L, W, check, 1, &gx);
+    if (s != UOT_OK) return s;
+    if (poll > 1 && nwin >= poll) {
+      s = get_graph(L, W, check, poll, &gxn);
+      if (s != UOT_OK) return s;
+    }
+  }
   h->have_hist = record;
   h->hist.assign(record ? B : 0, {});
   std::vector<double> hrel(record ? B : 0);
@@ -945,11 +958,15 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   int w = 0;
   while (w < nwin && n_active > 0) {
     const int burst = std::min(poll, nwin - w);
-    for (int i = 0; i < burst; ++i) {
-      if (gx) HIPCHK(hipGraphLaunch(gx, h->stream));
-      else {
-        s = enqueue_window(L, W, check);
-        if (s != UOT_OK) return s;
+    if (gxn && burst == poll) {
+      HIPCHK(hipGraphLaunch(gxn, h->stream));
+    } else {
+      for (int i = 0; i < burst; ++i) {
+        if (gx) HIPCHK(hipGraphLaunch(gx, h->stream));
+        else {
+          s = enqueue_window(L, W, check);
+          if (s != UOT_OK) return s;
+        }
       }
     }
     w += burst;
