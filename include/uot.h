@@ -110,11 +110,11 @@ typedef struct uot_params {
                            larger than the last-level cache).  The vectorised shapes
                            take any row layout; they run at full speed when every row
                            starts on a 16-byte boundary (see pitch).
-                           1000 * T + rows (4008, 2016, 4016, 8016, 4032, 8032):
+                           1000 * T + rows (4004, 4008, 2016, 4016, 8016, 4032, 8032):
                            temporally blocked, up to T iterations per launch on
                            64 x rows tiles with a T-pixel halo; the last iteration
                            before each convergence check runs in the single-step
-                           kernel of the same rows (100 + rows; 8 for 4008).  Every
+                           kernel of the same rows (100 + rows; 4 / 8 for 4004 / 4008).  Every
                            shape computes bit-identical iterates                         */
   int32_t pitch;        /* row stride of uot_solve's planes in elements; 0 = nx.  A
                            pitch rounded up to a multiple of 4 puts every row on a

@@ -86,14 +86,15 @@ void tune_store_locked() {
 }
 
 // Default kernel shape by size (the codes are listed with shape_rows below).
-// Measured on one MI355X, per iteration: the blocked kernels take 1.8 us at
-// 64^2..256^2 (single-step: 3.7 us, the launch floor), 2.2 us at 512^2 (4.7),
-// 60 us at 4096^2 (121) and 56 us on a 14.7 Mpx ragged batch (110).
+// Measured on one MI355X, per iteration: the blocked kernels take 1.55 us at
+// 256^2 with 64 x 4 tiles (1.78 with 64 x 8; single-step: 3.7 us, the launch
+// floor), 2.1 us at 512^2 with 64 x 8 (2.5 with 64 x 4), 60 us at 4096^2
+// (121) and 56 us on a 14.7 Mpx ragged batch (110).
 int heuristic_shape(long npx) {
-  // temporally blocked, 4 iterations per launch: 64 x 8 tiles while the
-  // grid is too small to give every CU a 64 x 16 tile (more workgroups hide
-  // more latency), 64 x 16 tiles above (less halo work)
-  return npx <= (1L << 18) ? 4008 : 4016;
+  // temporally blocked, 4 iterations per launch: the smaller the grid, the
+  // smaller the tile, so that enough workgroups hide the latency of the
+  // steps' barriers; above 2^18 pixels 64 x 16 tiles (less halo work)
+  return npx <= (1L << 16) ? 4004 : (npx <= (1L << 18) ? 4008 : 4016);
 }
 
 // Kernel shape codes: rows (4, 8, 16, 32) = the scalar kernel; 100 + rows =
@@ -111,7 +112,7 @@ int shape_single(int code) {
 bool shape_known(int code) {
   switch (code) {
     case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
-    case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: return true;
+    case 4004: case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: return true;
   }
   return false;
 }
@@ -283,7 +284,7 @@ uot_status uot_check_params(const uot_params* p) {
   if (!std::isfinite(p->tol)) return UOT_ERR_ARG;
   switch (p->tile_rows) {
     case 0: case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
-    case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: break;
+    case 4004: case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: break;
     default: return UOT_ERR_ARG;
   }
   if ((p->flags & UOT_ALLOW_SIGNED) && p->mode != UOT_DIST) return UOT_ERR_ARG;
@@ -789,7 +790,7 @@ uot_status autotune(uot_handle* h, const Layout& L, const float* src, const floa
   const int resid = resid_of(p);
   std::vector<int> cand = {4, 8, 16, 32};
   if (J.vec_ok) {
-    for (int c : {116, 132, 316, 332, 4008, 2016, 4016, 8016, 4032, 8032}) cand.push_back(c);
+    for (int c : {116, 132, 316, 332, 4004, 4008, 2016, 4016, 8016, 4032, 8032}) cand.push_back(c);
   }
   Job J4;
   uot_status s = plan(h, L, J4, 4);

@@ -839,6 +839,7 @@ hipError_t iter_by_ty(int ty, int grid, const IterArgs& a, hipStream_t s) {
     case 316: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 16, true>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 332: hipLaunchKernelGGL((cp_iter_vec_kernel<MODE, RES, BC, 32, true>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 4008: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 8, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
+    case 4004: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 4, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 2016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 2>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 8016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 8>), dim3(grid), dim3(BLOCK), 0, s, a); break;
     case 4016: hipLaunchKernelGGL((cp_iter_tb_kernel<MODE, RES, BC, 16, 4>), dim3(grid), dim3(BLOCK), 0, s, a); break;
@@ -861,6 +862,7 @@ hipError_t occ_by_ty(int ty, int* n) {
     case 316: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 16, true>, BLOCK, 0);
     case 332: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_vec_kernel<MODE, RES, BC, 32, true>, BLOCK, 0);
     case 4008: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 8, 4>, BLOCK, 0);
+    case 4004: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 4, 4>, BLOCK, 0);
     case 2016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 2>, BLOCK, 0);
     case 8016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 8>, BLOCK, 0);
     case 4016: return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, cp_iter_tb_kernel<MODE, RES, BC, 16, 4>, BLOCK, 0);

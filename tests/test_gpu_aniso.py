@@ -95,7 +95,7 @@ def test_fixed_iterations_match_oracle(dev, mode, balanced, resid, bc, shape):
         assert abs(rep["dual"] - g.dual) <= VAL_TOL * max(abs(g.dual), abs(g.primal))
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332, 4008, 2016, 4016, 8016, 4032, 8032])
+@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332, 4004, 4008, 2016, 4016, 8016, 4032, 8032])
 @pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 2), (PROX_FIXED, True, 1)])
 @pytest.mark.parametrize("shape", [(45, 133), (19, 66)])
 def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):

@@ -114,7 +114,7 @@ def test_fixed_iterations_all_modes(dev, mode, balanced, resid, bc, shape):
         assert abs(rep["dual"] - g.dual) <= VAL_TOL * max(abs(g.dual), abs(g.primal))
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332, 4008, 2016, 4016, 8016, 4032, 8032])
+@pytest.mark.parametrize("ty", [4, 8, 16, 32, 116, 132, 316, 332, 4004, 4008, 2016, 4016, 8016, 4032, 8032])
 @pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 1), (PROX_FIXED, True, 1),
                                                  (DIST, True, 1), (PROX, False, 2)])
 @pytest.mark.parametrize("shape", [(45, 133), (45, 132), (70, 256), (19, 66), (23, 131)])
@@ -133,7 +133,7 @@ def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):
         assert torch.equal(base[k], st[k]), k
 
 
-@pytest.mark.parametrize("ty", [4008, 2016, 4016, 8016, 4032, 8032])
+@pytest.mark.parametrize("ty", [4004, 4008, 2016, 4016, 8016, 4032, 8032])
 @pytest.mark.parametrize("mode,balanced,resid", [(DIST, False, 1), (PROX, False, 2), (DIST, True, 1)])
 @pytest.mark.parametrize("shape,iters,check_every", [((3, 5), 17, 6), ((40, 131), 47, 20), ((70, 256), 61, 8),
                                                      ((130, 9), 33, 10)])
