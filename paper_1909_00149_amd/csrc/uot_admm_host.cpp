@@ -237,7 +237,7 @@ uot_status uotdf_create(const uotdf_params* prm, void* hip_stream, uotdf_handle*
   const int rows = h->shape >= 1000 ? h->shape % 1000 : h->shape % 100;
   std::vector<Tile> tiles;
   for (int y = 0; y < prm->ny; y += rows)
-    for (int x = 0; x < prm->nx; x += TX) tiles.push_back(Tile{0, x, y, 0});
+    for (int x = 0; x < prm->nx; x += TX) tiles.push_back(Tile{0, x, y, (int32_t)tiles.size()});
   h->ntiles = (int)tiles.size();
   PairInfo P{};
   P.off = 0;
@@ -638,7 +638,7 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
     P.inv2mt = (float)(1.0 / (1.0 + 2.0 * prm->mu * t1));
     P.tile_begin = (int32_t)tiles.size();
     for (int y = 0; y < prm->ny; y += rows)
-      for (int x = 0; x < prm->nx; x += TX) tiles.push_back(Tile{b, x, y, 0});
+      for (int x = 0; x < prm->nx; x += TX) tiles.push_back(Tile{b, x, y, (int32_t)tiles.size()});
     P.tile_count = (int32_t)tiles.size() - P.tile_begin;
     P.pitch = prm->nx;
   }

@@ -360,9 +360,10 @@ Planes planes_of(const uot_state& s) { return Planes{s.Mx, s.My, s.r, s.a, s.x0,
 // reading, bit 1 the anisotropic flux norm.
 int bcn_of(const uot_params& p) { return p.bc | (p.norm == UOT_NORM_ANISO ? 2 : 0); }
 
-int iter_grid(uot_handle* h, int mode, int resid, int bc, int ty, int ntiles) {
+int iter_grid(uot_handle* h, int mode, int resid, int bc, int ty, int ntiles, bool chk = false) {
   int occ = 0;
-  if (iter_occupancy(mode, resid, bc, ty, &occ) != hipSuccess || occ <= 0) occ = 4;
+  const hipError_t e = chk ? iter_chk_occupancy(mode, resid, bc, ty, &occ) : iter_occupancy(mode, resid, bc, ty, &occ);
+  if (e != hipSuccess || occ <= 0) occ = chk ? 2 : 4;
   long g = std::min<long>((long)ntiles, (long)h->num_cu * occ);
   g = std::max<long>(8, (g + 7) / 8 * 8);
   return (int)g;
@@ -451,7 +452,7 @@ uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* 
     P.inv2mt = (float)(1.0 / (1.0 + 2.0 * p.mu * t1));
     P.tile_begin = (int32_t)J.tiles.size();
     for (int y = 0; y < ny[b]; y += ty)
-      for (int x = 0; x < nx[b]; x += TX) J.tiles.push_back(Tile{b, x, y, 0});
+      for (int x = 0; x < nx[b]; x += TX) J.tiles.push_back(Tile{b, x, y, (int32_t)J.tiles.size()});
     P.tile_count = (int32_t)J.tiles.size() - P.tile_begin;
     P.pitch = L.pitch_of(b);
   }
@@ -635,7 +636,7 @@ struct Launch {
   IterArgs fwd, bwd;   // A -> B and B -> A
   CheckArgs chk;
   DecideArgs dec;
-  int grid_iter, grid_single, grid_aux, resid;
+  int grid_iter, grid_single, grid_aux, grid_chk, resid;
 };
 
 // One launch of `steps` iterations: the shape's own kernel, or its
@@ -653,10 +654,21 @@ uot_status enqueue_window(Launch& L, int W, bool check) {
   uot_handle* h = L.h;
   const uot_params& p = h->prm;
   const std::vector<int> sched = step_schedule(W, shape_steps(L.J->shape), true, true);
-  for (size_t i = 0; i < sched.size(); ++i)
-    HIPCHK(launch_steps(h, L.resid, L.J->shape, sched[i], L.grid_iter, L.grid_single, (i & 1) ? L.bwd : L.fwd));
+  // with a blocked shape, the window's last (single) step also evaluates the
+  // check, from the two iterates it holds in LDS and registers
+  const bool fused = check && shape_steps(L.J->shape) > 1;
+  for (size_t i = 0; i < sched.size(); ++i) {
+    IterArgs a = (i & 1) ? L.bwd : L.fwd;
+    if (fused && i + 1 == sched.size()) {
+      a.steps = 1;
+      a.chk = h->d_partial;
+      HIPCHK(launch_iter_chk(p.mode, L.resid, bcn_of(p), L.J->shape, L.grid_chk, a, h->stream));
+    } else {
+      HIPCHK(launch_steps(h, L.resid, L.J->shape, sched[i], L.grid_iter, L.grid_single, a));
+    }
+  }
   if (check) {
-    HIPCHK(launch_check(p.mode, L.resid, bcn_of(p), L.grid_aux, L.chk, h->stream));
+    if (!fused) HIPCHK(launch_check(p.mode, L.resid, bcn_of(p), L.grid_aux, L.chk, h->stream));
     HIPCHK(launch_reduce_decide(L.dec, h->d_partial, h->stream));
   }
   return UOT_OK;
@@ -679,6 +691,7 @@ uot_status get_graph(Launch& L, int W, bool check, int reps, hipGraphExec_t* out
   int c = check;
   put(&c, sizeof(c));
   put(&L.grid_iter, sizeof(int));
+  put(&L.grid_chk, sizeof(int));
   put(&L.J->shape, sizeof(int));
   put(&h->prm, sizeof(h->prm));
   if (slot && key == skey) {
@@ -916,6 +929,7 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   L.resid = resid;
   L.grid_iter = iter_grid(h, p.mode, resid, bcn_of(p), J.shape, (int)J.tiles.size());
   L.grid_single = iter_grid(h, p.mode, resid, bcn_of(p), shape_single(J.shape), (int)J.tiles.size());
+  if (shape_steps(J.shape) > 1) L.grid_chk = iter_grid(h, p.mode, resid, bcn_of(p), J.shape, (int)J.tiles.size(), true);
   L.grid_aux = aux_grid(h, (int)J.tiles.size());
   const Planes A = planes_of(*st), Bp = shadow_planes(h);
   const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;

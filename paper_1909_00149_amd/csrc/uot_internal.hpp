@@ -54,7 +54,7 @@ struct PairInfo {
 };
 
 struct Tile {
-  int32_t pair, x0, y0, pad;
+  int32_t pair, x0, y0, pad;  // pad: the tile's index in the full tile list
 };
 
 struct Planes {
@@ -71,6 +71,9 @@ struct IterArgs {
   const int32_t* ntiles;
   const int32_t* active;
   int32_t steps;      // iterations per launch of the temporally blocked kernel
+  int32_t pad_;
+  double* chk;        // blocked kernel, one step: also the check's per-tile partial rows,
+                      // at row Tile::pad (the tile's index in the full list)
 };
 
 struct CheckArgs {
@@ -159,6 +162,12 @@ hipError_t launch_iter_mode2(int resid, int bcn, int ty, int grid, const IterArg
 hipError_t iter_occupancy_mode0(int resid, int bcn, int ty, int* n);
 hipError_t iter_occupancy_mode1(int resid, int bcn, int ty, int* n);
 hipError_t iter_occupancy_mode2(int resid, int bcn, int ty, int* n);
+hipError_t iter_chk_occupancy_mode0(int resid, int bcn, int ty, int* n);
+hipError_t iter_chk_occupancy_mode1(int resid, int bcn, int ty, int* n);
+hipError_t iter_chk_occupancy_mode2(int resid, int bcn, int ty, int* n);
+hipError_t launch_iter_chk_mode0(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
+hipError_t launch_iter_chk_mode1(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
+hipError_t launch_iter_chk_mode2(int resid, int bcn, int ty, int grid, const IterArgs& a, hipStream_t s);
 hipError_t launch_check_mode0(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s);
 hipError_t launch_check_mode1(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s);
 hipError_t launch_check_mode2(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s);
@@ -166,6 +175,9 @@ hipError_t launch_check_mode2(int resid, int bcn, int grid, const CheckArgs& a, 
 hipError_t launch_iter(int mode, int resid, int bc, int ty, int grid, const IterArgs& a,
                        hipStream_t s);
 hipError_t launch_check(int mode, int resid, int bc, int grid, const CheckArgs& a, hipStream_t s);
+// One step of a blocked shape that also writes the check's partial rows for
+// the iterate pair (in, out) into a.chk (the separate check kernel's rows).
+hipError_t launch_iter_chk(int mode, int resid, int bc, int ty, int grid, const IterArgs& a, hipStream_t s);
 hipError_t launch_setup(int grid, const SetupArgs& a, hipStream_t s);
 hipError_t launch_pair_reduce(const PairInfo* pairs, int B, const double* partial, uint32_t max_mask,
                               double* sums, hipStream_t s);
@@ -176,6 +188,8 @@ hipError_t launch_copy_active(const Planes& dst, const Planes& src, const PairIn
                               int grid, hipStream_t s);
 hipError_t launch_dual(int grid, const DualArgs& a, hipStream_t s);
 hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* blocks_per_cu);
+// the same for the one-step check variant of a blocked shape
+hipError_t iter_chk_occupancy(int mode, int resid, int bc, int ty, int* blocks_per_cu);
 
 }  // namespace uot
 

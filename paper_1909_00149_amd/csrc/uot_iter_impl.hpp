@@ -510,28 +510,104 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
 // kernels.  K(z^k) of each pixel is carried in a register from one step to
 // the next (it is the K(z^{k+1}) of the step before), so the old flux is not
 // needed again and the flux is updated in place.  The last iteration before
-// a convergence check runs in a single-step kernel, which leaves both
-// iterates the check compares in the ping-pong buffers.
-template <int MODE, int RES, int BC, int TH, int T>
-__global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
+// a convergence check runs as one step with a halo of two that also
+// evaluates the check: the iterate it read is kept in registers, the one it
+// wrote is in LDS, and both iterates stay in the ping-pong buffers for the
+// final evaluation of a solve.
+// ---------------------------------------------------------------------------
+// Block reduction of NS double slots into one partial row (and, if fin is
+// given, into that LDS row too, visible to the whole block on return),
+// through the LDS buffer buf of NS x BLOCK doubles.  Every thread stores its
+// NS values; then thread 16 s + g combines values g, g + 16, ... of slot s
+// (a pairwise tree; the 16 lanes of a load hit distinct banks), and the 16
+// lanes of a slot, consecutive lanes of one wave, combine by an xor
+// butterfly.  The order is fixed, so the result does not depend on timing.
+// Slots in max_mask are max-reduced, the others summed.
+__device__ __forceinline__ void block_reduce_lds(double (&acc)[NS], uint32_t max_mask, double* dst, double* buf,
+                                                 double* fin = nullptr) {
+  static_assert(NS == 16 && BLOCK == 256, "16 slots x 16 lanes x 16 values");
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) buf[s * BLOCK + tid] = acc[s];
+  __syncthreads();
+  const int s = tid >> 4, g = tid & 15;
+  const bool mx = (max_mask >> s) & 1u;
+  double w[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) w[k] = buf[s * BLOCK + g + 16 * k];
+#pragma unroll
+  for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+    for (int k = 0; k < h; ++k) w[k] = mx ? fmax(w[k], w[k + h]) : w[k] + w[k + h];
+  double v = w[0];
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    const double u = __shfl_xor(v, o, 16);
+    v = mx ? fmax(v, u) : v + u;
+  }
+  if (g == 0) {
+    dst[s] = v;
+    if (fin) fin[s] = v;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst,
+                                                   double* fin = nullptr) {
+  __shared__ double buf[NS * BLOCK];
+  block_reduce_lds(acc, max_mask, dst, buf, fin);
+}
+
+template <int MODE, int RES, int BC, int TH, int T, bool CHK, bool KEEP = false>
+__device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   constexpr int RW = TX + 2 * T, RH = TH + 2 * T, NCELL = RW * RH;
   constexpr int NC = (NCELL + BLOCK - 1) / BLOCK;
   // LDS rows of RW cells plus a zero border; the rows past the region hold
   // the cells of the last pass that fall outside it (always written zero)
   constexpr int LW = RW + 2, LH = (NC * BLOCK + RW - 1) / RW + 2;
   constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4, F_OWN = 8;  // per-cell flags
-  __shared__ float sa[LH * LW];
-  __shared__ float smx[LH * LW];
-  __shared__ float smy[LH * LW];
+  // a, Mx, My planes of the region; CHK: also the check's reduction buffer,
+  // used only between tiles (after the write of one, before the staging of
+  // the next)
+  constexpr int PLANE = LH * LW;
+  constexpr int POOL = CHK && NS * BLOCK > (3 * PLANE + 1) / 2 ? NS * BLOCK : (3 * PLANE + 1) / 2;
+  __shared__ double pool[POOL];
+  float* const sa = reinterpret_cast<float*>(pool);
+  float* const smx = sa + PLANE;
+  float* const smy = sa + 2 * PLANE;
   const int tid = threadIdx.x;
-  for (int i = tid; i < LH * LW; i += BLOCK) sa[i] = smx[i] = smy[i] = 0.f;
+  for (int i = tid; i < PLANE; i += BLOCK) sa[i] = smx[i] = smy[i] = 0.f;
   const int steps = A.steps;
   long t, stride, tend;
   xcd_chunk(*A.ntiles, t, stride, tend);
+  // CHK: per-thread check sums over the block's run of tiles of one pair,
+  // reduced once per run into the row of its first tile (the run's other
+  // rows are zeroed, so the per-pair sum of the rows is unchanged)
+  double acc[NS];
+  int run_pair = -1, run_row = 0;
+  if (CHK) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+  }
 
   for (; t < tend; t += stride) {
     const Tile tl = A.tiles[t];
     if (!A.active[tl.pair]) continue;  // uniform over the block
+    if (CHK) {
+      if (tl.pair != run_pair) {
+        if (run_pair >= 0) {
+          __syncthreads();  // the previous tile's write no longer reads the pool
+          block_reduce_lds(acc, kMaxSlotsCheck, A.chk + (long)run_row * NS, pool);
+#pragma unroll
+          for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+          for (int i = tid; i < PLANE; i += BLOCK) sa[i] = smx[i] = smy[i] = 0.f;  // the zero border again
+        }
+        run_pair = tl.pair;
+        run_row = tl.pad;
+      } else if (tid < NS) {
+        A.chk[(long)tl.pad * NS + tid] = 0.0;
+      }
+    }
     const PairInfo P = A.pairs[tl.pair];
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const long off = P.off;
@@ -539,6 +615,9 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
     const int bx = tl.x0 - T, by = tl.y0 - T;  // grid position of region cell (0, 0)
     int l_[NC], f_[NC];                        // LDS index and flags of each cell
     float r_[NC], c0_[NC], c1_[NC], x0_[NC], x1_[NC], kp_[NC];
+    // CHK with KEEP: the last step's input values the check needs, kept in
+    // registers (otherwise read back from the input planes)
+    float ka_[NC], kr_[NC], ku_[NC], kmx_[NC], kmy_[NC], kro_[NC], kx0_[NC], kx1_[NC];
 
     __syncthreads();  // LDS of the previous tile is no longer read
     // ---- stage the region ----
@@ -600,6 +679,16 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
         au_[k] = sa[l + LW];
         mx_[k] = smx[l];
         my_[k] = smy[l];
+        if (CHK && KEEP) {
+          ka_[k] = ac_[k];
+          kr_[k] = ar_[k];
+          ku_[k] = au_[k];
+          kmx_[k] = mx_[k];
+          kmy_[k] = my_[k];
+          kro_[k] = r_[k];
+          kx0_[k] = x0_[k];
+          kx1_[k] = x1_[k];
+        }
       }
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
@@ -659,6 +748,104 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
       __syncthreads();
     }
 
+    if (CHK) {
+      // the check of the iterate pair (input, output) of this one-step
+      // launch, per owned cell with the expressions of check_kernel: the
+      // input iterate is still in the input planes (read back through the
+      // L2), the output one is in LDS, exact one cell beyond the tile (the
+      // halo is two), where the check reads the right and upper neighbours'
+      // a and the left and lower neighbours' flux
+      constexpr float nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
+      static_assert(T >= 2, "the check needs one exact cell beyond the tile");
+      const float it1 = 1.f / tau1;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        if ((f_[k] & (F_IN | F_OWN)) != (F_IN | F_OWN)) continue;
+        const int l = l_[k];
+        const int idx = tid + k * BLOCK;
+        const int ry = idx / RW, rx = idx - ry * RW;
+        const int gx = bx + rx, gy = by + ry;
+        const long o = off + (long)gy * pitch + gx;
+        const bool hasR = gx + 1 < nx, hasU = gy + 1 < ny;
+        const float a = sa[l], ap = KEEP ? ka_[k] : A.in.a[o];
+        const float aR = sa[l + 1], apR = KEEP ? kr_[k] : (hasR ? A.in.a[o + 1] : 0.f);
+        const float aU = sa[l + LW], apU = KEEP ? ku_[k] : (hasU ? A.in.a[o + pitch] : 0.f);
+        float gxx = a - aR, gyy = a - aU;
+        float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
+        const bool zx = (BC & 1) == 0 && (f_[k] & F_ZX), zy = (BC & 1) == 0 && (f_[k] & F_ZY);
+        if (zx) gxx = dgx = 0.f;
+        if (zy) gyy = dgy = 0.f;
+        const float mx = zx ? 0.f : smx[l], my = zy ? 0.f : smy[l];
+        const float mxp = zx ? 0.f : (KEEP ? kmx_[k] : A.in.Mx[o]), myp = zy ? 0.f : (KEEP ? kmy_[k] : A.in.My[o]);
+        const float mxl = smx[l - 1];
+        const float myd = smy[l - LW];
+        const float dm = (mx - mxl) + (my - myd);
+        float x0 = 0.f, x1 = 0.f, e;
+        if (MODE == 0) {
+          e = dm + c0_[k];
+        } else if (MODE == 1) {
+          x0 = x0_[k];
+          x1 = x1_[k];
+          e = dm - x0 + x1;
+        } else {
+          x1 = x1_[k];
+          e = dm - c0_[k] + x1;
+        }
+        float r = 0.f, rp = 0.f;
+        if (RES != R_BAL) {
+          r = r_[k];
+          rp = KEEP ? kro_[k] : A.in.r[o];
+        }
+        const float kz = e - r;
+        const float da = ap - a;
+        const float sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
+        float st2 = sx * sx + sy * sy;
+        if (RES != R_BAL) {
+          const float sr = (rp - r) * it1 + da;
+          st2 += sr * sr;
+        }
+        if (MODE == 1) {
+          const float s0 = ((KEEP ? kx0_[k] : A.in.x0[o]) - x0) * it1 + da;
+          st2 += s0 * s0;
+        }
+        if (MODE != 0) {
+          const float s1 = ((KEEP ? kx1_[k] : A.in.x1[o]) - x1) * it1 - da;
+          st2 += s1 * s1;
+        }
+        const float g2 = gxx * gxx + gyy * gyy;
+        acc[S_PRES2] += kz * kz;
+        acc[S_STAT2] += st2;
+        acc[S_KA2] += g2 + nid * a * a;
+        acc[S_X0SQ] += x0 * x0;
+        acc[S_X1SQ] += x1 * x1;
+        acc[S_MNORM] += (BC & 2) ? fabsf(mx) + fabsf(my) : sqrtf(mx * mx + my * my);
+        if (RES == R_P1) {
+          acc[S_RPEN] += fabsf(r);
+          acc[S_EPEN] += fabsf(e);
+        } else if (RES == R_P2) {
+          acc[S_RPEN] += r * r;
+          acc[S_EPEN] += e * e;
+        }
+        if (MODE == 0) acc[S_LIN] += a * c0_[k];
+        if (MODE == 2) acc[S_LIN] -= a * c0_[k];
+        if (MODE == 1) {
+          const float d0 = x0 - c0_[k], d1 = x1 - c1_[k];
+          acc[S_QUAD] += d0 * d0 + d1 * d1;
+        }
+        if (MODE == 2) {
+          const float d1 = x1 - c1_[k];
+          acc[S_QUAD] += d1 * d1;
+        }
+        acc[S_MAXG] = fmax(acc[S_MAXG], (double)((BC & 2) ? fmaxf(fabsf(gxx), fabsf(gyy)) : sqrtf(g2)));
+        acc[S_MAXA] = fmax(acc[S_MAXA], (double)fabsf(a));
+        const bool fin = isfinite(a) && isfinite(mx) && isfinite(my) && isfinite(r) && isfinite(x0) &&
+                         isfinite(x1);
+        acc[S_NONFIN] += fin ? 0.0 : 1.0;
+        acc[S_A2] += a * a;
+        acc[S_SUMA] += a;
+      }
+    }
+
     // ---- write the owned tile ----
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -675,45 +862,25 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
       if (MODE != 0) A.out.x1[o] = x1_[k];
     }
   }
+  if (CHK && run_pair >= 0) {
+    __syncthreads();
+    block_reduce_lds(acc, kMaxSlotsCheck, A.chk + (long)run_row * NS, pool);
+  }
 }
 
-// ---------------------------------------------------------------------------
-// Block reduction of NS double slots into one partial row (and, if fin is
-// given, into that LDS row too, visible to the whole block on return).
-// Transposed through LDS: every thread stores its NS values, 16 threads per
-// slot each combine 16 threads' values, then one thread per slot combines
-// the 16 results, all in a fixed order (the result does not depend on
-// timing).  Slots in max_mask are max-reduced, the others summed.
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t max_mask, double* dst,
-                                                   double* fin = nullptr) {
-  static_assert(NS == 16 && BLOCK == 256, "16 slots x 16 groups of 16 threads");
-  __shared__ double buf[NS][BLOCK + 1];
-  __shared__ double red[NS][17];
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) buf[s][tid] = acc[s];
-  __syncthreads();
-  {
-    const int s = tid >> 4, g = tid & 15;
-    const bool mx = (max_mask >> s) & 1u;
-    double v = buf[s][16 * g];
-#pragma unroll
-    for (int k = 1; k < 16; ++k) {
-      const double w = buf[s][16 * g + k];
-      v = mx ? fmax(v, w) : v + w;
-    }
-    red[s][g] = v;
-  }
-  __syncthreads();
-  if (tid < NS) {
-    const int s = tid;
-    const bool mx = (max_mask >> s) & 1u;
-    double v = red[s][0];
-    for (int g = 1; g < 16; ++g) v = mx ? fmax(v, red[s][g]) : v + red[s][g];
-    dst[s] = v;
-    if (fin) fin[s] = v;
-  }
-  __syncthreads();
+template <int MODE, int RES, int BC, int TH, int T>
+__global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
+  cp_iter_tb_body<MODE, RES, BC, TH, T, false>(A);
+}
+
+// One step (A.steps = 1) of the blocked kernel that also leaves the check's
+// partial rows of the iterate pair it reads and writes (so the window needs
+// neither the single-step launch nor the separate check).  KEEP holds the
+// input iterate in registers rather than reading it back (fewer round trips
+// to memory, more registers).
+template <int MODE, int RES, int BC, int TH, int T, bool KEEP>
+__global__ __launch_bounds__(BLOCK) void cp_iter_tb_check_kernel(IterArgs A) {
+  cp_iter_tb_body<MODE, RES, BC, TH, T, true, KEEP>(A);
 }
 
 // Residuals and certificate terms of the current iterate (K2).  Direct
@@ -848,6 +1015,44 @@ hipError_t iter_by_ty(int ty, int grid, const IterArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+using IterKernel = void (*)(IterArgs);
+
+// The one-step check variant of a blocked shape: its tile rows with a halo
+// of two (the check reads one cell beyond the tile, exact after one step
+// everywhere but the region's outermost ring).
+template <int MODE, int RES, int BC>
+IterKernel chk_kernel_ty(int ty) {
+  switch (ty) {
+    case 4004: return cp_iter_tb_check_kernel<MODE, RES, BC, 4, 2, true>;
+    case 4008: return cp_iter_tb_check_kernel<MODE, RES, BC, 8, 2, true>;
+    case 2016:
+    case 4016:
+    case 8016: return cp_iter_tb_check_kernel<MODE, RES, BC, 16, 2, false>;
+    case 4032:
+    case 8032: return cp_iter_tb_check_kernel<MODE, RES, BC, 32, 2, false>;
+  }
+  return nullptr;
+}
+template <int MODE, int RES>
+IterKernel chk_kernel_bc(int bcn, int ty) {
+  switch (bcn) {
+    case 0: return chk_kernel_ty<MODE, RES, 0>(ty);
+    case 1: return chk_kernel_ty<MODE, RES, 1>(ty);
+    case 2: return chk_kernel_ty<MODE, RES, 2>(ty);
+    case 3: return chk_kernel_ty<MODE, RES, 3>(ty);
+  }
+  return nullptr;
+}
+template <int MODE>
+IterKernel chk_kernel(int res, int bcn, int ty) {
+  switch (res) {
+    case R_BAL: return chk_kernel_bc<MODE, R_BAL>(bcn, ty);
+    case R_P1: return chk_kernel_bc<MODE, R_P1>(bcn, ty);
+    case R_P2: return chk_kernel_bc<MODE, R_P2>(bcn, ty);
+  }
+  return nullptr;
 }
 
 template <int MODE, int RES, int BC>

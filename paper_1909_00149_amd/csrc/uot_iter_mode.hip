@@ -22,6 +22,20 @@ hipError_t UOT_CAT(iter_occupancy_mode, UOT_MODE)(int resid, int bcn, int ty, in
   return occ_res<UOT_MODE>(resid, bcn, ty, n);
 }
 
+hipError_t UOT_CAT(launch_iter_chk_mode, UOT_MODE)(int resid, int bcn, int ty, int grid, const IterArgs& a,
+                                                   hipStream_t s) {
+  const IterKernel k = chk_kernel<UOT_MODE>(resid, bcn, ty);
+  if (!k) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t UOT_CAT(iter_chk_occupancy_mode, UOT_MODE)(int resid, int bcn, int ty, int* n) {
+  const IterKernel k = chk_kernel<UOT_MODE>(resid, bcn, ty);
+  if (!k) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k, BLOCK, 0);
+}
+
 hipError_t UOT_CAT(launch_check_mode, UOT_MODE)(int resid, int bcn, int grid, const CheckArgs& a, hipStream_t s) {
   return check_res<UOT_MODE>(resid, bcn, grid, a, s);
 }

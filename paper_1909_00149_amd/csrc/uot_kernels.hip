@@ -221,11 +221,29 @@ hipError_t launch_iter(int mode, int resid, int bc, int ty, int grid, const Iter
   return hipErrorInvalidValue;
 }
 
+hipError_t iter_chk_occupancy(int mode, int resid, int bc, int ty, int* n) {
+  switch (mode) {
+    case 0: return iter_chk_occupancy_mode0(resid, bc, ty, n);
+    case 1: return iter_chk_occupancy_mode1(resid, bc, ty, n);
+    case 2: return iter_chk_occupancy_mode2(resid, bc, ty, n);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* n) {
   switch (mode) {
     case 0: return iter_occupancy_mode0(resid, bc, ty, n);
     case 1: return iter_occupancy_mode1(resid, bc, ty, n);
     case 2: return iter_occupancy_mode2(resid, bc, ty, n);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_iter_chk(int mode, int resid, int bc, int ty, int grid, const IterArgs& a, hipStream_t s) {
+  switch (mode) {
+    case 0: return launch_iter_chk_mode0(resid, bc, ty, grid, a, s);
+    case 1: return launch_iter_chk_mode1(resid, bc, ty, grid, a, s);
+    case 2: return launch_iter_chk_mode2(resid, bc, ty, grid, a, s);
   }
   return hipErrorInvalidValue;
 }
