@@ -206,3 +206,33 @@ def test_vectorised_kernel_on_odd_offsets_with_nan_gaps(dev, ty):
         assert torch.equal(ref[k][~gaps], st[k][~gaps]), k
         assert bool(torch.isfinite(st[k][~gaps]).all()), k
         assert bool(torch.isnan(st[k][gaps]).all()), k
+
+
+@pytest.mark.parametrize("mode,tol", [(DIST, 2e-4), (PROX, 1e-7)])
+def test_fused_check_agrees_with_the_separate_check(dev, mode, tol):
+    """A blocked shape evaluates each window's check inside the window's
+    last launch, accumulating over a workgroup's run of tiles of one pair;
+    a single-step shape runs the separate check kernel per tile.  On a
+    ragged batch (runs of tiles that change pair, pairs smaller than a tile,
+    one pair of many tiles) both take the same decisions at the same
+    checks: equal iteration counts and statuses, the recorded residuals
+    equal up to the order of the FP64 sums, and bitwise equal iterates."""
+    shapes = SHAPES + [(300, 257)]
+    pairs, src, dst, nx, ny, offs = batch_of(shapes, dev, seed0=40)
+    out = []
+    for ty in (4016, 16):
+        s = G.Solver(G.Params(mode=mode, mu=1.1, rho=0.8, max_iter=600, check_every=20, tol=tol, tile_rows=ty,
+                              flags=G.UOT_RECORD_HISTORY))
+        st, reps = s.solve_batched(src, dst, nx, ny, offs)
+        torch.cuda.synchronize()
+        hist = [s.history(b) for b in range(len(shapes))]
+        out.append((st, reps, hist))
+        assert all(r["tile_rows"] == ty for r in reps)
+    (sa, ra, ha), (sb, rb, hb) = out
+    assert len({r["iters"] for r in ra}) > 1, "the pairs should stop at different checks"
+    for b in range(len(shapes)):
+        assert ra[b]["iters"] == rb[b]["iters"] and ra[b]["status"] == rb[b]["status"], b
+        assert list(ha[b][0]) == list(hb[b][0]), b
+        np.testing.assert_allclose(ha[b][1], hb[b][1], rtol=1e-9, atol=0)
+    for k in planes(mode, False):
+        assert torch.equal(sa[k], sb[k]), k

@@ -139,12 +139,12 @@ def test_tile_shapes_agree_bitwise(dev, ty, mode, balanced, resid, shape):
                                                      ((130, 9), 33, 10)])
 def test_blocked_shapes_with_checks_and_tails(dev, ty, mode, balanced, resid, shape, iters, check_every):
     """Temporally blocked launches inside check windows (the last iteration
-    of a window runs single-step) and in an odd tail, with the stopping test
-    active (tol tiny, so it never stops): the iterates and every report
-    field agree bitwise with the single-step kernel over the same tile list
-    (the FP64 sums of the reports are taken per tile, so their rounding
-    follows the tile height).  Grids smaller than the halo and narrower than
-    a tile are included."""
+    of a window runs in the one-step check variant) and in an odd tail, with
+    the stopping test active (tol tiny, so it never stops): the iterates and
+    every report field agree bitwise with the single-step kernel over the
+    same tile list (the final evaluation's FP64 sums are taken per tile, so
+    their rounding follows the tile height).  Grids smaller than the halo
+    and narrower than a tile are included."""
     p, q = pair_inputs(shape, 5, mode)
     if balanced and mode == DIST:
         q = (q * (p.astype(np.float64).sum() / q.astype(np.float64).sum())).astype(np.float32)
