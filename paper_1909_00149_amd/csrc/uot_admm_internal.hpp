@@ -28,6 +28,7 @@ struct DfArgs {
 constexpr int RP_MAX_FRAMES = 64;  // the Gram eigensolve keeps T x T in LDS
 constexpr int RP_SLOTS = 5;        // residual partial slots per block
 constexpr int RP_MAX_SWEEPS = 40;  // Jacobi sweeps per eigensolve (rotations stored for each)
+constexpr int RP_MAX_REFINE = 3;  // refinement passes of the warm start before the sweeps
 constexpr long RP_ROT_PER_SWEEP = (RP_MAX_FRAMES - 1) * (RP_MAX_FRAMES / 2);
 struct RpArgs {
   long npx;                    // pixels per frame

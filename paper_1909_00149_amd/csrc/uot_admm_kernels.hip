@@ -337,18 +337,149 @@ __device__ __forceinline__ void rr_pair(int r, int k, int& p, int& q) {
   q = a < b ? b : a;
 }
 
+// acc = op(X) Y for 64 x 64 FP64 matrices in LDS (leading dimension 65),
+// op(X) = X or X^T; thread (bi, bj) of 16 x 16 forms the 4 x 4 block at
+// rows 4 bi, columns 4 bj.
+template <bool TX>
+__device__ __forceinline__ void mm64(const double* X, const double* Y, int bi, int bj, double (&acc)[4][4]) {
+  constexpr int N = RP_MAX_FRAMES, LD = N + 1;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < N; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = TX ? X[k * LD + 4 * bi + u] : X[(4 * bi + u) * LD + k];
+      b[u] = Y[k * LD + 4 * bj + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+}
+
+// acc1 = X^T Y1 and acc2 = X^T Y2 in one pass over k (the X loads shared).
+__device__ __forceinline__ void mm64t_pair(const double* X, const double* Y1, const double* Y2, int bi, int bj,
+                                           double (&acc1)[4][4], double (&acc2)[4][4]) {
+  constexpr int N = RP_MAX_FRAMES, LD = N + 1;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc1[u][v] = acc2[u][v] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < N; ++k) {
+    double a[4], b[4], c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = X[k * LD + 4 * bi + u];
+      b[u] = Y1[k * LD + 4 * bj + u];
+      c[u] = Y2[k * LD + 4 * bj + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc1[u][v] = fma(a[u], b[v], acc1[u][v]);
+        acc2[u][v] = fma(a[u], c[v], acc2[u][v]);
+      }
+  }
+}
+
+// Two sums and a maximum over the block, the same in every thread (fixed
+// order), through red[3][RB / 64].
+__device__ __forceinline__ void block_sum2_max(double& s0, double& s1, double& m, double (*red)[RB / 64]) {
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_down(s0, o, 64);
+    s1 += __shfl_down(s1, o, 64);
+    m = fmax(m, __shfl_down(m, o, 64));
+  }
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = s0;
+    red[1][tid >> 6] = s1;
+    red[2][tid >> 6] = m;
+  }
+  __syncthreads();
+  s0 = red[0][0];
+  s1 = red[1][0];
+  m = red[2][0];
+  for (int w = 1; w < RB / 64; ++w) {
+    s0 += red[0][w];
+    s1 += red[1][w];
+    m = fmax(m, red[2][w]);
+  }
+  __syncthreads();
+}
+
+// Two sums and two maxima over the block, the same in every thread.
+__device__ __forceinline__ void block_sum2_max2(double& s0, double& s1, double& m0, double& m1,
+                                                double (*red)[RB / 64]) {
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_down(s0, o, 64);
+    s1 += __shfl_down(s1, o, 64);
+    m0 = fmax(m0, __shfl_down(m0, o, 64));
+    m1 = fmax(m1, __shfl_down(m1, o, 64));
+  }
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = s0;
+    red[1][tid >> 6] = s1;
+    red[2][tid >> 6] = m0;
+    red[3][tid >> 6] = m1;
+  }
+  __syncthreads();
+  s0 = red[0][0];
+  s1 = red[1][0];
+  m0 = red[2][0];
+  m1 = red[3][0];
+  for (int w = 1; w < RB / 64; ++w) {
+    s0 += red[0][w];
+    s1 += red[1][w];
+    m0 = fmax(m0, red[2][w]);
+    m1 = fmax(m1, red[3][w]);
+  }
+  __syncthreads();
+}
+
 // One workgroup.  A lives in LDS in FP64; after the start only its upper
 // triangle (with the diagonal) is kept.  A round: 32 threads form the
 // rotations (symmetric Schur, Golub and Van Loan); then every block of the
 // upper triangle (pair k1 rows, pair k2 >= k1 columns) becomes
 // R_k1^T A R_k2, each block owned by one thread, the diagonal blocks taking
 // the exact diagonalisation.  V^T G V keeps a 4 x 4 block per thread.
-__global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, const double* Vg, double2* rots,
-                                                     double* lam, int* sweeps) {
+//
+// Before the sweeps, the warm start is refined by the iteration of Ogita and
+// Aishima (2018) for symmetric eigenproblems, which needs only matrix
+// products: with R = I - V^T V and S = V^T G V, the eigenvalue estimates are
+// l_i = S_ii / (1 - R_ii), and V <- V + V E with E_ij = (S_ij + l_j R_ij) /
+// (l_j - l_i) where |l_j - l_i| exceeds the cluster bound
+// delta = 2 (||S - diag(l)|| + ||G|| ||R||) and E_ij = R_ij / 2 otherwise (and
+// on the diagonal); the error falls quadratically.  The threshold needs only
+// the matrix function Wm = V diag(f(l)) V^T, which does not depend on the
+// basis inside the set of eigenvalues under the threshold (f = 0, most of
+// them), so pairs inside that set are only re-orthogonalised (E = R / 2),
+// never rotated, and the refinement stops when the first-order error of Wm,
+// max over i != j of |S_ij| |f_i - f_j| / |l_i - l_j|, and ||R|| are both
+// below 1e-9, provided a Gershgorin bound keeps every eigenvalue of the
+// f = 0 block of S under thr^2.  It is abandoned (the original V and the
+// sweeps take over) when S is far from diagonal (the first call, from the
+// identity), when that bound fails, or after RP_MAX_REFINE passes, which is
+// what happens when a cluster of close eigenvalues straddles the threshold.
+__global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg,
+                                                     double2* rots, double* lam, int* sweeps) {
   constexpr int N = RP_MAX_FRAMES, LD = N + 1, NP = N / 2;
   static_assert(N == 64 && RB == 256, "64 x 64 matrices, 16 x 16 threads of 4 x 4 blocks");
   __shared__ double Am[N * LD];
   __shared__ double Vm[N * LD];
+  __shared__ double Gm[N * LD];
+  __shared__ double Rm[N * LD];
+  __shared__ double lt[N], ft[N];
+  __shared__ double red3[3][RB / 64];
+  __shared__ double red4[4][RB / 64];
   __shared__ double rot[NP][3];  // c, s, t = s / c
   __shared__ double red[2][RB / 64];
   __shared__ int prs[(N - 1) * NP];  // round r, pair k: p | q << 8
@@ -367,30 +498,119 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, cons
       gv = G[p * T - p * (p - 1) / 2 + (q - p)];
       vv = Vg[i * T + j];
     }
-    Am[i * LD + j] = gv;
+    Gm[i * LD + j] = gv;
     Vm[i * LD + j] = vv;
   }
   __syncthreads();
   const int bi = tid >> 4, bj = tid & 15;
   double acc[4][4];
-  // Am <- G V
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < N; ++k) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = Am[(4 * bi + u) * LD + k];
-      b[u] = Vm[k * LD + 4 * bj + u];
-    }
+
+  // ---- refinement of the warm start ----
+  double gn = 0.0, z0 = 0.0, z1 = 0.0;
+  for (int e = tid; e < N * N; e += RB) {
+    const double g = Gm[(e >> 6) * LD + (e & (N - 1))];
+    gn += g * g;
+  }
+  block_sum2_max(gn, z0, z1, red3);
+  gn = sqrt(gn);
+  bool refined = false;
+  for (int it = 0; it < RP_MAX_REFINE; ++it) {
+    mm64<false>(Gm, Vm, bi, bj, acc);  // G V
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
+    __syncthreads();
+    double vv[4][4];
+    mm64t_pair(Vm, Am, Vm, bi, bj, acc, vv);  // S = V^T G V, V^T V
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * bi + u, j = 4 * bj + v;
+        Am[i * LD + j] = acc[u][v];
+        Rm[i * LD + j] = (i == j ? 1.0 : 0.0) - vv[u][v];
+      }
+    __syncthreads();
+    if (tid < N) {
+      const double l = Am[tid * LD + tid] / (1.0 - Rm[tid * LD + tid]);
+      const double sg = sqrt(fmax(l, 0.0));
+      lt[tid] = l;
+      ft[tid] = (tid < T && sg > thr) ? 1.0 - thr / sg : 0.0;
+    }
+    __syncthreads();
+    // off: S off the diagonal over the pairs with f > 0 on either side (the
+    // basis inside the f = 0 set is never rotated); werr: the first-order
+    // error of Wm; gm: Gershgorin bound on the eigenvalues of the f = 0 block
+    // of S, which must stay under thr^2 for that block to hold no eigenvalue
+    // with f > 0.  Thread 4 i + q takes row i, columns q, q + 4, ...; the
+    // row's Gershgorin sum is combined from its four threads (consecutive
+    // lanes).
+    double off = 0.0, rn = 0.0, werr = 0.0, gm = -INFINITY;
+    {
+      const int i = tid >> 2, q = tid & 3;
+      const bool zi = i < T && ft[i] == 0.0;
+      double gs = 0.0;
+      if (i < T) {
+#pragma unroll 4
+        for (int j = q; j < T; j += 4) {
+          const double r = Rm[i * LD + j];
+          rn += r * r;
+          if (j != i) {
+            const double sij = Am[i * LD + j];
+            const double fj = ft[j];
+            if (ft[i] > 0.0 || fj > 0.0) off += sij * sij;
+            if (zi && fj == 0.0) gs += fabs(sij);
+            const double dl = fabs(lt[i] - lt[j]), df = fabs(ft[i] - fj);
+            if (df > 0.0) werr = fmax(werr, dl > 0.0 ? fabs(sij) * df / dl : INFINITY);
+          }
+        }
+      }
+      gs += __shfl_xor(gs, 1, 4);
+      gs += __shfl_xor(gs, 2, 4);
+      if (zi) gm = lt[i] + gs;
+    }
+    block_sum2_max2(off, rn, werr, gm, red4);  // uniform over the block
+    off = sqrt(off);
+    rn = sqrt(rn);
+    const bool zero_block_ok = gm <= thr * thr;
+    if (werr <= 1e-9 && rn <= 1e-9 && zero_block_ok) {
+      refined = true;
+      break;
+    }
+    if (!(off <= 1e-2 * gn) || !zero_block_ok || it + 1 == RP_MAX_REFINE) break;  // the sweeps take over
+    const double delta = 2.0 * (off + gn * rn);
+    for (int e = tid; e < N * N; e += RB) {  // E in place of R
+      const int i = e >> 6, j = e & (N - 1);
+      const double r = Rm[i * LD + j], dl = lt[j] - lt[i];
+      const bool rot = i != j && (ft[i] > 0.0 || ft[j] > 0.0) && fabs(dl) > delta;
+      Rm[i * LD + j] = rot ? (Am[i * LD + j] + lt[j] * r) / dl : 0.5 * r;
+    }
+    __syncthreads();
+    mm64<false>(Vm, Rm, bi, bj, acc);  // V E
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Vm[(4 * bi + u) * LD + 4 * bj + v] += acc[u][v];
+    __syncthreads();
   }
+  if (refined) {
+    if (tid < N) lam[tid] = lt[tid];
+    for (int e = tid; e < T * T; e += RB) Vg[e] = Vm[(e / T) * LD + e % T];
+    if (tid == 0) *sweeps = 0;
+    return;  // uniform
+  }
+  // the sweeps start again from the caller's V
+  for (int e = tid; e < N * N; e += RB) {
+    const int i = e >> 6, j = e & (N - 1);
+    Vm[i * LD + j] = (i < T && j < T) ? Vg[i * T + j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+
+  // Am <- G V
+  mm64<false>(Gm, Vm, bi, bj, acc);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -398,23 +618,7 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, cons
     for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
   __syncthreads();
   // Am <- V^T Am
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < N; ++k) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = Vm[k * LD + 4 * bi + u];
-      b[u] = Am[k * LD + 4 * bj + u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-  }
+  mm64<true>(Vm, Am, bi, bj, acc);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -858,7 +1062,7 @@ hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double*
 
 hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2* rots, double* lam, float* Wm,
                          int* sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, V, rots, lam, sweeps);
+  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, thr, V, rots, lam, sweeps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rp_vrot_kernel, dim3(T), dim3(64), 0, s, T, rots, sweeps, V);
