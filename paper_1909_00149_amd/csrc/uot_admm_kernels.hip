@@ -362,31 +362,39 @@ __device__ __forceinline__ void mm64(const double* X, const double* Y, int bi, i
   }
 }
 
-// acc1 = X^T Y1 and acc2 = X^T Y2 in one pass over k (the X loads shared).
-__device__ __forceinline__ void mm64t_pair(const double* X, const double* Y1, const double* Y2, int bi, int bj,
-                                           double (&acc1)[4][4], double (&acc2)[4][4]) {
+// The same products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  One
+// instruction forms a 16 x 16 tile from a 16 x 4 slice of op(X) (lane l
+// holds row l % 16, column l / 16) and a 4 x 16 slice of Y (row l / 16,
+// column l % 16), and lane l accumulates rows l / 16 + 4 r (r < 4), column
+// l % 16 of the tile.  Wave w forms the four tiles of rows 16 w .. 16 w + 15;
+// c[t][r] is element (16 w + l / 16 + 4 r, 16 t + l % 16).  With two Y, the
+// slices of op(X) are shared.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <bool TX, int NY>
+__device__ __forceinline__ void mm64_mfma(const double* X, const double* const (&Y)[NY], double (&c)[NY][4][4]) {
   constexpr int N = RP_MAX_FRAMES, LD = N + 1;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, m = l & 15, g = l >> 4;
+  f64x4 acc[NY][4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int y = 0; y < NY; ++y)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc1[u][v] = acc2[u][v] = 0.0;
-#pragma unroll 2
-  for (int k = 0; k < N; ++k) {
-    double a[4], b[4], c[4];
+    for (int t = 0; t < 4; ++t) acc[y][t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kc = 0; kc < N / 4; ++kc) {
+    const int row = 16 * w + m, col = 4 * kc + g;
+    const double a = TX ? X[col * LD + row] : X[row * LD + col];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = X[k * LD + 4 * bi + u];
-      b[u] = Y1[k * LD + 4 * bj + u];
-      c[u] = Y2[k * LD + 4 * bj + u];
-    }
+    for (int y = 0; y < NY; ++y)
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        acc1[u][v] = fma(a[u], b[v], acc1[u][v]);
-        acc2[u][v] = fma(a[u], c[v], acc2[u][v]);
-      }
+      for (int t = 0; t < 4; ++t)
+        acc[y][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Y[y][col * LD + 16 * t + m], acc[y][t], 0, 0, 0);
   }
+#pragma unroll
+  for (int y = 0; y < NY; ++y)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c[y][t][r] = acc[y][t][r];
 }
 
 // Two sums and a maximum over the block, the same in every thread (fixed
@@ -514,24 +522,33 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
   block_sum2_max(gn, z0, z1, red3);
   gn = sqrt(gn);
   bool refined = false;
+  // element (mi + 4 r, 16 t + mj) of a product is c[t][r] of this thread
+  const int mi = 16 * (tid >> 6) + ((tid & 63) >> 4), mj = tid & 15;
   for (int it = 0; it < RP_MAX_REFINE; ++it) {
-    mm64<false>(Gm, Vm, bi, bj, acc);  // G V
+    {
+      double c[1][4][4];
+      const double* const y1[1] = {Vm};
+      mm64_mfma<false, 1>(Gm, y1, c);  // G V
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
+        for (int r = 0; r < 4; ++r) Am[(mi + 4 * r) * LD + 16 * t + mj] = c[0][t][r];
+    }
     __syncthreads();
-    double vv[4][4];
-    mm64t_pair(Vm, Am, Vm, bi, bj, acc, vv);  // S = V^T G V, V^T V
-    __syncthreads();
+    {
+      double c[2][4][4];
+      const double* const y2[2] = {Am, Vm};
+      mm64_mfma<true, 2>(Vm, y2, c);  // S = V^T G V, V^T V
+      __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * bi + u, j = 4 * bj + v;
-        Am[i * LD + j] = acc[u][v];
-        Rm[i * LD + j] = (i == j ? 1.0 : 0.0) - vv[u][v];
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int i = mi + 4 * r, j = 16 * t + mj;
+          Am[i * LD + j] = c[0][t][r];
+          Rm[i * LD + j] = (i == j ? 1.0 : 0.0) - c[1][t][r];
+        }
+    }
     __syncthreads();
     if (tid < N) {
       const double l = Am[tid * LD + tid] / (1.0 - Rm[tid * LD + tid]);
@@ -588,12 +605,16 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
       Rm[i * LD + j] = rot ? (Am[i * LD + j] + lt[j] * r) / dl : 0.5 * r;
     }
     __syncthreads();
-    mm64<false>(Vm, Rm, bi, bj, acc);  // V E
-    __syncthreads();
+    {
+      double c[1][4][4];
+      const double* const y1[1] = {Rm};
+      mm64_mfma<false, 1>(Vm, y1, c);  // V E
+      __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Vm[(4 * bi + u) * LD + 4 * bj + v] += acc[u][v];
+        for (int r = 0; r < 4; ++r) Vm[(mi + 4 * r) * LD + 16 * t + mj] += c[0][t][r];
+    }
     __syncthreads();
   }
   if (refined) {
