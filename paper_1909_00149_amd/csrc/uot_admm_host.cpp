@@ -743,7 +743,7 @@ uot_status rpca_solve(rpca_handle* h, const float* y, const float* phi, float* S
   rep->r_dual = rd;
   rep->ms_per_iter = k > 0 ? (double)ms / k : 0.0;
   rep->seconds = elapsed_s(t0);
-  rep->jacobi_sweeps = sweeps;
+  rep->jacobi_sweeps = sweeps < 0 ? 0 : sweeps;  // -1: the warm start was refined, no sweep ran
   return UOT_OK;
 }
 

@@ -319,10 +319,12 @@ __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart,
 // the iteration moves little from one ADMM step to the next, so V^T G V is
 // nearly diagonal and one sweep usually finishes it.  Three kernels:
 //   rp_eig_kernel   A = V^T G V, then Jacobi sweeps on A; stores every
-//                   rotation (c, s) and the eigenvalues diag(A)
+//                   rotation (c, s) and the eigenvalues diag(A) (when the
+//                   refinement below succeeds: the refined V, its
+//                   eigenvalues and Wm, and no sweep)
 //   rp_vrot_kernel  applies the stored rotations to V, one row per workgroup
 //                   (rows are independent)
-//   rp_wm_kernel    Wm = V diag(f) V^T
+//   rp_wm_kernel    Wm = V diag(f) V^T after the sweeps
 // The matrices are padded to 64 x 64 (zero rows and columns of A, identity
 // in V; no rotation touches the padding since its off-diagonal entries stay
 // zero), so all index arithmetic is shifts.
@@ -478,7 +480,7 @@ __device__ __forceinline__ void block_sum2_max2(double& s0, double& s1, double& 
 // identity), when that bound fails, or after RP_MAX_REFINE passes, which is
 // what happens when a cluster of close eigenvalues straddles the threshold.
 __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg,
-                                                     double2* rots, double* lam, int* sweeps) {
+                                                     double2* rots, double* lam, float* Wm, int* sweeps) {
   constexpr int N = RP_MAX_FRAMES, LD = N + 1, NP = N / 2;
   static_assert(N == 64 && RB == 256, "64 x 64 matrices, 16 x 16 threads of 4 x 4 blocks");
   __shared__ double Am[N * LD];
@@ -618,9 +620,26 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     __syncthreads();
   }
   if (refined) {
+    // Wm = V diag(f) V^T here; sweeps = -1 tells rp_vrot and rp_wm to return.
+    // Rm <- diag(f) V^T, then V Rm on the matrix cores
     if (tid < N) lam[tid] = lt[tid];
     for (int e = tid; e < T * T; e += RB) Vg[e] = Vm[(e / T) * LD + e % T];
-    if (tid == 0) *sweeps = 0;
+    for (int e = tid; e < N * N; e += RB) {
+      const int k = e >> 6, j = e & (N - 1);
+      Rm[k * LD + j] = ft[k] * Vm[j * LD + k];
+    }
+    __syncthreads();
+    double c[1][4][4];
+    const double* const y1[1] = {Rm};
+    mm64_mfma<false, 1>(Vm, y1, c);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = mi + 4 * r, j = 16 * t + mj;
+        if (i < T && j < T) Wm[i * T + j] = (float)c[0][t][r];
+      }
+    if (tid == 0) *sweeps = -1;
     return;  // uniform
   }
   // the sweeps start again from the caller's V
@@ -742,8 +761,9 @@ __global__ __launch_bounds__(64) void rp_vrot_kernel(int T, const double2* rots,
   constexpr int N = RP_MAX_FRAMES, NP = N / 2, NR = (N - 1) * NP, N1 = N - 1;
   __shared__ double2 rs[NR];
   const int i = blockIdx.x, lane = threadIdx.x;
-  double v = lane < T ? Vg[i * T + lane] : 0.0;
   const int nsw = *sweeps;
+  if (nsw <= 0) return;  // uniform: no rotation to apply (-1: the eigensolve refined V itself)
+  double v = lane < T ? Vg[i * T + lane] : 0.0;
   for (int sw = 0; sw < nsw; ++sw) {
     __syncthreads();
 #pragma unroll
@@ -768,8 +788,10 @@ __global__ __launch_bounds__(64) void rp_vrot_kernel(int T, const double2* rots,
 }
 
 // Wm = V diag(f) V^T, f_k = max(1 - thr / sqrt(lam_k), 0) (FP32 result).
-__global__ __launch_bounds__(RB) void rp_wm_kernel(int T, double thr, const double* Vg, const double* lam, float* Wm) {
+__global__ __launch_bounds__(RB) void rp_wm_kernel(int T, double thr, const double* Vg, const double* lam,
+                                                    const int* sweeps, float* Wm) {
   constexpr int N = RP_MAX_FRAMES, LD = N + 1;
+  if (*sweeps < 0) return;  // uniform: the refinement already formed Wm
   __shared__ double Vm[N * LD];
   __shared__ double fj[N];
   const int tid = threadIdx.x;
@@ -1083,13 +1105,13 @@ hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double*
 
 hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2* rots, double* lam, float* Wm,
                          int* sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, thr, V, rots, lam, sweeps);
+  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, thr, V, rots, lam, Wm, sweeps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rp_vrot_kernel, dim3(T), dim3(64), 0, s, T, rots, sweeps, V);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rp_wm_kernel, dim3(1), dim3(RB), 0, s, T, thr, V, lam, Wm);
+  hipLaunchKernelGGL(rp_wm_kernel, dim3(1), dim3(RB), 0, s, T, thr, V, lam, sweeps, Wm);
   return hipGetLastError();
 }
 
