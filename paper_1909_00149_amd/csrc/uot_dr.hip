@@ -1,7 +1,7 @@
 // HIP kernels (gfx950) of the Douglas-Rachford splitting of the UOT
 // problems, the projection-based alternative to Algorithm 1:
-//   z = prox_{gamma G}(w)                 (dr_prox_kernel: z, u = 2 z - w)
-//   e = K u - b                            (dr_rhs_kernel)
+//   z = prox_{gamma G}(w), u = 2 z - w,
+//   e = K u - b                            (dr_prox_rhs_kernel)
 //   (n I + D D*) phi = e                   (the DCT Poisson solve)
 //   y = u - K^T phi,  w <- w + y - z       (dr_update_kernel)
 // G holds the separable terms: the flux norm (group or component shrink),
@@ -38,43 +38,77 @@ __device__ __forceinline__ double dr_block_sum(double v, double* red) {
 
 }  // namespace
 
-__global__ __launch_bounds__(DB) void dr_prox_kernel(DrArgs A) {
-  const long n = (long)A.nx * A.ny;
+// Prox of gamma times the flux norm at one pixel (group or component shrink).
+__device__ __forceinline__ void dr_flux_prox(float wx, float wy, float g, int aniso, float& zx, float& zy) {
+  if (aniso) {
+    zx = dr_shrink1(wx, g);
+    zy = dr_shrink1(wy, g);
+  } else {
+    const float n2 = wx * wx + wy * wy;
+    const float s = n2 > g * g ? 1.f - g * rsqrtf(n2) : 0.f;
+    zx = s * wx;
+    zy = s * wy;
+  }
+}
+
+// z = prox(w), u = 2 z - w, and e = K u - b in one pass: D M_u needs u's
+// flux at the left and lower neighbours, which is recomputed from w there
+// (the flux prox is per pixel), so u is not read back.
+__global__ __launch_bounds__(DB) void dr_prox_rhs_kernel(DrArgs A, float* out) {
+  const int nx = A.nx, ny = A.ny;
+  const long n = (long)nx * ny;
   const float g = A.gamma;
   for (long e = blockIdx.x * (long)DB + threadIdx.x; e < n; e += (long)gridDim.x * DB) {
+    const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
     const float wx = A.w.Mx[e], wy = A.w.My[e];
     float zx, zy;
-    if (A.aniso) {
-      zx = dr_shrink1(wx, g);
-      zy = dr_shrink1(wy, g);
-    } else {
-      const float n2 = wx * wx + wy * wy;
-      const float s = n2 > g * g ? 1.f - g * rsqrtf(n2) : 0.f;
-      zx = s * wx;
-      zy = s * wy;
-    }
+    dr_flux_prox(wx, wy, g, A.aniso, zx, zy);
+    const float ux = 2.f * zx - wx, uy = 2.f * zy - wy;
     A.z.Mx[e] = zx;
     A.z.My[e] = zy;
-    A.u.Mx[e] = 2.f * zx - wx;
-    A.u.My[e] = 2.f * zy - wy;
+    A.u.Mx[e] = ux;
+    A.u.My[e] = uy;
+    float uxl = 0.f, uyd = 0.f;
+    if (i > 0) {
+      const float lx = A.w.Mx[e - 1], ly = A.w.My[e - 1];
+      float qx, qy;
+      dr_flux_prox(lx, ly, g, A.aniso, qx, qy);
+      uxl = 2.f * qx - lx;
+    }
+    if (j > 0) {
+      const float dx = A.w.Mx[e - nx], dy = A.w.My[e - nx];
+      float qx, qy;
+      dr_flux_prox(dx, dy, g, A.aniso, qx, qy);
+      uyd = 2.f * qy - dy;
+    }
+    float v = (ux - uxl) + (uy - uyd);
     if (A.z.r) {
       const float wr = A.w.r[e];
       const float zr = A.resid == R_P1 ? dr_shrink1(wr, g * A.mu) : wr / (1.f + 2.f * g * A.mu);
+      const float ur = 2.f * zr - wr;
       A.z.r[e] = zr;
-      A.u.r[e] = 2.f * zr - wr;
+      A.u.r[e] = ur;
+      v -= ur;
     }
     if (A.z.x0) {
       const float wv = A.w.x0[e];
       const float zv = fmaxf((g * A.src[e] + A.rho * wv) / (A.rho + g), 0.f);
+      const float uv = 2.f * zv - wv;
       A.z.x0[e] = zv;
-      A.u.x0[e] = 2.f * zv - wv;
+      A.u.x0[e] = uv;
+      v -= uv;
     }
     if (A.z.x1) {
       const float wv = A.w.x1[e];
       const float zv = fmaxf((g * A.dst[e] + A.rho * wv) / (A.rho + g), 0.f);
+      const float uv = 2.f * zv - wv;
       A.z.x1[e] = zv;
-      A.u.x1[e] = 2.f * zv - wv;
+      A.u.x1[e] = uv;
+      v += uv;
     }
+    if (A.mode == 0) v += A.dst[e] - A.src[e];
+    if (A.mode == 2) v -= A.src[e];
+    out[e] = v;
   }
 }
 
@@ -173,8 +207,8 @@ __global__ __launch_bounds__(DB) void dr_objective_kernel(DrArgs A, double* part
 
 int dr_blocks(long n) { return (int)std::min<long>(DR_MAX_BLOCKS, std::max<long>(1, (n + DB - 1) / DB)); }
 
-hipError_t launch_dr_prox(const DrArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(dr_prox_kernel, dim3(dr_blocks((long)a.nx * a.ny)), dim3(DB), 0, s, a);
+hipError_t launch_dr_prox_rhs(const DrArgs& a, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(dr_prox_rhs_kernel, dim3(dr_blocks((long)a.nx * a.ny)), dim3(DB), 0, s, a, out);
   return hipGetLastError();
 }
 

@@ -1377,8 +1377,7 @@ uot_status uot_dr_solve(uot_handle* h, const float* src, const float* dst, uot_s
     float* phi = h->pw[2];
     HIPCHK(hipMemsetAsync(h->drbuf, 0, (size_t)n * 5 * sizeof(float), h->stream));
     auto iteration = [&](bool record) -> uot_status {
-      HIPCHK(launch_dr_prox(a, h->stream));
-      HIPCHK(launch_dr_rhs(a, 0, e, nullptr, h->stream));
+      HIPCHK(launch_dr_prox_rhs(a, e, h->stream));
       HIPCHK(poisson_solve(cx, cy, nx, ny, (float)nid, e, phi, h->pw[0], h->pw[1], h->stream));
       HIPCHK(launch_dr_update(a, phi, record ? 1 : 0, h->d_drp, h->stream));
       return UOT_OK;

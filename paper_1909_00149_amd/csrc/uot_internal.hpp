@@ -150,7 +150,7 @@ struct DrArgs {
 };
 constexpr int DR_MAX_BLOCKS = 1024;  // blocks of the DR kernels (partials per block: 3 at most)
 int dr_blocks(long n);
-hipError_t launch_dr_prox(const DrArgs& a, hipStream_t s);
+hipError_t launch_dr_prox_rhs(const DrArgs& a, float* out, hipStream_t s);  // z, u and e = K u - b
 hipError_t launch_dr_rhs(const DrArgs& a, int of_z, float* out, double* partial, hipStream_t s);
 hipError_t launch_dr_update(const DrArgs& a, const float* phi, int record, double* partial, hipStream_t s);
 hipError_t launch_dr_objective(const DrArgs& a, double* partial, hipStream_t s);

@@ -27,10 +27,15 @@ constexpr int GK = 32;   // K slab of one wave
 // order at the end.  Lane l supplies A[l%32][l/32] and B[l/32][l%32] of
 // each K = 2 step and holds C rows 8(r/4) + 4(l/32) + r%4, column l%32, in
 // accumulator register r.
-template <bool TA, bool TB>
+//
+// With SPEC the product is the forward transform T = Cy (c Cx^T) (M = ny,
+// N = nx), and each output element is divided by its eigenvalue
+// alpha + 4 sin^2(pi n / (2 N)) + 4 sin^2(pi m / (2 M)) on the way out (the
+// constant mode dropped when that is zero), in place of a separate pass.
+template <bool TA, bool TB, bool SPEC = false>
 __global__ __launch_bounds__(256) void sgemm_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
                                                     const float* __restrict__ B, int ldb, float* __restrict__ C,
-                                                    int ldc) {
+                                                    int ldc, float alpha = 0.f) {
   typedef float f32x16 __attribute__((ext_vector_type(16)));
   constexpr int LT = GT + 1;
   __shared__ float As[4][GK][LT];  // [wave][k][m]
@@ -109,26 +114,23 @@ __global__ __launch_bounds__(256) void sgemm_kernel(int M, int N, int K, const f
     part[(wv * GT + row) * LT + col] = acc[r];
   }
   __syncthreads();
+  // a thread's output column is the same for every q (256 is a multiple of 32)
+  const double sx = SPEC ? sin(3.14159265358979323846 * (n0 + (threadIdx.x & 31)) / (2.0 * N)) : 0.0;
 #pragma unroll
   for (int q = 0; q < GT * GT / 256; ++q) {
     const int idx = threadIdx.x + 256 * q, row = idx >> 5, col = idx & 31;
     const float v = ((part[(0 * GT + row) * LT + col] + part[(1 * GT + row) * LT + col]) +
                      part[(2 * GT + row) * LT + col]) + part[(3 * GT + row) * LT + col];
     const int m = m0 + row, n = n0 + col;
-    if (m < M && n < N) C[(long)m * ldc + n] = v;
-  }
-}
-
-// Divide the spectrum by alpha + lambda_y[j] + lambda_x[i]; the constant
-// mode is dropped when its eigenvalue is zero.
-__global__ void spectrum_divide_kernel(float* T, int nx, int ny, float alpha) {
-  const long n = (long)nx * ny;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const int j = (int)(e / nx), i = (int)(e - (long)j * nx);
-    const double sx = sin(3.14159265358979323846 * i / (2.0 * nx));
-    const double sy = sin(3.14159265358979323846 * j / (2.0 * ny));
-    const double lam = (double)alpha + 4.0 * sx * sx + 4.0 * sy * sy;
-    T[e] = lam > 0.0 ? (float)(T[e] / lam) : 0.f;
+    if (m < M && n < N) {
+      if (SPEC) {
+        const double sy = sin(3.14159265358979323846 * m / (2.0 * M));
+        const double lam = (double)alpha + 4.0 * sx * sx + 4.0 * sy * sy;
+        C[(long)m * ldc + n] = lam > 0.0 ? (float)(v / lam) : 0.f;
+      } else {
+        C[(long)m * ldc + n] = v;
+      }
+    }
   }
 }
 
@@ -223,10 +225,11 @@ static int elem_grid(long n) { return (int)std::min<long>(4096, std::max<long>(1
 hipError_t poisson_solve(const float* Cx, const float* Cy, int nx, int ny, float alpha, const float* rhs, float* phi,
                          float* t1, float* t2, hipStream_t s) {
   hipError_t e;
-  // T1 = rhs Cx^T (transform along x), T2 = Cy T1 (along y)
+  // T1 = rhs Cx^T (transform along x)
   if ((e = launch_sgemm(false, true, ny, nx, nx, rhs, nx, Cx, nx, t1, nx, s)) != hipSuccess) return e;
-  if ((e = launch_sgemm(false, false, ny, nx, ny, Cy, ny, t1, nx, t2, nx, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(spectrum_divide_kernel, dim3(elem_grid((long)nx * ny)), dim3(256), 0, s, t2, nx, ny, alpha);
+  // T2 = Cy T1 (along y), divided by the spectrum in the product's epilogue
+  hipLaunchKernelGGL((sgemm_kernel<false, false, true>), dim3((nx + GT - 1) / GT, (ny + GT - 1) / GT), dim3(256), 0,
+                     s, ny, nx, ny, Cy, ny, t1, nx, t2, nx, alpha);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // T1 = Cy^T T2, phi = T1 Cx
   if ((e = launch_sgemm(true, false, ny, nx, ny, Cy, ny, t2, nx, t1, nx, s)) != hipSuccess) return e;
