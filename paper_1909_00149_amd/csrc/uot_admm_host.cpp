@@ -379,7 +379,6 @@ struct rpca_handle {
   float *B = nullptr, *C = nullptr, *P0 = nullptr, *P1 = nullptr, *zo = nullptr, *wo = nullptr;
   float* st[2][RP_NPLANES] = {};
   double *d_gpart = nullptr, *d_G = nullptr, *d_V = nullptr, *d_lam = nullptr;
-  double2* d_rot = nullptr;
   float* d_Wm = nullptr;
   int* d_sweeps = nullptr;
   int gblocks = 1;
@@ -409,7 +408,6 @@ struct rpca_handle {
         if (q) (void)hipFree(q);
     for (double* q : {d_gpart, d_G, d_V, d_lam, d_partial, d_sums})
       if (q) (void)hipFree(q);
-    if (d_rot) (void)hipFree(d_rot);
     if (d_sweeps) (void)hipFree(d_sweeps);
     if (d_pairs) (void)hipFree(d_pairs);
     if (d_tiles) (void)hipFree(d_tiles);
@@ -471,7 +469,7 @@ uot_status rp_iteration(rpca_handle* h, const float* y, const float* phi, int i,
   if (i == 0) DFCHK(launch_rp_sx(a, h->bx, h->stream));
   DFCHK(launch_rp_gram(a, h->gblocks, h->d_gpart, h->stream));
   DFCHK(launch_rp_gram_reduce(h->d_gpart, h->gblocks, P.frames, h->d_G, h->stream));
-  DFCHK(launch_rp_eig(h->d_G, P.frames, P.gam / P.rho, h->d_V, h->d_rot, h->d_lam, h->d_Wm, h->d_sweeps,
+  DFCHK(launch_rp_eig(h->d_G, P.frames, P.gam / P.rho, h->d_V, h->d_lam, h->d_Wm, h->d_sweeps,
                       h->stream));
   DFCHK(launch_rp_svt_apply(a, h->sblocks, h->stream));
   for (int left = P.prox_iters; left > 0;) {
@@ -608,7 +606,6 @@ uot_status rpca_create(const rpca_params* prm, void* hip_stream, rpca_handle** o
       hipMalloc((void**)&h->d_V, (size_t)Tf * Tf * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->d_Wm, (size_t)Tf * Tf * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&h->d_lam, RP_MAX_FRAMES * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&h->d_rot, (size_t)RP_MAX_SWEEPS * RP_ROT_PER_SWEEP * sizeof(double2)) != hipSuccess ||
       hipMalloc((void**)&h->d_sweeps, sizeof(int)) != hipSuccess)
     return fail(UOT_ERR_OOM);
 
@@ -743,7 +740,7 @@ uot_status rpca_solve(rpca_handle* h, const float* y, const float* phi, float* S
   rep->r_dual = rd;
   rep->ms_per_iter = k > 0 ? (double)ms / k : 0.0;
   rep->seconds = elapsed_s(t0);
-  rep->jacobi_sweeps = sweeps < 0 ? 0 : sweeps;  // -1: the warm start was refined, no sweep ran
+  rep->jacobi_sweeps = sweeps;  // 0 when the warm start was refined
   return UOT_OK;
 }
 

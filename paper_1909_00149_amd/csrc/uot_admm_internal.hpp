@@ -27,9 +27,8 @@ struct DfArgs {
 // planes (b, c, prox centres, the prox state's z and w) hold T - 1 frames.
 constexpr int RP_MAX_FRAMES = 64;  // the Gram eigensolve keeps T x T in LDS
 constexpr int RP_SLOTS = 5;        // residual partial slots per block
-constexpr int RP_MAX_SWEEPS = 40;  // Jacobi sweeps per eigensolve (rotations stored for each)
+constexpr int RP_MAX_SWEEPS = 40;  // Jacobi sweeps per eigensolve
 constexpr int RP_MAX_REFINE = 3;  // refinement passes of the warm start before the sweeps
-constexpr long RP_ROT_PER_SWEEP = (RP_MAX_FRAMES - 1) * (RP_MAX_FRAMES / 2);
 struct RpArgs {
   long npx;                    // pixels per frame
   int T;                       // frames
@@ -58,10 +57,11 @@ int df_blocks(long n);
 hipError_t launch_rp_sx(const RpArgs& a, int bx, hipStream_t s);  // grid bx x T
 hipError_t launch_rp_gram(const RpArgs& a, int blocks, double* gpart, hipStream_t s);
 hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double* G, hipStream_t s);
-// Jacobi eigensolve of G warm-started from V (updated in place), then Wm;
-// rots holds RP_MAX_SWEEPS * RP_ROT_PER_SWEEP rotations, lam 64 eigenvalues.
-hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2* rots, double* lam, float* Wm,
-                         int* sweeps, hipStream_t s);
+// Eigensolve of G warm-started from V (updated in place): refinement by
+// matrix products, else Jacobi sweeps; then Wm.  lam holds 64 eigenvalues,
+// sweeps the number of Jacobi sweeps run (0 after a refinement).
+hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double* lam, float* Wm, int* sweeps,
+                         hipStream_t s);
 hipError_t launch_rp_svt_apply(const RpArgs& a, int blocks, hipStream_t s);
 hipError_t launch_rp_dual(const RpArgs& a, int bx, hipStream_t s);  // grid bx x T
 hipError_t launch_rp_reduce(const double* partial, int pstride, const RpCounts& cnt, double* out, hipStream_t s);

@@ -313,18 +313,13 @@ __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart,
 
 // Singular-value threshold of M from its Gram matrix G = M^T M = V Lam V^T:
 // SVT_thr(M) = M V diag(f) V^T with f_j = max(1 - thr / sigma_j, 0),
-// sigma_j = sqrt(lam_j).  The eigenvectors come from the cyclic Jacobi
+// sigma_j = sqrt(lam_j).  One kernel, one workgroup (rp_eig_kernel), from
+// the previous call's eigenvectors V: the iteration moves little from one
+// ADMM step to the next, so V^T G V is nearly diagonal.  V is refined by
+// matrix products (below); where that does not apply, the cyclic Jacobi
 // method with the parallel round-robin ordering (every round rotates 32
-// disjoint pairs at once), started from the previous call's eigenvectors V:
-// the iteration moves little from one ADMM step to the next, so V^T G V is
-// nearly diagonal and one sweep usually finishes it.  Three kernels:
-//   rp_eig_kernel   A = V^T G V, then Jacobi sweeps on A; stores every
-//                   rotation (c, s) and the eigenvalues diag(A) (when the
-//                   refinement below succeeds: the refined V, its
-//                   eigenvalues and Wm, and no sweep)
-//   rp_vrot_kernel  applies the stored rotations to V, one row per workgroup
-//                   (rows are independent)
-//   rp_wm_kernel    Wm = V diag(f) V^T after the sweeps
+// disjoint pairs at once) diagonalises A = V^T G V and rotates V alongside.
+// Either way the kernel leaves V, the eigenvalues and Wm = V diag(f) V^T.
 // The matrices are padded to 64 x 64 (zero rows and columns of A, identity
 // in V; no rotation touches the padding since its off-diagonal entries stay
 // zero), so all index arithmetic is shifts.
@@ -479,8 +474,8 @@ __device__ __forceinline__ void block_sum2_max2(double& s0, double& s1, double& 
 // sweeps take over) when S is far from diagonal (the first call, from the
 // identity), when that bound fails, or after RP_MAX_REFINE passes, which is
 // what happens when a cluster of close eigenvalues straddles the threshold.
-__global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg,
-                                                     double2* rots, double* lam, float* Wm, int* sweeps) {
+__global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, double thr, double* Vg, double* lam,
+                                                     float* Wm, int* sweeps) {
   constexpr int N = RP_MAX_FRAMES, LD = N + 1, NP = N / 2;
   static_assert(N == 64 && RB == 256, "64 x 64 matrices, 16 x 16 threads of 4 x 4 blocks");
   __shared__ double Am[N * LD];
@@ -619,10 +614,9 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     }
     __syncthreads();
   }
-  if (refined) {
-    // Wm = V diag(f) V^T here; sweeps = -1 tells rp_vrot and rp_wm to return.
-    // Rm <- diag(f) V^T, then V Rm on the matrix cores
-    if (tid < N) lam[tid] = lt[tid];
+  // The result: the eigenvalues, V, and Wm = V diag(f) V^T (Rm <- diag(f)
+  // V^T, then V Rm on the matrix cores); ft must hold f.
+  auto finish = [&](int nsweeps) {
     for (int e = tid; e < T * T; e += RB) Vg[e] = Vm[(e / T) * LD + e % T];
     for (int e = tid; e < N * N; e += RB) {
       const int k = e >> 6, j = e & (N - 1);
@@ -639,7 +633,11 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
         const int i = mi + 4 * r, j = 16 * t + mj;
         if (i < T && j < T) Wm[i * T + j] = (float)c[0][t][r];
       }
-    if (tid == 0) *sweeps = -1;
+    if (tid == 0) *sweeps = nsweeps;
+  };
+  if (refined) {
+    if (tid < N) lam[tid] = lt[tid];
+    finish(0);
     return;  // uniform
   }
   // the sweeps start again from the caller's V
@@ -711,9 +709,18 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
         rot[tid][0] = c;
         rot[tid][1] = s_;
         rot[tid][2] = t;
-        rots[((long)sweep * (N - 1) + r) * NP + tid] = make_double2(c, s_);
       }
       __syncthreads();
+      // V <- V J: row i, pair k: (V_ip, V_iq) <- (c V_ip - s V_iq, s V_ip + c V_iq)
+#pragma unroll
+      for (int m = 0; m < N * NP / RB; ++m) {
+        const int e = tid + RB * m, i = e >> 5, k = e & (NP - 1);
+        const int pq = prs[r * NP + k], p = pq & 255, q = pq >> 8;
+        const double c = rot[k][0], sn = rot[k][1];
+        const double vp = Vm[i * LD + p], vq = Vm[i * LD + q];
+        Vm[i * LD + p] = c * vp - sn * vq;
+        Vm[i * LD + q] = sn * vp + c * vq;
+      }
       // every upper-triangle block of this round, branch-free: a diagonal
       // block (k1 = k2) writes its first off-diagonal slot twice, both zero
       const int k2 = tid & (NP - 1), pq2 = prs[r * NP + k2], p2 = pq2 & 255, q2 = pq2 >> 8;
@@ -748,90 +755,13 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
       __syncthreads();
     }
   }
-  if (tid < N) lam[tid] = Am[tid * LD + tid];
-  if (tid == 0) *sweeps = sweep;
-}
-
-// V <- V J for every stored rotation, in order; workgroup i (one wave) owns
-// row i of V, lane j its entry j (rows at and beyond T are identity rows
-// that no rotation touches).  In round r the partner of j is 2r - j mod 63
-// (j = 63 and j = r pair with each other), which a shuffle fetches.  A
-// sweep's rotations (63 rounds of 32) are staged in LDS first.
-__global__ __launch_bounds__(64) void rp_vrot_kernel(int T, const double2* rots, const int* sweeps, double* Vg) {
-  constexpr int N = RP_MAX_FRAMES, NP = N / 2, NR = (N - 1) * NP, N1 = N - 1;
-  __shared__ double2 rs[NR];
-  const int i = blockIdx.x, lane = threadIdx.x;
-  const int nsw = *sweeps;
-  if (nsw <= 0) return;  // uniform: no rotation to apply (-1: the eigensolve refined V itself)
-  double v = lane < T ? Vg[i * T + lane] : 0.0;
-  for (int sw = 0; sw < nsw; ++sw) {
-    __syncthreads();
-#pragma unroll
-    for (int e = lane; e < NR; e += 64) rs[e] = rots[(long)sw * NR + e];
-    __syncthreads();
-    for (int r = 0; r < N1; ++r) {
-      int partner, k;
-      if (lane == N1 || lane == r) {
-        partner = lane == N1 ? r : N1;
-        k = 0;
-      } else {
-        partner = (2 * r - lane + 2 * N1) % N1;
-        const int d = (lane - r + N1) % N1;
-        k = d <= NP - 1 ? d : N1 - d;
-      }
-      const double2 cs = rs[r * NP + k];
-      const double w = __shfl(v, partner, 64);
-      v = lane < partner ? cs.x * v - cs.y * w : cs.y * w + cs.x * v;
-    }
-  }
-  if (lane < T) Vg[i * T + lane] = v;
-}
-
-// Wm = V diag(f) V^T, f_k = max(1 - thr / sqrt(lam_k), 0) (FP32 result).
-__global__ __launch_bounds__(RB) void rp_wm_kernel(int T, double thr, const double* Vg, const double* lam,
-                                                    const int* sweeps, float* Wm) {
-  constexpr int N = RP_MAX_FRAMES, LD = N + 1;
-  if (*sweeps < 0) return;  // uniform: the refinement already formed Wm
-  __shared__ double Vm[N * LD];
-  __shared__ double fj[N];
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int e = tid; e < N * N; e += RB) {
-    const int i = e >> 6, j = e & (N - 1);
-    Vm[i * LD + j] = (i < T && j < T) ? Vg[i * T + j] : 0.0;
-  }
   if (tid < N) {
-    const double sig = sqrt(fmax(lam[tid], 0.0));
-    fj[tid] = (tid < T && sig > thr) ? 1.0 - thr / sig : 0.0;
+    const double l = Am[tid * LD + tid], sg = sqrt(fmax(l, 0.0));
+    lam[tid] = l;
+    ft[tid] = (tid < T && sg > thr) ? 1.0 - thr / sg : 0.0;
   }
   __syncthreads();
-  const int bi = tid >> 4, bj = tid & 15;
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < N; ++k) {
-    const double f = fj[k];
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = Vm[(4 * bi + u) * LD + k] * f;
-      b[u] = Vm[(4 * bj + u) * LD + k];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 4 * bi + u, j = 4 * bj + v;
-      if (i < T && j < T) Wm[i * T + j] = (float)acc[u][v];
-    }
+  finish(sweep);
 }
 
 // Tn = (L + D) Wm per pixel, then D <- (L + D) - Tn (= D + L - Tn): for 32
@@ -1103,15 +1033,9 @@ hipError_t launch_rp_gram_reduce(const double* gpart, int blocks, int T, double*
   return hipGetLastError();
 }
 
-hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double2* rots, double* lam, float* Wm,
-                         int* sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, thr, V, rots, lam, Wm, sweeps);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rp_vrot_kernel, dim3(T), dim3(64), 0, s, T, rots, sweeps, V);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rp_wm_kernel, dim3(1), dim3(RB), 0, s, T, thr, V, lam, sweeps, Wm);
+hipError_t launch_rp_eig(const double* G, int T, double thr, double* V, double* lam, float* Wm, int* sweeps,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(rp_eig_kernel, dim3(1), dim3(RB), 0, s, G, T, thr, V, lam, Wm, sweeps);
   return hipGetLastError();
 }
 
