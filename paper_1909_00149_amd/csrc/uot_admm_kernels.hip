@@ -489,22 +489,27 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
   __shared__ double red[2][RB / 64];
   __shared__ int prs[(N - 1) * NP];  // round r, pair k: p | q << 8
   const int tid = threadIdx.x;
-  for (int e = tid; e < (N - 1) * NP; e += RB) {
-    int p, q;
-    rr_pair(e / NP, e % NP, p, q);
-    prs[e] = p | q << 8;
-  }
+  {
+    // all loads in flight before the first store
+    constexpr int PT = N * N / RB;
+    double gv[PT], vv[PT];
 #pragma unroll
-  for (int e = tid; e < N * N; e += RB) {
-    const int i = e >> 6, j = e & (N - 1);
-    double gv = 0.0, vv = i == j ? 1.0 : 0.0;
-    if (i < T && j < T) {
-      const int p = i < j ? i : j, q = i < j ? j : i;
-      gv = G[p * T - p * (p - 1) / 2 + (q - p)];
-      vv = Vg[i * T + j];
+    for (int m = 0; m < PT; ++m) {
+      const int e = tid + RB * m, i = e >> 6, j = e & (N - 1);
+      gv[m] = 0.0;
+      vv[m] = i == j ? 1.0 : 0.0;
+      if (i < T && j < T) {
+        const int p = i < j ? i : j, q = i < j ? j : i;
+        gv[m] = G[p * T - p * (p - 1) / 2 + (q - p)];
+        vv[m] = Vg[i * T + j];
+      }
     }
-    Gm[i * LD + j] = gv;
-    Vm[i * LD + j] = vv;
+#pragma unroll
+    for (int m = 0; m < PT; ++m) {
+      const int e = tid + RB * m, i = e >> 6, j = e & (N - 1);
+      Gm[i * LD + j] = gv[m];
+      Vm[i * LD + j] = vv[m];
+    }
   }
   __syncthreads();
   const int bi = tid >> 4, bj = tid & 15;
@@ -664,6 +669,11 @@ __global__ __launch_bounds__(RB) void rp_eig_kernel(const double* G, int T, doub
     for (int v = 0; v < 4; ++v) Am[(4 * bi + u) * LD + 4 * bj + v] = acc[u][v];
   __syncthreads();
 
+  for (int e = tid; e < (N - 1) * NP; e += RB) {  // the round-robin pairs (read after the next barrier)
+    int p, q;
+    rr_pair(e / NP, e % NP, p, q);
+    prs[e] = p | q << 8;
+  }
   auto up = [](int i, int j) { return i < j ? i * LD + j : j * LD + i; };  // upper-triangle slot
   int sweep = 0;
   for (; sweep < RP_MAX_SWEEPS; ++sweep) {
