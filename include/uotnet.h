@@ -8,8 +8,8 @@
  * library adds a learned start: a small encoder-decoder maps an image pair
  * (p, q) to an initial flux (Mx, My) and dual a, from which the residual is
  * completed as r = D M + q - p so that the start satisfies the constraint.
- * The plain cold-start solver remains the fallback and the judge of
- * convergence.
+ * The plain cold-start solver remains the fallback, and its stopping rule
+ * decides convergence either way.
  *
  * Network (U-Net, NHWC BF16 activations and weights, FP32 accumulation on
  * the matrix cores, FP32 master weights and Adam moments):
