@@ -287,12 +287,12 @@ __global__ __launch_bounds__(RB) void rp_gram_kernel(RpArgs A, double* gpart) {
 }
 
 // G[j] = sum over blocks of gpart[b][j]: a block adds 64 entries, its four
-// waves take every fourth partial (eight loads in flight, added in block
+// waves take every fourth partial (32 loads in flight, added in block
 // order), and the four sums are combined in a fixed order (the result does
 // not depend on timing).
 __global__ __launch_bounds__(RB) void rp_gram_reduce_kernel(const double* gpart, int blocks, int np, double* G) {
   __shared__ double red[RB / 64][64];
-  constexpr int Q = RB / 64, U = 8;
+  constexpr int Q = RB / 64, U = 32;
   const int jl = threadIdx.x & 63, q = threadIdx.x >> 6, j = blockIdx.x * 64 + jl;
   double v = 0.0;
   if (j < np) {
