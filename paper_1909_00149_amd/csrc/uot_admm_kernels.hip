@@ -979,13 +979,22 @@ __global__ __launch_bounds__(RB) void rp_sub_kernel(long n, const float* a, cons
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) out[i] = a[i] - b[i];
 }
 
-// out[j] = sum of the first count[j] partials of slot j (one block, fixed order).
+// out[j] = sum of the first count[j] partials of slot j: block j, fixed order.
 __global__ __launch_bounds__(RB) void rp_reduce_kernel(const double* partial, int pstride, RpCounts cnt, double* out) {
-  for (int j = 0; j < RP_SLOTS; ++j) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < cnt.n[j]; b += RB) v += partial[(long)j * pstride + b];
-    block_sum(v, out + j);
+  const int j = blockIdx.x;
+  const int n = cnt.n[j];
+  const double* p = partial + (long)j * pstride;
+  double v = 0.0;
+  int b = threadIdx.x;
+  for (; b + 7 * RB < n; b += 8 * RB) {  // eight loads in flight, added in order
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = p[b + u * RB];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += w[u];
   }
+  for (; b < n; b += RB) v += p[b];
+  block_sum(v, out + j);
 }
 
 // Input check: counts the non-finite entries of y and phi into slot 0.
@@ -1072,7 +1081,7 @@ hipError_t launch_rp_sub(long n, const float* a, const float* b, float* out, hip
 }
 
 hipError_t launch_rp_reduce(const double* partial, int pstride, const RpCounts& cnt, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(rp_reduce_kernel, dim3(1), dim3(RB), 0, s, partial, pstride, cnt, out);
+  hipLaunchKernelGGL(rp_reduce_kernel, dim3(RP_SLOTS), dim3(RB), 0, s, partial, pstride, cnt, out);
   return hipGetLastError();
 }
 
