@@ -103,13 +103,12 @@ __global__ __launch_bounds__(RB) void df_absx_kernel(DfArgs A) {
   if (A.record) block_sum(dx2, A.partial + 3 * blockIdx.x + 1);
 }
 
-// out[j] = sum over blocks of partial[3 b + j], j = 0..2 (one block).
+// out[j] = sum over blocks of partial[3 b + j], j = 0..2 (block j, fixed order).
 __global__ __launch_bounds__(RB) void df_reduce_kernel(const double* partial, int nblocks, double* out) {
-  for (int j = 0; j < 3; ++j) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += RB) v += partial[3 * b + j];
-    block_sum(v, out + j);
-  }
+  const int j = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += RB) v += partial[3 * b + j];
+  block_sum(v, out + j);
 }
 
 // Input check: counts non-finite entries of y, phi, s0 and negative entries
@@ -1025,7 +1024,7 @@ hipError_t launch_df_absx(const DfArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_df_reduce(const double* partial, int nblocks, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(df_reduce_kernel, dim3(1), dim3(RB), 0, s, partial, nblocks, out);
+  hipLaunchKernelGGL(df_reduce_kernel, dim3(3), dim3(RB), 0, s, partial, nblocks, out);
   return hipGetLastError();
 }
 
