@@ -58,12 +58,20 @@ __global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
 
 // Stopping decision for pair b after a window of W iterations (device side,
 // so that captured windows need no host round trip).
-__device__ void decide_pair(const DecideArgs& A, int b, const double* S) {
-  if (!A.active[b]) return;
-  A.iters[b] += A.W;
+// The pair's flag, iteration count, norm and adaptation factor come in
+// preloaded (read at the start of the reduction, in flight with it).
+struct DecidePre {
+  int active, iters;
+  double xnorm, alpha;
+};
+
+__device__ void decide_pair(const DecideArgs& A, int b, const double* S, const PairInfo& P0, const DecidePre& pre) {
+  if (!pre.active) return;
+  const int iters = pre.iters + A.W;
+  A.iters[b] = iters;
   bool done = false;
   if (A.check) {
-    const double xn = A.mode == 0 ? A.xnorm[b] : sqrt(S[S_X0SQ]) + sqrt(S[S_X1SQ]);
+    const double xn = A.mode == 0 ? pre.xnorm : sqrt(S[S_X0SQ]) + sqrt(S[S_X1SQ]);
     const double p = sqrt(S[S_PRES2]) / fmax(xn, 1e-30);
     const double d = sqrt(S[S_STAT2]) / fmax(sqrt(S[S_KA2]), 1e-30);
     const double rel = fmax(p, d);
@@ -79,8 +87,8 @@ __device__ void decide_pair(const DecideArgs& A, int b, const double* S) {
       // residual balancing: keep tau1*tau2, move the ratio toward the side
       // whose relative residual lags
       PairInfo& P = A.pairs[b];
-      const double al = A.alpha[b];
-      double t1 = P.tau1, t2 = P.tau2;
+      const double al = pre.alpha;
+      double t1 = P0.tau1, t2 = P0.tau2;
       bool ch = false;
       if (d > 1.5 * p) {
         t1 /= (1.0 - al);
@@ -101,7 +109,7 @@ __device__ void decide_pair(const DecideArgs& A, int b, const double* S) {
       }
     }
   }
-  if (!done && (A.final_pass || A.iters[b] >= A.max_iter)) {
+  if (!done && (A.final_pass || iters >= A.max_iter)) {
     A.status[b] = 1;
     done = true;
   }
@@ -116,7 +124,14 @@ __global__ __launch_bounds__(BLOCK) void pair_reduce_kernel(const PairInfo* pair
   const int b = blockIdx.x;
   const PairInfo P = pairs[b];
   // uniform: a stopped pair keeps its record; the final pass still sums it
-  if (do_decide && !dec.active[b] && !dec.final_pass) return;
+  const int act = do_decide ? dec.active[b] : 0;
+  if (do_decide && !act && !dec.final_pass) return;
+  DecidePre pre{act, 0, 0.0, 0.0};
+  if (do_decide && threadIdx.x == 0) {
+    pre.iters = dec.iters[b];
+    if (dec.mode == 0) pre.xnorm = dec.xnorm[b];
+    if (dec.adaptive) pre.alpha = dec.alpha[b];
+  }
   // thread (group g, slot s): slot s of the pair's tiles g, g + 16, ..., so a
   // wave reads four whole partial rows per step
   static_assert(NS == 16 && BLOCK == 256, "16 slots x 16 groups");
@@ -148,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void pair_reduce_kernel(const PairInfo* pair
     fin[s] = u;
   }
   __syncthreads();
-  if (do_decide && threadIdx.x == 0) decide_pair(dec, b, fin);
+  if (do_decide && threadIdx.x == 0) decide_pair(dec, b, fin, P, pre);
 }
 
 // Copies the current iterate from src to dst for pairs still active.
