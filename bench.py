@@ -77,14 +77,14 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # the figure unknown (null) until the counters are taken again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "9cbdbf91fc4b9123d0501ead3bf5756a45ac68fe043ddef3f2a1c214c7789307"
+TRAFFIC_SHA256 = "4f23132b5edcbc675c3f9b1556cea5421652f4c9c46bb8e50f5fa9b6f8425002"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 TRAFFIC_KIB = {
     "pair512": (4008, 2876.928, 4096.000),
-    "ragged256": (4016, 159272.940, 231696.539),
-    "sweep4096": (4016, 216101.793, 262144.906),
-    "video63": (4016, 64904.005, 96769.066),
+    "ragged256": (4016, 159274.156, 231696.491),
+    "sweep4096": (4016, 214475.684, 262148.915),
+    "video63": (4016, 64862.759, 96768.139),
 }
 
 
