@@ -28,9 +28,14 @@
  *   - stopping rule: rel_res = max(||K z^k|| / (||x0^k|| + ||x1^k||),
  *     ||(z^{k-1}-z^k)/tau1 - K*(a^{k-1}-a^k)|| / ||K* a^k||) <= tol,
  *     tested every check_every iterations.
- *   - default steps tau1 = tau2 = 0.99 / ||K|| with ||K||^2 = lambda_max(D D*)
- *     + (number of identity blocks of K), which keeps tau1 tau2 ||K||^2 < 1
- *     (Theorem 1).  The paper tunes its steps by search and fixes no rule;
+ *   - default steps tau1 = 0.99 s / ||K||, tau2 = 0.99 / (s ||K||) with
+ *     ||K||^2 = lambda_max(D D*) + (number of identity blocks of K), which
+ *     keeps tau1 tau2 ||K||^2 = 0.98 < 1 (Theorem 1), and s the image scale
+ *     of the pair: the largest |pixel| of src and dst (1 if both are zero).
+ *     The problem is 1-homogeneous (images scaled by t scale M and r by t
+ *     and leave a unchanged), so tying tau1 / tau2 to s^2 makes the
+ *     iterates of scaled images the scaled iterates.  The paper tunes its
+ *     steps by search and fixes no rule;
  *     UOT_ADAPTIVE_STEPS keeps the product tau1 tau2 and rebalances the
  *     ratio at every check by residual balancing (adaptive primal-dual
  *     hybrid gradient, Goldstein, Li and Yuan): when the relative
@@ -99,7 +104,8 @@ typedef struct uot_params {
   int32_t bc;           /* 0 zero flux (default), 1 literal boundary                  */
   double mu;            /* growth/decay weight mu > 0 (unbalanced only)               */
   double rho;           /* prox step rho > 0 (PROX modes)                             */
-  double tau1, tau2;    /* primal / dual steps; 0 selects 0.99/||K|| for both         */
+  double tau1, tau2;    /* primal / dual steps; 0 (both) selects the scaled default
+                           0.99 s/||K||, 0.99/(s ||K||) per pair (see above)          */
   int32_t max_iter;     /* iteration cap, >= 0                                        */
   int32_t check_every;  /* iterations between convergence checks (rounded up to even) */
   double tol;           /* stop when rel_res <= tol; <= 0 runs exactly max_iter       */
@@ -126,7 +132,12 @@ typedef struct uot_params {
                            flux prox (group vs component shrink), the flux norm in
                            objectives and the dual feasibility (||.||_2 vs ||.||_inf)
                            of the certified bounds                                   */
-  int32_t reserved;
+  int32_t max_groups;   /* upper bound on the workgroups of the persistent launches (the
+                           fused iteration, the check, set-up and copy kernels walk the
+                           tile list with a fixed grid); rounded down to a multiple of 8
+                           (the XCD count), at least 8.  0 = as many as fill the device.
+                           Results do not depend on it: every tile is computed alike by
+                           whichever workgroup visits it                              */
 } uot_params;
 
 enum { UOT_NORM_ISO = 0, UOT_NORM_ANISO = 1 };

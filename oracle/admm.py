@@ -89,7 +89,7 @@ def df_iterate(y, s0, st: DfState, kappa, mu, rho, phi=None, lam=0.0, balanced=F
     s = np.maximum(0.5 * ((st.x + st.a) + (st.z + st.b)) - lam / (2.0 * rho), 0.0)
     x = (ph * y + rho * (s - st.a)) / (ph * ph + rho)
     prob = df_problem(s0, s - st.b, kappa, mu, rho, balanced, residual_p, bc)
-    t1, t2 = prob.default_steps() if tau is None else tau
+    t1, t2 = prob.unit_steps() if tau is None else tau
     pst = st.prox
     for _ in range(prox_iters):
         pst = uot.iterate(prob, pst, t1, t2)
@@ -242,7 +242,7 @@ def rpca_iterate(Y, st: RpcaState, kappa, mu, rho, lam, gam, phi=None, balanced=
     prox = []
     for t in range(T - 1):
         prob = rpca_problem(S[t] - st.b[t], S[t + 1] - st.c[t], kappa, mu, rho, balanced, residual_p, bc)
-        t1, t2 = prob.default_steps() if tau is None else tau
+        t1, t2 = prob.unit_steps() if tau is None else tau
         pst = st.prox[t]
         for _ in range(prox_iters):
             pst = uot.iterate(prob, pst, t1, t2)
@@ -386,7 +386,7 @@ def _pair_prox(S, b, c, prox, kappa, mu, rho, balanced, residual_p, bc, prox_ite
     out = []
     for t in range(S.shape[0] - 1):
         prob = rpca_problem(S[t] - b[t], S[t + 1] - c[t], kappa, mu, rho, balanced, residual_p, bc)
-        t1, t2 = prob.default_steps() if tau is None else tau
+        t1, t2 = prob.unit_steps() if tau is None else tau
         pst = prox[t]
         for _ in range(prox_iters):
             pst = uot.iterate(prob, pst, t1, t2)

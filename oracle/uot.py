@@ -74,10 +74,30 @@ class Problem:
         ny, nx = self.shape
         return ops.knorm2(nx, ny, self.mode, self.balanced, self.bc)
 
-    def default_steps(self):
+    def image_scale(self):
+        """s = the largest |pixel| of the two images (1 if both are zero)."""
+        s = max(float(np.max(np.abs(self.src), initial=0.0)), float(np.max(np.abs(self.dst), initial=0.0)))
+        return s if np.isfinite(s) and s > 0.0 else 1.0
+
+    def unit_steps(self):
         """tau1 = tau2 = 0.99 / ||K||, so tau1 tau2 ||K||^2 = 0.98 < 1 (Theorem 1)."""
         t = 0.99 / np.sqrt(self.knorm2())
         return t, t
+
+    def default_steps(self):
+        """Steps that follow the image scale s (``image_scale``):
+        tau1 = 0.99 s / ||K||, tau2 = 0.99 / (s ||K||).
+
+        The paper tunes its steps by search.  This default uses the
+        1-homogeneity of the problem: with both images scaled by t the
+        minimisers M, r scale by t and the multiplier a does not change, and
+        one iteration on the scaled images with (tau1, tau2) is one iteration
+        on the originals with (tau1 / t, tau2 t).  Tying tau1 / tau2 to s^2
+        makes the iterates of scaled images the scaled iterates.  The product
+        tau1 tau2 ||K||^2 = 0.98 < 1 (Theorem 1) does not depend on s."""
+        k = np.sqrt(self.knorm2())
+        s = self.image_scale()
+        return 0.99 * s / k, 0.99 / (s * k)
 
 
 @dataclass
@@ -295,10 +315,14 @@ def relative_residuals(prob: Problem, prev: State, cur: State, tau1: float):
 
 
 def solve(prob: Problem, tau1=None, tau2=None, max_iter=1000, check_every=20, tol=0.0,
-          state: State | None = None, record=False, adaptive=False):
+          state: State | None = None, record=False, adaptive=False, gap_tol=0.0, gap_every=1000):
     """Run Algorithm 1 from zero (or ``state``) until rel_res <= tol at a
     check (every ``check_every`` iterations) or ``max_iter`` iterations.
     tol <= 0 runs exactly ``max_iter`` iterations.
+
+    gap_tol > 0 also stops (status "CONVERGED") at the first multiple of
+    ``gap_every`` where the certified relative gap (``certified_gap``) is
+    <= gap_tol, so that a run can be certified rather than trusted.
 
     adaptive: the paper fixes no step rule (its steps come from a parameter
     search).  With ``adaptive`` the product tau1 tau2 is kept and the ratio
@@ -322,6 +346,11 @@ def solve(prob: Problem, tau1=None, tau2=None, max_iter=1000, check_every=20, to
         st = iterate(prob, st, tau1, tau2)
         if not np.all(np.isfinite(st.a)):
             rep.iters, rep.status = k, "DIVERGED"
+            return st, rep
+        if gap_tol > 0 and k % gap_every == 0 and certified_gap(prob, st).rel_gap <= gap_tol:
+            rep.iters, rep.status = k, "CONVERGED"
+            rep.rel_res = max(relative_residuals(prob, prev, st, tau1))
+            rep.tau1, rep.tau2 = tau1, tau2
             return st, rep
         if (tol > 0 and k % check_every == 0) or (k == max_iter):
             rp, rd = relative_residuals(prob, prev, st, tau1)

@@ -28,7 +28,7 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("tile_rows", ctypes.c_int32), ("pitch", ctypes.c_int32),
-                ("norm", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("norm", ctypes.c_int32), ("max_groups", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):

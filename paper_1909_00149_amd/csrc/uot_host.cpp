@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -280,6 +281,7 @@ uot_status uot_check_params(const uot_params* p) {
   if (p->mode != UOT_DIST && !(p->rho > 0.0 && std::isfinite(p->rho))) return UOT_ERR_ARG;
   if (!(p->tau1 >= 0.0 && p->tau2 >= 0.0) || !std::isfinite(p->tau1) || !std::isfinite(p->tau2)) return UOT_ERR_ARG;
   if ((p->tau1 == 0.0) != (p->tau2 == 0.0)) return UOT_ERR_ARG;
+  if (p->max_groups < 0) return UOT_ERR_ARG;
   if (p->max_iter < 0 || p->check_every < 0) return UOT_ERR_ARG;
   if (!std::isfinite(p->tol)) return UOT_ERR_ARG;
   switch (p->tile_rows) {
@@ -340,6 +342,35 @@ namespace {
     }                                               \
   } while (0)
 
+// Default steps (tau1 = tau2 = 0 in the params).  The problem is
+// 1-homogeneous in the images: scaling p and q by t scales M and r by t and
+// leaves the multiplier a unchanged, and running the iteration on the
+// scaled images is running it on the originals with tau1 / t and tau2 t.
+// The default therefore follows the image scale s (the largest |pixel| of
+// the pair's two images; 1 if that is zero):
+//   tau1 = 0.99 s / ||K||,   tau2 = 0.99 / (s ||K||),
+// so the iterates of scaled images are the scaled iterates, and the
+// product tau1 tau2 ||K||^2 = 0.98 < 1 (Theorem 1) whatever s is.
+void default_steps(double k2, double scale, double* t1, double* t2) {
+  const double k = std::sqrt(k2);
+  *t1 = 0.99 * scale / k;
+  *t2 = 0.99 / (scale * k);
+}
+
+double image_scale(const double* setup_sums) {
+  const double s = setup_sums[U_MAXIN];
+  return std::isfinite(s) && s > 0.0 ? s : 1.0;
+}
+
+// The per-pair step fields the kernels read.
+void set_steps(const uot_params& p, PairInfo& P, double t1, double t2) {
+  P.tau1 = (float)t1;
+  P.tau2 = (float)t2;
+  P.theta = p.mode == UOT_DIST ? 0.f : (float)(t1 / (p.rho + t1));
+  P.mutau = (float)(p.mu * t1);
+  P.inv2mt = (float)(1.0 / (1.0 + 2.0 * p.mu * t1));
+}
+
 struct Job {
   int B = 0;
   std::vector<PairInfo> pairs;
@@ -360,17 +391,24 @@ Planes planes_of(const uot_state& s) { return Planes{s.Mx, s.My, s.r, s.a, s.x0,
 // reading, bit 1 the anisotropic flux norm.
 int bcn_of(const uot_params& p) { return p.bc | (p.norm == UOT_NORM_ANISO ? 2 : 0); }
 
+// The caller's cap on the persistent grids (uot_params.max_groups), rounded
+// down to a multiple of the 8 XCDs, at least 8; no cap when 0.
+long group_cap(const uot_handle* h) {
+  const int m = h->prm.max_groups;
+  return m > 0 ? std::max(8, m / 8 * 8) : LONG_MAX;
+}
+
 int iter_grid(uot_handle* h, int mode, int resid, int bc, int ty, int ntiles, bool chk = false) {
   int occ = 0;
   const hipError_t e = chk ? iter_chk_occupancy(mode, resid, bc, ty, &occ) : iter_occupancy(mode, resid, bc, ty, &occ);
   if (e != hipSuccess || occ <= 0) occ = chk ? 2 : 4;
   long g = std::min<long>((long)ntiles, (long)h->num_cu * occ);
   g = std::max<long>(8, (g + 7) / 8 * 8);
-  return (int)g;
+  return (int)std::min(g, group_cap(h));
 }
 
 int aux_grid(uot_handle* h, int ntiles) {
-  return std::max(1, std::min(ntiles, h->num_cu * 8));
+  return (int)std::max<long>(1, std::min<long>(std::min(ntiles, h->num_cu * 8), group_cap(h)));
 }
 
 uot_status validate_state(const uot_params& p, const uot_state* s) {
@@ -439,17 +477,13 @@ uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* 
     const double k2 = uot_knorm2(nx[b], ny[b], p.mode, p.balanced, p.bc);
     J.knorm2[b] = k2;
     double t1 = p.tau1, t2 = p.tau2;
-    if (t1 == 0.0) t1 = t2 = 0.99 / std::sqrt(k2);
+    if (t1 == 0.0) default_steps(k2, 1.0, &t1, &t2);  // rescaled once the image scale is known
     if (!(p.flags & UOT_UNSAFE_STEPS) && t1 * t2 * k2 >= 1.0) return UOT_ERR_STEP;
     PairInfo& P = J.pairs[b];
     P.off = offset[b];
     P.nx = nx[b];
     P.ny = ny[b];
-    P.tau1 = (float)t1;
-    P.tau2 = (float)t2;
-    P.theta = p.mode == UOT_DIST ? 0.f : (float)(t1 / (p.rho + t1));
-    P.mutau = (float)(p.mu * t1);
-    P.inv2mt = (float)(1.0 / (1.0 + 2.0 * p.mu * t1));
+    set_steps(p, P, t1, t2);
     P.tile_begin = (int32_t)J.tiles.size();
     for (int y = 0; y < ny[b]; y += ty)
       for (int x = 0; x < nx[b]; x += TX) J.tiles.push_back(Tile{b, x, y, (int32_t)J.tiles.size()});
@@ -531,7 +565,7 @@ uot_status run_setup(uot_handle* h, const Job& J, const float* src, const float*
   sa.tile_rows = J.ty;
   sa.partial = h->d_partial;
   HIPCHK(launch_setup(aux_grid(h, sa.ntiles), sa, h->stream));
-  HIPCHK(launch_pair_reduce(h->d_pairs, J.B, h->d_partial, 0u, h->d_sums, h->stream));
+  HIPCHK(launch_pair_reduce(h->d_pairs, J.B, h->d_partial, kMaxSlotsSetup, h->d_sums, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, (size_t)J.B * NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return UOT_OK;
@@ -550,6 +584,27 @@ uot_status check_setup_sums(uot_handle* h, const Job& J, bool warm) {
     }
   }
   return UOT_OK;
+}
+
+// Scales the default steps of every pair by its image scale (from the
+// setup sums in `scale`) and uploads the pair records.  No-op when the
+// caller gave the steps.
+uot_status scale_default_steps(uot_handle* h, Job& J, const std::vector<double>& scale) {
+  const uot_params& p = h->prm;
+  if (p.tau1 != 0.0) return UOT_OK;
+  for (int b = 0; b < J.B; ++b) {
+    double t1, t2;
+    default_steps(J.knorm2[b], scale[b], &t1, &t2);
+    set_steps(p, J.pairs[b], t1, t2);
+  }
+  HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), J.B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+  return UOT_OK;
+}
+
+std::vector<double> image_scales(const uot_handle* h, int B) {
+  std::vector<double> sc(B);
+  for (int b = 0; b < B; ++b) sc[b] = image_scale(h->h_sums + (size_t)b * NS);
+  return sc;
 }
 
 struct Reporter {
@@ -886,10 +941,13 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   if (s != UOT_OK) return s;
   s = check_setup_sums(h, J, warm);
   if (s != UOT_OK) return s;
+  const std::vector<double> scale = image_scales(h, B);
   if ((p.flags & UOT_AUTOTUNE) && p.tile_rows == 0 && !cached) {
     s = autotune(h, lay, src, dst, st, J);
     if (s != UOT_OK) return s;
   }
+  s = scale_default_steps(h, J, scale);
+  if (s != UOT_OK) return s;
 
   // per-pair host bookkeeping
   int32_t* h_active = h->h_i32;
@@ -1100,6 +1158,8 @@ uot_status time_core(uot_handle* h, const Layout& L, const float* src, const flo
                         h->stream));
   s = run_setup(h, J, src, dst, st, true, false);
   if (s != UOT_OK) return s;
+  s = scale_default_steps(h, J, image_scales(h, B));
+  if (s != UOT_OK) return s;
   for (int b = 0; b < B; ++b) h->h_i32[b] = 1;
   HIPCHK(hipMemcpyAsync(h->d_i32, h->h_i32, (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   s = upload_live(h, J, h->h_i32);
@@ -1243,10 +1303,12 @@ uot_status uot_objective(uot_handle* h, const float* src, const float* dst, cons
     sa.tile_rows = J.ty;
     sa.partial = h->d_partial;
     HIPCHK(launch_setup(aux_grid(h, sa.ntiles), sa, h->stream));
-    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, 0u, h->d_sums, h->stream));
+    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, kMaxSlotsSetup, h->d_sums, h->stream));
     HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     const double xn = std::sqrt(h->h_sums[U_SQS]) + std::sqrt(h->h_sums[U_SQD]);
+    s = scale_default_steps(h, J, image_scales(h, 1));
+    if (s != UOT_OK) return s;
     int32_t one = 1;
     HIPCHK(hipMemcpyAsync(h->d_i32, &one, sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
     const uot_state* q = prev ? prev : st;
@@ -1333,7 +1395,7 @@ uot_status uot_dr_solve(uot_handle* h, const float* src, const float* dst, uot_s
     sa.tile_rows = J.ty;
     sa.partial = h->d_partial;
     HIPCHK(launch_setup(aux_grid(h, sa.ntiles), sa, h->stream));
-    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, 0u, h->d_sums, h->stream));
+    HIPCHK(launch_pair_reduce(h->d_pairs, 1, h->d_partial, kMaxSlotsSetup, h->d_sums, h->stream));
     HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     s = check_setup_sums(h, J, false);

@@ -37,7 +37,10 @@ enum CheckSlot {
 // Partial-sum slots written by the setup kernel.
 enum SetupSlot {
   U_NONFIN_IN = 0, U_NEG = 1, U_NONFIN_ST = 2, U_SUMS = 3, U_SUMD = 4, U_SQS = 5, U_SQD = 6,
+  U_MAXIN = 7,  // max |pixel| over src and dst (max-reduced): the image scale of the default steps
 };
+
+inline constexpr uint32_t kMaxSlotsSetup = 1u << U_MAXIN;
 
 inline constexpr uint32_t kMaxSlotsCheck = (1u << S_MAXG) | (1u << S_MAXA);
 

@@ -28,6 +28,7 @@ __global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
       acc[U_SUMD] += d;
       acc[U_SQS] += (double)s * s;
       acc[U_SQD] += (double)d * d;
+      acc[U_MAXIN] = fmax(acc[U_MAXIN], (double)fmaxf(fabsf(s), fabsf(d)));
       if (A.mode == 0 && A.write_c) A.c[o] = d - s;
       const bool zx = (A.bc == 0 && gx == nx - 1), zy = (A.bc == 0 && gy == ny - 1);
       if (!A.warm) {
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(BLOCK) void setup_kernel(SetupArgs A) {
         }
       }
     }
-    block_reduce_store(acc, 0u, A.partial + (long)t * NS);
+    block_reduce_store(acc, kMaxSlotsSetup, A.partial + (long)t * NS);
   }
 }
 

@@ -47,7 +47,7 @@ class Params:
     tile_rows: int = 0
     pitch: int = 0
     norm: int = 0          # NORM_ISO (the paper's l2,1) or NORM_ANISO (l1,1)
-    reserved: int = 0
+    max_groups: int = 0    # cap on the persistent grid (0 = fill the device)
 
     def to_c(self):
         return _lib.Params(**{f.name: (int(getattr(self, f.name)) if f.type in ("int", "bool")

@@ -63,7 +63,7 @@ def test_iterates_match_oracle(dev, shape, prox_iters, variant):
     ratio, tau = 0.0, None
     if variant == "ratio":
         ratio = 0.05
-        tt = ora.df_problem(s0, np.zeros_like(s0), kw["kappa"], kw["mu"], kw["rho"]).default_steps()[0]
+        tt = ora.df_problem(s0, np.zeros_like(s0), kw["kappa"], kw["mu"], kw["rho"]).unit_steps()[0]
         tau = (tt * np.sqrt(ratio), tt / np.sqrt(ratio))
     iters = 37
     solver = A.UotDf(shape[1], shape[0], prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0,

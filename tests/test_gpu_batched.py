@@ -208,21 +208,24 @@ def test_vectorised_kernel_on_odd_offsets_with_nan_gaps(dev, ty):
         assert bool(torch.isnan(st[k][gaps]).all()), k
 
 
+@pytest.mark.parametrize("max_groups", [0, 8])
 @pytest.mark.parametrize("mode,tol", [(DIST, 2e-4), (PROX, 1e-7)])
-def test_fused_check_agrees_with_the_separate_check(dev, mode, tol):
+def test_fused_check_agrees_with_the_separate_check(dev, mode, tol, max_groups):
     """A blocked shape evaluates each window's check inside the window's
     last launch, accumulating over a workgroup's run of tiles of one pair;
     a single-step shape runs the separate check kernel per tile.  On a
     ragged batch (runs of tiles that change pair, pairs smaller than a tile,
     one pair of many tiles) both take the same decisions at the same
     checks: equal iteration counts and statuses, the recorded residuals
-    equal up to the order of the FP64 sums, and bitwise equal iterates."""
+    equal up to the order of the FP64 sums, and bitwise equal iterates.
+    With max_groups = 8 every workgroup walks long runs of tiles (the
+    persistent walk and the per-run accumulation of the fused check)."""
     shapes = SHAPES + [(300, 257)]
     pairs, src, dst, nx, ny, offs = batch_of(shapes, dev, seed0=40)
     out = []
     for ty in (4016, 16):
         s = G.Solver(G.Params(mode=mode, mu=1.1, rho=0.8, max_iter=600, check_every=20, tol=tol, tile_rows=ty,
-                              flags=G.UOT_RECORD_HISTORY))
+                              flags=G.UOT_RECORD_HISTORY, max_groups=max_groups))
         st, reps = s.solve_batched(src, dst, nx, ny, offs)
         torch.cuda.synchronize()
         hist = [s.history(b) for b in range(len(shapes))]
@@ -236,3 +239,51 @@ def test_fused_check_agrees_with_the_separate_check(dev, mode, tol):
         np.testing.assert_allclose(ha[b][1], hb[b][1], rtol=1e-9, atol=0)
     for k in planes(mode, False):
         assert torch.equal(sa[k], sb[k]), k
+
+
+@pytest.mark.parametrize("ty", [4016, 4004, 116, 8])
+def test_capped_grid_walks_the_tile_list(dev, ty):
+    """max_groups = 8 gives each workgroup tens of tiles of several pairs
+    (the persistent XCD-chunked walk, and for the blocked shape the fused
+    check accumulated over runs of tiles of one pair).  Against the
+    uncapped grid: the same decisions at the same checks and bitwise equal
+    iterates.  Against the FP64 oracle, pair by pair on non-normalised
+    inputs with a tolerance that stops pairs at different checks: the
+    iterate after the GPU's iteration count matches element by element, and
+    the oracle stops at the same check (or a neighbouring one, where the
+    residual crosses tol within FP32 rounding)."""
+    shapes = [(40, 70), (9, 130), (64, 64), (3, 5), (100, 33), (70, 70), (1, 90), (50, 1)]
+    pairs, src, dst, nx, ny, offs = batch_of(shapes, dev, seed0=70, order=[3, 0, 5, 1, 7, 2, 6, 4], gap=5)
+    tol, ce = 2e-4, 20
+    runs = []
+    for cap in (0, 8):
+        s = G.Solver(G.Params(mode=DIST, mu=1.1, max_iter=3000, check_every=ce, tol=tol, tile_rows=ty,
+                              max_groups=cap))
+        st, reps = s.solve_batched(src, dst, nx, ny, offs)
+        torch.cuda.synchronize()
+        runs.append((st, reps))
+    (s0, r0), (s8, r8) = runs
+    rows = ty % 1000 if ty >= 1000 else ty % 100
+    tiles = sum(-(-h // rows) * -(-w // 64) for h, w in shapes)
+    assert tiles > 8 * 4, "every workgroup should walk several tiles"
+    for b in range(len(shapes)):
+        assert r0[b]["iters"] == r8[b]["iters"] and r0[b]["status"] == r8[b]["status"], b
+        assert abs(r0[b]["rel_res"] - r8[b]["rel_res"]) <= 1e-9 * r0[b]["rel_res"], b
+    for k in planes(DIST, False):
+        assert torch.equal(s0[k], s8[k]), k
+    assert len({r["iters"] for r in r8}) > 1, "the pairs should stop at different checks"
+    for b, (p, q) in enumerate(pairs):
+        if p.size > 5000:
+            continue  # the oracle runs of the small pairs suffice
+        prob = ora.Problem(p.astype(np.float64), q.astype(np.float64), mu=1.1)
+        t1, t2 = prob.default_steps()
+        ref, _ = ora.solve(prob, tau1=np.float32(t1), tau2=np.float32(t2), max_iter=r8[b]["iters"], tol=0)
+        o = offs[b]
+        for k in planes(DIST, False):
+            g = s8[k][o:o + p.size].double().cpu().numpy().reshape(p.shape)
+            want = getattr(ref, k)
+            assert np.abs(g - want).max() <= 1e-4 * max(1.0, np.abs(want).max()), (b, k)
+        if r8[b]["status_name"] == "CONVERGED":
+            _, orep = ora.solve(prob, tau1=np.float32(t1), tau2=np.float32(t2), max_iter=3000, tol=tol,
+                                check_every=ce)
+            assert abs(orep.iters - r8[b]["iters"]) <= ce, b

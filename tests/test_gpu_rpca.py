@@ -64,7 +64,7 @@ def test_iterates_match_oracle(dev, T, shape, prox_iters, variant):
     if variant == "ratio":
         ratio = 0.02
         zf = np.zeros(shape)
-        tt = ora.rpca_problem(zf, zf, kw["kappa"], kw["mu"], kw["rho"]).default_steps()[0]
+        tt = ora.rpca_problem(zf, zf, kw["kappa"], kw["mu"], kw["rho"]).unit_steps()[0]
         tau = (tt * np.sqrt(ratio), tt / np.sqrt(ratio))
     iters = 23
     solver = A.Rpca(shape[1], shape[0], T, prox_iters=prox_iters, max_iter=iters, check_every=5, eps=0.0,

@@ -125,7 +125,7 @@ def test_printed_one_block_s_step_ignores_the_transport_term():
         s = np.maximum(st.x + st.a, 0.0)  # the printed s-step
         x = (y + rho * (s - st.a)) / (1.0 + rho)
         prob = admm.df_problem(s0, s - st.b, kappa, mu, rho)
-        t1, t2 = prob.default_steps()
+        t1, t2 = prob.unit_steps()
         pst = st.prox
         for _ in range(10):
             pst = uot.iterate(prob, pst, t1, t2)
