@@ -110,6 +110,16 @@ int shape_single(int code) {
   const int rows = code % 1000;
   return rows % 16 == 0 ? 100 + rows : rows;
 }
+// Steps of the check variant of a blocked shape (the window's last launch,
+// halo one more than that): 4 for the 4- and 8-step shapes of 4 to 16
+// rows, 2 for 2016 and the 32-row shapes (fewer registers).
+int shape_chk_steps(int code) {
+  switch (code) {
+    case 4004: case 4008: case 4016: case 8016: return 4;
+    case 2016: case 4032: case 8032: return 2;
+  }
+  return 1;
+}
 bool shape_known(int code) {
   switch (code) {
     case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
@@ -137,6 +147,21 @@ std::vector<int> step_schedule(int n, int T, bool last_single, bool even) {
   }
   for (int i = 0; i < k; ++i) v.push_back(R / k + (i < R % k ? 1 : 0));
   if (last_single) v.push_back(1);
+  return v;
+}
+
+// A check window of n iterations on a blocked shape: launches of up to T
+// iterations, the last one (the check variant) of up to F, spread evenly.
+// The number of launches may be odd: the window then ends in the other
+// copy of the state.
+std::vector<int> fused_schedule(int n, int T, int F) {
+  std::vector<int> v;
+  if (n <= 0) return v;
+  const int f = std::min(F, n);
+  const int R = n - f;
+  const int k = (R + T - 1) / T;
+  for (int i = 0; i < k; ++i) v.push_back(R / k + (i < R % k ? 1 : 0));
+  v.push_back(f);
   return v;
 }
 
@@ -219,22 +244,24 @@ struct uot_handle {
   const void* dr_key[4] = {};
   double* h_pp = nullptr;       // pinned
 
-  // cached graph of one check window
-  hipGraphExec_t gexec = nullptr;    // one check window
-  std::vector<unsigned char> gkey;
-  hipGraphExec_t gexec_n = nullptr;  // a burst of several windows between host polls
-  std::vector<unsigned char> gkey_n;
+  // cached graphs: [burst][parity], burst 0 one check window, 1 a burst of
+  // several windows between host polls; parity 1 starts from the shadow copy
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  std::vector<unsigned char> gkey[2][2];
+  int32_t* d_mask = nullptr;    // per-pair flags of a masked copy
+  size_t cap_mask = 0;
 
   ~uot_handle() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (gexec_n) (void)hipGraphExecDestroy(gexec_n);
+    for (auto& row : gexec)
+      for (auto& g : row)
+        if (g) (void)hipGraphExecDestroy(g);
     if (drexec) (void)hipGraphExecDestroy(drexec);
     if (drbuf) (void)hipFree(drbuf);
     if (d_drp) (void)hipFree(d_drp);
     if (h_drp) (void)hipHostFree(h_drp);
     for (auto& p : B)
       if (p) (void)hipFree(p);
-    void* dev[] = {cplane, d_tiles, d_live, d_nlive, d_partial, d_pairs, d_sums, d_i32, d_f64, d_invs};
+    void* dev[] = {cplane, d_tiles, d_live, d_nlive, d_partial, d_pairs, d_sums, d_i32, d_f64, d_invs, d_mask};
     for (void* p : dev)
       if (p) (void)hipFree(p);
     if (h_sums) (void)hipHostFree(h_sums);
@@ -511,6 +538,7 @@ uot_status ensure_workspace(uot_handle* h, const Job& J) {
   HIPCHK(grow(&h->d_i32, &h->cap_i32, (size_t)J.B * 3 + 1));
   HIPCHK(grow(&h->d_f64, &h->cap_f64, (size_t)J.B * 3));
   HIPCHK(grow(&h->d_invs, &h->cap_invs, (size_t)J.B));
+  HIPCHK(grow(&h->d_mask, &h->cap_mask, (size_t)J.B));
   if (h->cap_hsums < (size_t)J.B * NS) {
     if (h->h_sums) (void)hipHostFree(h->h_sums);
     h->h_sums = nullptr;
@@ -705,17 +733,23 @@ hipError_t launch_steps(uot_handle* h, int resid, int shape, int steps, int grid
   return launch_iter(p.mode, resid, bcn_of(p), shape, grid_multi, a, h->stream);
 }
 
-uot_status enqueue_window(Launch& L, int W, bool check) {
+// Launches of one window of W iterations starting from copy `parity` (0:
+// the caller's planes, 1: the shadow).  With a check on a blocked shape the
+// window's last launch is the check variant (fused_schedule; the window may
+// end in the other copy); otherwise its last launch runs one iteration and
+// the window has an even number of launches (step_schedule), followed by
+// the separate check kernel when there is a check.
+uot_status enqueue_window(Launch& L, int W, bool check, int parity) {
   uot_handle* h = L.h;
   const uot_params& p = h->prm;
-  const std::vector<int> sched = step_schedule(W, shape_steps(L.J->shape), true, true);
-  // with a blocked shape, the window's last (single) step also evaluates the
-  // check, from the two iterates it holds in LDS and registers
-  const bool fused = check && shape_steps(L.J->shape) > 1;
+  const int T = shape_steps(L.J->shape);
+  const bool fused = check && T > 1;
+  const std::vector<int> sched =
+      fused ? fused_schedule(W, T, shape_chk_steps(L.J->shape)) : step_schedule(W, T, true, true);
   for (size_t i = 0; i < sched.size(); ++i) {
-    IterArgs a = (i & 1) ? L.bwd : L.fwd;
+    IterArgs a = ((i + parity) & 1) ? L.bwd : L.fwd;
     if (fused && i + 1 == sched.size()) {
-      a.steps = 1;
+      a.steps = sched[i];
       a.chk = h->d_partial;
       HIPCHK(launch_iter_chk(p.mode, L.resid, bcn_of(p), L.J->shape, L.grid_chk, a, h->stream));
     } else {
@@ -729,10 +763,18 @@ uot_status enqueue_window(Launch& L, int W, bool check) {
   return UOT_OK;
 }
 
-uot_status get_graph(Launch& L, int W, bool check, int reps, hipGraphExec_t* out) {
+// Launches per window (its parity decides which copy a window ends in).
+int window_launches(const Launch& L, int W, bool check) {
+  const int T = shape_steps(L.J->shape);
+  if (check && T > 1) return (int)fused_schedule(W, T, shape_chk_steps(L.J->shape)).size();
+  return (int)step_schedule(W, T, true, true).size();
+}
+
+uot_status get_graph(Launch& L, int W, bool check, int reps, int parity, hipGraphExec_t* out) {
   uot_handle* h = L.h;
-  hipGraphExec_t& slot = reps == 1 ? h->gexec : h->gexec_n;
-  std::vector<unsigned char>& skey = reps == 1 ? h->gkey : h->gkey_n;
+  const int per = window_launches(L, W, check);
+  hipGraphExec_t& slot = h->gexec[reps == 1 ? 0 : 1][parity];
+  std::vector<unsigned char>& skey = h->gkey[reps == 1 ? 0 : 1][parity];
   std::vector<unsigned char> key;
   auto put = [&](const void* d, size_t n) {
     const unsigned char* c = (const unsigned char*)d;
@@ -743,6 +785,7 @@ uot_status get_graph(Launch& L, int W, bool check, int reps, hipGraphExec_t* out
   put(&L.dec, sizeof(L.dec));
   put(&W, sizeof(W));
   put(&reps, sizeof(reps));
+  put(&parity, sizeof(parity));
   int c = check;
   put(&c, sizeof(c));
   put(&L.grid_iter, sizeof(int));
@@ -760,7 +803,11 @@ uot_status get_graph(Launch& L, int W, bool check, int reps, hipGraphExec_t* out
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   uot_status st = UOT_OK;
-  for (int r = 0; r < reps && st == UOT_OK; ++r) st = enqueue_window(L, W, check);
+  int par = parity;
+  for (int r = 0; r < reps && st == UOT_OK; ++r) {
+    st = enqueue_window(L, W, check, par);
+    par ^= per & 1;
+  }
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (st != UOT_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -1002,24 +1049,34 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   const bool adaptive = check && (p.flags & UOT_ADAPTIVE_STEPS);
   L.dec = DecideArgs{h->d_pairs, h->d_sums, d_xn, d_active, d_iters, d_status, d_rel, B, W,
                      p.max_iter, check ? 1 : 0, 0, p.mode, n_identity(p.mode, p.balanced), p.tol,
-                     adaptive ? 1 : 0, d_alpha, p.mu, p.rho};
+                     adaptive ? 1 : 0, d_alpha, p.mu, p.rho, 0, 0};
 
   int n_active = 0;
   for (int b = 0; b < B; ++b) n_active += h_active[b];
-  const int nwin = p.max_iter / W;
-  const int tail = p.max_iter % W;
+  // Windows of W iterations.  Without a check the last window of the solve is
+  // the tail, so the solve always ends in a single-iteration launch (the final
+  // evaluation compares the last two iterates).
+  const int nwin = check ? p.max_iter / W : std::max(0, p.max_iter - 1) / W;
+  const int tail = p.max_iter - nwin * W;
   const bool use_graph = !(p.flags & UOT_NO_GRAPH);
+  const int per = window_launches(L, W, check);  // launches per window
   // windows: the device decides convergence; the host polls every few windows
   // (every window when the history is recorded).  A full burst of windows
-  // between polls replays one captured graph; a shorter last burst replays
-  // the one-window graph.
-  const int poll = record ? 1 : std::min(32, std::max(1, 256 / W));
-  hipGraphExec_t gx = nullptr, gxn = nullptr;
+  // between polls replays one captured graph (an even number of windows when
+  // a window flips the copy, so a burst starts and ends in the same copy); a
+  // shorter last burst replays the one-window graphs.
+  int poll = record ? 1 : std::min(32, std::max(1, 256 / W));
+  if ((per & 1) && poll > 1) poll += poll & 1;
+  hipGraphExec_t gx[2] = {nullptr, nullptr}, gxn = nullptr;
   if (n_active > 0 && nwin > 0 && use_graph) {
-    s = get_graph(L, W, check, 1, &gx);
+    s = get_graph(L, W, check, 1, 0, &gx[0]);
     if (s != UOT_OK) return s;
+    if (per & 1) {
+      s = get_graph(L, W, check, 1, 1, &gx[1]);
+      if (s != UOT_OK) return s;
+    }
     if (poll > 1 && nwin >= poll) {
-      s = get_graph(L, W, check, poll, &gxn);
+      s = get_graph(L, W, check, poll, 0, &gxn);
       if (s != UOT_OK) return s;
     }
   }
@@ -1029,17 +1086,21 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   std::vector<int32_t> hprev_active(record ? B : 0);
   int done_iters = 0;  // iterations of pairs that never stop early (fixed mode)
   int w = 0;
+  int par = 0;  // copy holding the iterate of the pairs still running
   while (w < nwin && n_active > 0) {
     const int burst = std::min(poll, nwin - w);
     if (gxn && burst == poll) {
       HIPCHK(hipGraphLaunch(gxn, h->stream));
+      par ^= (burst * per) & 1;
     } else {
       for (int i = 0; i < burst; ++i) {
-        if (gx) HIPCHK(hipGraphLaunch(gx, h->stream));
-        else {
-          s = enqueue_window(L, W, check);
+        if (gx[par]) {
+          HIPCHK(hipGraphLaunch(gx[par], h->stream));
+        } else {
+          s = enqueue_window(L, W, check, par);
           if (s != UOT_OK) return s;
         }
+        par ^= per & 1;
       }
     }
     w += burst;
@@ -1072,18 +1133,39 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     // fixed iteration count: every active pair ran the windows
     HIPCHK(hipStreamSynchronize(h->stream));
   }
-  // tail iterations for pairs still running
+  // Pairs that stopped at a check after an odd number of copy flips hold
+  // their iterate in the shadow copy: copy it back.  A pair that stopped at
+  // the check of window k (iterations k W) has seen k windows.
+  if (check && (per & 1)) {
+    std::vector<int32_t> back(B, 0);
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      const int wins = W > 0 ? h->h_i32[B + b] / W : 0;
+      back[b] = !h_active[b] && h->h_i32[2 * B + b] != UOT_MAX_ITER && ((wins * per) & 1);
+      any = any || back[b];
+    }
+    if (any) {
+      HIPCHK(hipMemcpyAsync(h->d_mask, back.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(launch_copy_active(A, Bp, h->d_pairs, h->d_tiles, (int)J.tiles.size(), J.ty, h->d_mask, L.grid_aux,
+                                h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+  }
+  // tail iterations for pairs still running, from the copy that holds them;
+  // the tail ends in a single-iteration launch
   const bool run_tail = n_active > 0 && tail > 0;
   const std::vector<int> tsched = step_schedule(tail, shape_steps(J.shape), true, false);
   if (run_tail) {
     for (size_t i = 0; i < tsched.size(); ++i)
-      HIPCHK(launch_steps(h, resid, J.shape, tsched[i], L.grid_iter, L.grid_single, (i & 1) ? L.bwd : L.fwd));
+      HIPCHK(launch_steps(h, resid, J.shape, tsched[i], L.grid_iter, L.grid_single,
+                          ((i + par) & 1) ? L.bwd : L.fwd));
+    par ^= tsched.size() & 1;
   }
-  const bool odd = run_tail && (tsched.size() & 1);
+  const bool in_shadow = n_active > 0 && par == 1;
   // final evaluation of every pair, then the final decision
   CheckArgs fin = L.chk;
   if (p.max_iter == 0) fin.B = A;  // no iteration ran: no previous iterate
-  fin.swap_active = odd ? 1 : 0;
+  fin.swap_active = in_shadow ? 1 : 0;
   fin.all_pairs = 1;
   HIPCHK(launch_check(p.mode, resid, bcn_of(p), L.grid_aux, fin, h->stream));
   DecideArgs fd = L.dec;
@@ -1091,14 +1173,17 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   fd.check = 1;
   fd.tol = check ? p.tol : 0.0;
   fd.final_pass = 1;
-  if (odd) {
+  // no iteration since the last window's check: its rel_res is the current
+  // iterate's (the copy behind may hold an older iterate than the previous)
+  fd.keep_rel = (check && !run_tail && nwin > 0) ? 1 : 0;
+  if (in_shadow) {
     // pairs still active hold their iterate in the shadow copy: copy it back
     // before the decision clears their flag
     HIPCHK(launch_copy_active(A, Bp, h->d_pairs, h->d_tiles, (int)J.tiles.size(), J.ty, d_active, L.grid_aux,
                               h->stream));
   }
-  // Pairs that stopped in an earlier window keep their recorded status; the
-  // final decision re-evaluates only still-active pairs.
+  // Pairs that stopped in an earlier window keep their recorded status and
+  // rel_res; the final decision re-evaluates only still-active pairs.
   HIPCHK(launch_reduce_decide(fd, h->d_partial, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_sums, h->d_sums, (size_t)B * NS * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(h->h_i32, h->d_i32, (size_t)B * 3 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -1128,7 +1213,9 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     r.status = h->h_i32[2 * B + b];
     r.seconds = secs;
     r.tile_rows = J.shape;
-    if (r.status == UOT_CONVERGED && relres[b] == 0.0) r.rel_res = 0.0;
+    // rel_res as the stopping rule last evaluated it (at the check where the
+    // pair stopped, or at its last iterate)
+    if (std::isfinite(relres[b])) r.rel_res = relres[b];
     // the final evaluation, unless the pair stopped at an earlier check
     if (record && (h->hist[b].empty() || h->hist[b].back().first != r.iters))
       h->hist[b].emplace_back(r.iters, r.rel_res);

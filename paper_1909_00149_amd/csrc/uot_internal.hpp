@@ -129,6 +129,8 @@ struct DecideArgs {
   int32_t adaptive;   // residual balancing of tau1/tau2
   double* alpha;      // per-pair adaptation factor
   double mu, rho;
+  int32_t keep_rel;   // final pass right after a check: keep that check's rel_res
+  int32_t pad_;
 };
 
 struct DualArgs {

@@ -22,6 +22,7 @@
 #include "uot_internal.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace uot {
 
@@ -558,14 +559,60 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NS], uint32_t m
   block_reduce_lds(acc, max_mask, dst, buf, fin);
 }
 
-template <int MODE, int RES, int BC, int TH, int T, bool CHK, bool KEEP = false>
+// Cell idx (0 <= idx < NC * BLOCK) of a workgroup's region, in region
+// coordinates (rx, ry), region cell (0, 0) being grid pixel (x0 - H, y0 - H):
+// the owned 64 x TH tile first, row by row, so that each thread's first
+// TH / 4 cells are owned and every wave reads and writes whole tile rows;
+// then the ring around the tile: the H rows below and the H rows above it
+// (full region width), then the H columns left and right of its rows.
+// Slots past the region come back with ry = RH and rx numbering them.
+template <int TH, int H>
+__device__ __forceinline__ void region_cell(int idx, int& rx, int& ry) {
+  constexpr int RW = TX + 2 * H;
+  constexpr int OWN = TX * TH, BAND = H * RW, SIDE = H * TH;
+  if (idx < OWN) {
+    ry = H + idx / TX;
+    rx = H + idx % TX;
+    return;
+  }
+  int j = idx - OWN;
+  if (j < 2 * BAND) {
+    const int b = j >= BAND;  // 0 below the tile, 1 above
+    j -= b * BAND;
+    ry = j / RW + b * (H + TH);
+    rx = j % RW;
+    return;
+  }
+  j -= 2 * BAND;
+  if (j < 2 * SIDE) {
+    const int b = j >= SIDE;  // 0 left of the tile, 1 right
+    j -= b * SIDE;
+    ry = H + j / H;
+    rx = j % H + b * (H + TX);
+    return;
+  }
+  ry = TH + 2 * H;
+  rx = j - 2 * SIDE;
+}
+
+// H: the halo, so up to H steps per launch keep the owned tile exact.  CHK:
+// the launch also evaluates the convergence check of the iterate pair of its
+// last step (steps <= H - 1, so that the new iterate is exact one cell
+// beyond the tile, where the check reads its neighbours); the last step's
+// input values the check needs are kept in registers for the owned cells.
+template <int MODE, int RES, int BC, int TH, int H, bool CHK>
 __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
-  constexpr int RW = TX + 2 * T, RH = TH + 2 * T, NCELL = RW * RH;
+  constexpr int RW = TX + 2 * H, RH = TH + 2 * H, NCELL = RW * RH;
   constexpr int NC = (NCELL + BLOCK - 1) / BLOCK;
-  // LDS rows of RW cells plus a zero border; the rows past the region hold
-  // the cells of the last pass that fall outside it (always written zero)
-  constexpr int LW = RW + 2, LH = (NC * BLOCK + RW - 1) / RW + 2;
-  constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4, F_OWN = 8;  // per-cell flags
+  constexpr int NOWN = TX * TH / BLOCK;  // owned cells per thread: the first NOWN
+  static_assert(TX * TH % BLOCK == 0, "whole tile rows per thread");
+  static_assert(!CHK || H >= 2, "the check needs one exact cell beyond the tile");
+  // LDS rows of RW cells plus a zero border; the slots past the region use
+  // spare rows above the top border (always written zero, read only by
+  // themselves)
+  constexpr int PAD = NC * BLOCK - NCELL;
+  constexpr int LW = RW + 2, LH = RH + 3 + (PAD + RW - 1) / RW;
+  constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4;  // per-cell flags
   // a, Mx, My planes of the region; CHK: also the check's reduction buffer,
   // used only between tiles (after the write of one, before the staging of
   // the next)
@@ -580,9 +627,19 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   const int steps = A.steps;
   long t, stride, tend;
   xcd_chunk(*A.ntiles, t, stride, tend);
+  // the LDS index of each cell does not depend on the tile
+  int l_[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    int rx, ry;
+    region_cell<TH, H>(tid + k * BLOCK, rx, ry);
+    l_[k] = ry < RH ? (ry + 1) * LW + rx + 1 : (RH + 2 + rx / RW) * LW + rx % RW + 1;
+  }
   // CHK: per-thread check sums over the block's run of tiles of one pair,
   // reduced once per run into the row of its first tile (the run's other
-  // rows are zeroed, so the per-pair sum of the rows is unchanged)
+  // rows are zeroed, so the per-pair sum of the rows is unchanged).  Only
+  // the terms of the stopping rule are accumulated: the report's objective
+  // and bounds come from the final evaluation of a solve.
   double acc[NS];
   int run_pair = -1, run_row = 0;
   if (CHK) {
@@ -612,25 +669,22 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const long off = P.off;
     const float tau1 = P.tau1, tau2 = P.tau2, t2 = tau1 * tau1;
-    const int bx = tl.x0 - T, by = tl.y0 - T;  // grid position of region cell (0, 0)
-    int l_[NC], f_[NC];                        // LDS index and flags of each cell
+    const int bx = tl.x0 - H, by = tl.y0 - H;  // grid position of region cell (0, 0)
+    int f_[NC];                                // flags of each cell
     float r_[NC], c0_[NC], c1_[NC], x0_[NC], x1_[NC], kp_[NC];
-    // CHK with KEEP: the last step's input values the check needs, kept in
-    // registers (otherwise read back from the input planes)
-    float ka_[NC], kr_[NC], ku_[NC], kmx_[NC], kmy_[NC], kro_[NC], kx0_[NC], kx1_[NC];
+    // CHK: the last step's input values of the owned cells
+    float ka_[NOWN], kr_[NOWN], ku_[NOWN], kmx_[NOWN], kmy_[NOWN], kro_[NOWN], kx0_[NOWN], kx1_[NOWN];
 
     __syncthreads();  // LDS of the previous tile is no longer read
     // ---- stage the region ----
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int idx = tid + k * BLOCK;
-      const int ry = idx / RW, rx = idx - ry * RW;
+      int rx, ry;
+      region_cell<TH, H>(tid + k * BLOCK, rx, ry);
       const int gx = bx + rx, gy = by + ry;
       const bool in = ry < RH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-      const int l = (ry + 1) * LW + rx + 1;
-      l_[k] = l;
-      f_[k] = (in ? F_IN : 0) | ((BC & 1) == 0 && gx == nx - 1 ? F_ZX : 0) | ((BC & 1) == 0 && gy == ny - 1 ? F_ZY : 0) |
-              (rx >= T && rx < T + TX && ry >= T && ry < T + TH ? F_OWN : 0);
+      const int l = l_[k];
+      f_[k] = (in ? F_IN : 0) | ((BC & 1) == 0 && gx == nx - 1 ? F_ZX : 0) | ((BC & 1) == 0 && gy == ny - 1 ? F_ZY : 0);
       float a = 0.f, mx = 0.f, my = 0.f;
       r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
       if (in) {
@@ -668,7 +722,10 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     }
     __syncthreads();  // the flux phase overwrites M, which the neighbours read above
 
-    for (int st = 0; st < steps; ++st) {
+    // one step over the region; KEEPSTEP: the step whose input iterate the
+    // check compares with (the last), which keeps the owned cells' inputs
+    auto one_step = [&](auto keep_tag) {
+      constexpr bool KEEPSTEP = decltype(keep_tag)::value;
       // ---- new flux: read every cell's inputs, then compute and write ----
       float ac_[NC], ar_[NC], au_[NC], mx_[NC], my_[NC];
 #pragma unroll
@@ -679,7 +736,10 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
         au_[k] = sa[l + LW];
         mx_[k] = smx[l];
         my_[k] = smy[l];
-        if (CHK && KEEP) {
+      }
+      if (KEEPSTEP) {
+#pragma unroll
+        for (int k = 0; k < NOWN; ++k) {
           ka_[k] = ac_[k];
           kr_[k] = ar_[k];
           ku_[k] = au_[k];
@@ -746,37 +806,37 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
         x1_[k] = x1n;
       }
       __syncthreads();
+    };
+    if (CHK) {
+      // the host launches the check variant with 1 <= steps <= H - 1
+      for (int st = 0; st + 1 < steps; ++st) one_step(std::false_type{});
+      one_step(std::true_type{});
+    } else {
+      for (int st = 0; st < steps; ++st) one_step(std::false_type{});
     }
 
     if (CHK) {
-      // the check of the iterate pair (input, output) of this one-step
-      // launch, per owned cell with the expressions of check_kernel: the
-      // input iterate is still in the input planes (read back through the
-      // L2), the output one is in LDS, exact one cell beyond the tile (the
-      // halo is two), where the check reads the right and upper neighbours'
-      // a and the left and lower neighbours' flux
+      // the stopping rule's terms for the iterate pair of the last step, per
+      // owned cell, with the expressions of check_kernel: the input values
+      // are in registers, the output ones in LDS, exact one cell beyond the
+      // tile, where the check reads the right and upper neighbours' a and
+      // the left and lower neighbours' flux
       constexpr float nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
-      static_assert(T >= 2, "the check needs one exact cell beyond the tile");
       const float it1 = 1.f / tau1;
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        if ((f_[k] & (F_IN | F_OWN)) != (F_IN | F_OWN)) continue;
+      for (int k = 0; k < NOWN; ++k) {
+        if (!(f_[k] & F_IN)) continue;
         const int l = l_[k];
-        const int idx = tid + k * BLOCK;
-        const int ry = idx / RW, rx = idx - ry * RW;
-        const int gx = bx + rx, gy = by + ry;
-        const long o = off + (long)gy * pitch + gx;
-        const bool hasR = gx + 1 < nx, hasU = gy + 1 < ny;
-        const float a = sa[l], ap = KEEP ? ka_[k] : A.in.a[o];
-        const float aR = sa[l + 1], apR = KEEP ? kr_[k] : (hasR ? A.in.a[o + 1] : 0.f);
-        const float aU = sa[l + LW], apU = KEEP ? ku_[k] : (hasU ? A.in.a[o + pitch] : 0.f);
+        const float a = sa[l], ap = ka_[k];
+        const float aR = sa[l + 1], apR = kr_[k];
+        const float aU = sa[l + LW], apU = ku_[k];
         float gxx = a - aR, gyy = a - aU;
         float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
         const bool zx = (BC & 1) == 0 && (f_[k] & F_ZX), zy = (BC & 1) == 0 && (f_[k] & F_ZY);
         if (zx) gxx = dgx = 0.f;
         if (zy) gyy = dgy = 0.f;
         const float mx = zx ? 0.f : smx[l], my = zy ? 0.f : smy[l];
-        const float mxp = zx ? 0.f : (KEEP ? kmx_[k] : A.in.Mx[o]), myp = zy ? 0.f : (KEEP ? kmy_[k] : A.in.My[o]);
+        const float mxp = zx ? 0.f : kmx_[k], myp = zy ? 0.f : kmy_[k];
         const float mxl = smx[l - 1];
         const float myd = smy[l - LW];
         const float dm = (mx - mxl) + (my - myd);
@@ -794,7 +854,7 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
         float r = 0.f, rp = 0.f;
         if (RES != R_BAL) {
           r = r_[k];
-          rp = KEEP ? kro_[k] : A.in.r[o];
+          rp = kro_[k];
         }
         const float kz = e - r;
         const float da = ap - a;
@@ -805,11 +865,11 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
           st2 += sr * sr;
         }
         if (MODE == 1) {
-          const float s0 = ((KEEP ? kx0_[k] : A.in.x0[o]) - x0) * it1 + da;
+          const float s0 = (kx0_[k] - x0) * it1 + da;
           st2 += s0 * s0;
         }
         if (MODE != 0) {
-          const float s1 = ((KEEP ? kx1_[k] : A.in.x1[o]) - x1) * it1 - da;
+          const float s1 = (kx1_[k] - x1) * it1 - da;
           st2 += s1 * s1;
         }
         const float g2 = gxx * gxx + gyy * gyy;
@@ -818,42 +878,19 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
         acc[S_KA2] += g2 + nid * a * a;
         acc[S_X0SQ] += x0 * x0;
         acc[S_X1SQ] += x1 * x1;
-        acc[S_MNORM] += (BC & 2) ? fabsf(mx) + fabsf(my) : sqrtf(mx * mx + my * my);
-        if (RES == R_P1) {
-          acc[S_RPEN] += fabsf(r);
-          acc[S_EPEN] += fabsf(e);
-        } else if (RES == R_P2) {
-          acc[S_RPEN] += r * r;
-          acc[S_EPEN] += e * e;
-        }
-        if (MODE == 0) acc[S_LIN] += a * c0_[k];
-        if (MODE == 2) acc[S_LIN] -= a * c0_[k];
-        if (MODE == 1) {
-          const float d0 = x0 - c0_[k], d1 = x1 - c1_[k];
-          acc[S_QUAD] += d0 * d0 + d1 * d1;
-        }
-        if (MODE == 2) {
-          const float d1 = x1 - c1_[k];
-          acc[S_QUAD] += d1 * d1;
-        }
-        acc[S_MAXG] = fmax(acc[S_MAXG], (double)((BC & 2) ? fmaxf(fabsf(gxx), fabsf(gyy)) : sqrtf(g2)));
-        acc[S_MAXA] = fmax(acc[S_MAXA], (double)fabsf(a));
         const bool fin = isfinite(a) && isfinite(mx) && isfinite(my) && isfinite(r) && isfinite(x0) &&
                          isfinite(x1);
         acc[S_NONFIN] += fin ? 0.0 : 1.0;
-        acc[S_A2] += a * a;
-        acc[S_SUMA] += a;
       }
     }
 
     // ---- write the owned tile ----
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      if ((f_[k] & (F_IN | F_OWN)) != (F_IN | F_OWN)) continue;
+    for (int k = 0; k < NOWN; ++k) {
+      if (!(f_[k] & F_IN)) continue;
       const int l = l_[k];
-      const int idx = tid + k * BLOCK;
-      const int ry = idx / RW, rx = idx - ry * RW;
-      const long o = off + (long)(by + ry) * pitch + (bx + rx);
+      const int idx = tid + k * BLOCK;  // an owned cell: row idx / 64 of the tile
+      const long o = off + (long)(tl.y0 + idx / TX) * pitch + (tl.x0 + idx % TX);
       A.out.Mx[o] = smx[l];
       A.out.My[o] = smy[l];
       A.out.a[o] = sa[l];
@@ -873,14 +910,13 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
   cp_iter_tb_body<MODE, RES, BC, TH, T, false>(A);
 }
 
-// One step (A.steps = 1) of the blocked kernel that also leaves the check's
-// partial rows of the iterate pair it reads and writes (so the window needs
-// neither the single-step launch nor the separate check).  KEEP holds the
-// input iterate in registers rather than reading it back (fewer round trips
-// to memory, more registers).
-template <int MODE, int RES, int BC, int TH, int T, bool KEEP>
+// The last launch of a check window on a blocked shape: up to H - 1 steps
+// of the blocked kernel with a halo of H that also leave the stopping rule's
+// partial rows of the iterate pair of its last step (so the window needs
+// neither a single-step launch nor a separate check).
+template <int MODE, int RES, int BC, int TH, int H>
 __global__ __launch_bounds__(BLOCK) void cp_iter_tb_check_kernel(IterArgs A) {
-  cp_iter_tb_body<MODE, RES, BC, TH, T, true, KEEP>(A);
+  cp_iter_tb_body<MODE, RES, BC, TH, H, true>(A);
 }
 
 // Residuals and certificate terms of the current iterate (K2).  Direct
@@ -1019,19 +1055,19 @@ hipError_t iter_by_ty(int ty, int grid, const IterArgs& a, hipStream_t s) {
 
 using IterKernel = void (*)(IterArgs);
 
-// The one-step check variant of a blocked shape: its tile rows with a halo
-// of two (the check reads one cell beyond the tile, exact after one step
-// everywhere but the region's outermost ring).
+// The check variant of a blocked shape: its tile rows with a halo of one
+// more than the steps it runs (the check reads one cell beyond the tile);
+// chk_steps() gives those steps per shape.
 template <int MODE, int RES, int BC>
 IterKernel chk_kernel_ty(int ty) {
   switch (ty) {
-    case 4004: return cp_iter_tb_check_kernel<MODE, RES, BC, 4, 2, true>;
-    case 4008: return cp_iter_tb_check_kernel<MODE, RES, BC, 8, 2, true>;
-    case 2016:
+    case 4004: return cp_iter_tb_check_kernel<MODE, RES, BC, 4, 5>;
+    case 4008: return cp_iter_tb_check_kernel<MODE, RES, BC, 8, 5>;
+    case 2016: return cp_iter_tb_check_kernel<MODE, RES, BC, 16, 3>;
     case 4016:
-    case 8016: return cp_iter_tb_check_kernel<MODE, RES, BC, 16, 2, false>;
+    case 8016: return cp_iter_tb_check_kernel<MODE, RES, BC, 16, 5>;
     case 4032:
-    case 8032: return cp_iter_tb_check_kernel<MODE, RES, BC, 32, 2, false>;
+    case 8032: return cp_iter_tb_check_kernel<MODE, RES, BC, 32, 3>;
   }
   return nullptr;
 }

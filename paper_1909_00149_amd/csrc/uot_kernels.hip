@@ -71,7 +71,7 @@ __device__ void decide_pair(const DecideArgs& A, int b, const double* S, const P
   const int iters = pre.iters + A.W;
   A.iters[b] = iters;
   bool done = false;
-  if (A.check) {
+  if (A.check && !A.keep_rel) {
     const double xn = A.mode == 0 ? pre.xnorm : sqrt(S[S_X0SQ]) + sqrt(S[S_X1SQ]);
     const double p = sqrt(S[S_PRES2]) / fmax(xn, 1e-30);
     const double d = sqrt(S[S_STAT2]) / fmax(sqrt(S[S_KA2]), 1e-30);
@@ -183,9 +183,9 @@ __global__ __launch_bounds__(BLOCK) void copy_active_kernel(Planes dst, Planes s
       dst.Mx[o] = src.Mx[o];
       dst.My[o] = src.My[o];
       dst.a[o] = src.a[o];
-      if (dst.r) dst.r[o] = src.r[o];
-      if (dst.x0) dst.x0[o] = src.x0[o];
-      if (dst.x1) dst.x1[o] = src.x1[o];
+      if (dst.r && src.r) dst.r[o] = src.r[o];
+      if (dst.x0 && src.x0) dst.x0[o] = src.x0[o];
+      if (dst.x1 && src.x1) dst.x1[o] = src.x1[o];
     }
   }
 }
