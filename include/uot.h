@@ -76,7 +76,8 @@ typedef enum uot_status {
   UOT_ERR_NEGATIVE = 5,   /* negative pixel in an input image                      */
   UOT_ERR_DEVICE = 6,     /* a HIP call failed or no usable GPU                    */
   UOT_ERR_OOM = 7,        /* workspace allocation failed                           */
-  UOT_ERR_MASS = 8        /* balanced mode, zero-flux boundary, unequal masses     */
+  UOT_ERR_MASS = 8,       /* balanced mode, zero-flux boundary, unequal masses     */
+  UOT_ERR_TOO_LARGE = 9   /* uot_solve_noalloc: the problem exceeds its scratch    */
 } uot_status;
 
 enum { UOT_DIST = 0, UOT_PROX = 1, UOT_PROX_FIXED = 2 };
@@ -290,6 +291,32 @@ uot_status uot_time_iterations_batched(uot_handle *h, int32_t B, const int32_t *
                                        const int32_t *pitch, const int64_t *offset, const float *src,
                                        const float *dst, uot_state *packed, int32_t n,
                                        double *ms_per_iter, int32_t *tile_rows);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): uot_solve
+ * without a handle and without any allocation.  The workspace (the shadow
+ * copy of the state, the c plane, tile lists, partial sums and per-pair
+ * records) is carved from a fixed device array of UOT_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every GPU it runs on until the process ends; no
+ * hipMalloc, hipHostMalloc, hipFree or graph instantiation is called.
+ * Arguments as uot_create + uot_solve (prm: one grid of nx x ny, hip_stream:
+ * a hipStream_t or NULL for the default stream), with these differences:
+ *   - UOT_AUTOTUNE is rejected (UOT_ERR_ARG); kernels are launched directly
+ *     (as with UOT_NO_GRAPH);
+ *   - the balanced zero-flux DIST mode reports no certified bounds (primal,
+ *     dual, rel_gap are NaN: they need the DCT Poisson solve's matrices);
+ *   - UOT_ERR_TOO_LARGE when the workspace does not fit the scratch: at most
+ *     UOT_NOALLOC_MAX_PIXELS pixels (pitch * (ny - 1) + nx) and
+ *     UOT_NOALLOC_MAX_TILES tiles of the chosen kernel shape.
+ * Every call on a GPU uses that GPU's one scratch array, which keeps the last
+ * call's contents (everything a call reads from it, it has written first):
+ * calls that overlap on one GPU (several host threads or streams) race and
+ * must be serialised by the caller.  Synchronous with respect to the host. */
+#define UOT_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define UOT_NOALLOC_MAX_PIXELS (1 << 20)
+#define UOT_NOALLOC_MAX_TILES (1 << 14)
+uot_status uot_solve_noalloc(const uot_params *prm, void *hip_stream, const float *src, const float *dst,
+                             uot_state *st, uot_report *rep);
 
 /* Releases the handle's workspace.  NULL is a no-op. */
 void uot_destroy(uot_handle *h);

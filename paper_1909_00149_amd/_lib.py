@@ -7,7 +7,8 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libuot.so")
 
 UOT_OK, UOT_ERR_ARG, UOT_ERR_SHAPE, UOT_ERR_STEP, UOT_ERR_NONFINITE = 0, 1, 2, 3, 4
-UOT_ERR_NEGATIVE, UOT_ERR_DEVICE, UOT_ERR_OOM, UOT_ERR_MASS = 5, 6, 7, 8
+UOT_ERR_NEGATIVE, UOT_ERR_DEVICE, UOT_ERR_OOM, UOT_ERR_MASS, UOT_ERR_TOO_LARGE = 5, 6, 7, 8, 9
+UOT_NOALLOC_SCRATCH_BYTES, UOT_NOALLOC_MAX_PIXELS, UOT_NOALLOC_MAX_TILES = 32 << 20, 1 << 20, 1 << 14
 STATUS_NAMES = {0: "CONVERGED", 1: "MAX_ITER", 2: "DIVERGED"}
 
 UOT_WARM_START = 0x1
@@ -142,6 +143,8 @@ SIGNATURES = {
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State)]),
+    "uot_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(State), ctypes.POINTER(Report)]),
     "uot_destroy": (None, [ctypes.c_void_p]),
     "uotdf_check_params": (ctypes.c_int, [ctypes.POINTER(DfParams)]),
     "uotdf_create": (ctypes.c_int, [ctypes.POINTER(DfParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),

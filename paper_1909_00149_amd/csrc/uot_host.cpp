@@ -183,6 +183,9 @@ hipError_t grow(T** p, size_t* cap, size_t n) {
 
 struct uot_handle {
   uot_params prm{};
+  // workspace borrowed from the no-allocation scratch: never freed, and no
+  // path that would allocate (graphs, autotuning, the Poisson certificate)
+  bool borrowed = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
@@ -252,6 +255,7 @@ struct uot_handle {
   size_t cap_mask = 0;
 
   ~uot_handle() {
+    if (borrowed) return;
     for (auto& row : gexec)
       for (auto& g : row)
         if (g) (void)hipGraphExecDestroy(g);
@@ -288,6 +292,7 @@ const char* uot_status_string(uot_status s) {
     case UOT_ERR_DEVICE: return "HIP device error";
     case UOT_ERR_OOM: return "device memory allocation failed";
     case UOT_ERR_MASS: return "balanced zero-flux problem with unequal masses";
+    case UOT_ERR_TOO_LARGE: return "problem larger than the no-allocation scratch";
   }
   return "unknown status";
 }
@@ -1199,7 +1204,7 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     if (s != UOT_OK) return s;
   }
   std::vector<double> bal(B, std::nan(""));
-  if (p.mode == UOT_DIST && resid == R_BAL && p.bc == 0) {
+  if (p.mode == UOT_DIST && resid == R_BAL && p.bc == 0 && !h->borrowed) {
     s = balanced_primal(h, J, src, dst, st, bal);
     if (s != UOT_OK) return s;
   }
@@ -1294,7 +1299,111 @@ uot_status time_core(uot_handle* h, const Layout& L, const float* src, const flo
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The no-allocation workspace: one fixed device array per GPU (each device
+// holds its own copy at its own address), located once per device with
+// hipGetSymbolAddress; host code uses only that address, never the array's
+// name, which on the host is a stand-in symbol and not a device address.
+static __device__ __align__(256) unsigned char scratch[UOT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// The scratch address on the current device `dev`.
+uot_status scratch_of(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return UOT_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return UOT_ERR_DEVICE;
+    g_scratch[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch[dev];
+  return UOT_OK;
+}
+
+// Hands out 256-byte-aligned pieces of the scratch.
+struct Carver {
+  unsigned char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n, size_t* cap) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(base + off);
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    *cap = std::max<size_t>(n, 1);
+    return p;
+  }
+};
+
+}  // namespace
+
 extern "C" {
+
+uot_status uot_solve_noalloc(const uot_params* prm, void* hip_stream, const float* src, const float* dst,
+                             uot_state* st, uot_report* rep) {
+  if (!prm || !src || !dst || !st || !rep) return UOT_ERR_ARG;
+  uot_status s = uot_check_params(prm);
+  if (s != UOT_OK) return s;
+  if (prm->flags & UOT_AUTOTUNE) return UOT_ERR_ARG;
+  if (prm->nx < 1 || prm->ny < 1) return UOT_ERR_SHAPE;
+  const int32_t nx = prm->nx, ny = prm->ny, pitch = prm->pitch > 0 ? prm->pitch : prm->nx;
+  const int64_t off = 0;
+  if ((int64_t)pitch * (ny - 1) + nx > (int64_t)UOT_NOALLOC_MAX_PIXELS) return UOT_ERR_TOO_LARGE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UOT_ERR_DEVICE;
+  unsigned char* base = nullptr;
+  s = scratch_of(dev, &base);
+  if (s != UOT_OK) return s;
+  try {
+    uot_handle h;
+    h.borrowed = true;
+    h.prm = *prm;
+    h.prm.flags |= UOT_NO_GRAPH;
+    h.stream = (hipStream_t)hip_stream;
+    h.device = dev;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      h.num_cu = cu;
+    const Layout lay{1, &nx, &ny, &pitch, &off};
+    Job J;
+    const bool ptrs_aligned = aligned4(src) && aligned4(dst) && aligned4(st->Mx) && aligned4(st->My) &&
+                              aligned4(st->r) && aligned4(st->a) && aligned4(st->x0) && aligned4(st->x1);
+    s = plan(&h, lay, J, 0, nullptr, ptrs_aligned);  // the plan solve_core will make: sizes only
+    if (s != UOT_OK) return s;
+    const size_t px = (size_t)J.total_px, nt = J.tiles.size();
+    if (nt > (size_t)UOT_NOALLOC_MAX_TILES) return UOT_ERR_TOO_LARGE;
+    Carver c{base};
+    for (int i = 0; i < 6; ++i) h.B[i] = c.take<float>(px, &h.capB[i]);
+    h.cplane = c.take<float>(px, &h.cap_c);
+    h.d_tiles = c.take<Tile>(nt, &h.cap_tiles);
+    h.d_live = c.take<Tile>(nt, &h.cap_live);
+    h.d_nlive = c.take<int32_t>(1, &h.cap_nlive);
+    h.d_partial = c.take<double>(nt * NS, &h.cap_partial);
+    h.d_pairs = c.take<PairInfo>(1, &h.cap_pairs);
+    h.d_sums = c.take<double>(NS, &h.cap_sums);
+    h.d_i32 = c.take<int32_t>(4, &h.cap_i32);
+    h.d_f64 = c.take<double>(3, &h.cap_f64);
+    h.d_invs = c.take<float>(1, &h.cap_invs);
+    h.d_mask = c.take<int32_t>(1, &h.cap_mask);
+    if (c.off > (size_t)UOT_NOALLOC_SCRATCH_BYTES) return UOT_ERR_TOO_LARGE;
+    // the host side of the per-pair records: plain (pageable) memory
+    double hsums[NS];
+    int32_t hi32[4];
+    h.h_sums = hsums;
+    h.cap_hsums = NS;
+    h.h_i32 = hi32;
+    h.cap_hi32 = 4;
+    s = solve_core(&h, lay, src, dst, st, rep);
+    if (hipStreamSynchronize(h.stream) != hipSuccess && s == UOT_OK) s = UOT_ERR_DEVICE;
+    return s;
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
 
 uot_status uot_solve(uot_handle* h, const float* src, const float* dst, uot_state* st, uot_report* rep) {
   if (!h) return UOT_ERR_ARG;

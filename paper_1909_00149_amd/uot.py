@@ -257,6 +257,25 @@ class Solver:
         return rep.as_dict()
 
 
+def solve_noalloc(params: Params, src, dst, state=None, stream=None):
+    """uot_solve_noalloc: one grid solved with the library's fixed device
+    scratch instead of a handle's allocations (for callers that cannot
+    allocate); returns (state, report)."""
+    lib = _lib.load()
+    if state is None:
+        state = new_state(params.mode, params.balanced, src.shape, src.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    c = params.to_c()
+    cs = _cstate(state)
+    rep = _lib.Report()
+    rc = lib.uot_solve_noalloc(ctypes.byref(c), ctypes.c_void_p(stream.cuda_stream), _ptr(src), _ptr(dst),
+                               ctypes.byref(cs), ctypes.byref(rep))
+    if rc != 0:
+        raise UOTError(rc, "uot_solve_noalloc")
+    return state, rep.as_dict()
+
+
 def pack(images):
     """Packs a list of (ny, nx) tensors into one flat plane; returns
     (packed, nx list, ny list, offsets)."""
