@@ -28,22 +28,25 @@ namespace uot {
 
 namespace {
 
+// Soft threshold sign(v) max(|v| - s, 0), s >= 0, as v minus its clamp to
+// [-s, s]: the same rounding (v - s, v + s or exactly 0), two instructions.
 __device__ __forceinline__ float shrink1f(float v, float s) {
-  float m = fabsf(v) - s;
-  return m > 0.f ? copysignf(m, v) : 0.f;
+  return v - __builtin_amdgcn_fmed3f(v, -s, s);
 }
 
 // Prox of tau1 times the flux norm at v = (vx, vy) of one pixel: the group
 // shrink of the l2,1 norm (the paper's), or with bit 1 of the boundary code
 // set, the component shrink of the anisotropic l1,1 norm.
 template <int BC>
-__device__ __forceinline__ void flux_shrink(float vx, float vy, float tau1, float t2, float& ox, float& oy) {
+__device__ __forceinline__ void flux_shrink(float vx, float vy, float tau1, float& ox, float& oy) {
   if (BC & 2) {
     ox = shrink1f(vx, tau1);
     oy = shrink1f(vy, tau1);
   } else {
+    // max(1 - tau1 / ||v||, 0) v; at v = 0 the reciprocal square root is
+    // +inf and the factor is 0
     const float n2 = vx * vx + vy * vy;
-    const float s = n2 > t2 ? 1.f - tau1 * rsqrtf(n2) : 0.f;
+    const float s = fmaxf(1.f - tau1 * rsqrtf(n2), 0.f);
     ox = s * vx;
     oy = s * vy;
   }
@@ -144,7 +147,6 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
     __syncthreads();
 
     // ---- new flux over the tile and its low-side halo ----
-    const float t2 = tau1 * tau1;
     for (int idx = tid; idx < (TY + 1) * (TX + 1); idx += BLOCK) {
       const int ry = idx / (TX + 1), rx = idx - ry * (TX + 1);
       const int gx = gx0 - 1 + rx, gy = gy0 - 1 + ry;
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_kernel(IterArgs A) {
         }
         const float vx = smx[ry][rx] - tau1 * gxx;
         const float vy = smy[ry][rx] - tau1 * gyy;
-        flux_shrink<BC>(vx, vy, tau1, t2, nxv, nyv);
+        flux_shrink<BC>(vx, vy, tau1, nxv, nyv);
       }
       snx[ry][rx] = nxv;
       sny[ry][rx] = nyv;
@@ -389,7 +391,6 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
       __syncthreads();
 
       // ---- new flux over the tile and its low-side halo ----
-      const float t2 = tau1 * tau1;
       auto shrink = [&](float ac, float ar, float au, float mx, float my, int gx, int gy, float& ox, float& oy) {
         if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) {
           ox = oy = 0.f;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_vec_kernel(IterArgs A) {
         }
         const float vx = mx - tau1 * gxx;
         const float vy = my - tau1 * gyy;
-        flux_shrink<BC>(vx, vy, tau1, t2, ox, oy);
+        flux_shrink<BC>(vx, vy, tau1, ox, oy);
       };
       for (int ry = rr; ry < TY + 1; ry += 16) {
         const int gy = gy0 - 1 + ry;
@@ -647,9 +648,16 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     for (int q = 0; q < NS; ++q) acc[q] = 0.0;
   }
 
+  // the next tile's record is loaded while this one computes; its flag and
+  // pair record are then loaded together
+  Tile tl_n{};
+  if (t < tend) tl_n = A.tiles[t];
   for (; t < tend; t += stride) {
-    const Tile tl = A.tiles[t];
-    if (!A.active[tl.pair]) continue;  // uniform over the block
+    const Tile tl = tl_n;
+    const int act = A.active[tl.pair];
+    const PairInfo P = A.pairs[tl.pair];
+    if (t + stride < tend) tl_n = A.tiles[t + stride];
+    if (!act) continue;  // uniform over the block
     if (CHK) {
       if (tl.pair != run_pair) {
         if (run_pair >= 0) {
@@ -665,10 +673,9 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
         A.chk[(long)tl.pad * NS + tid] = 0.0;
       }
     }
-    const PairInfo P = A.pairs[tl.pair];
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const long off = P.off;
-    const float tau1 = P.tau1, tau2 = P.tau2, t2 = tau1 * tau1;
+    const float tau1 = P.tau1, tau2 = P.tau2;
     const int bx = tl.x0 - H, by = tl.y0 - H;  // grid position of region cell (0, 0)
     int f_[NC];                                // flags of each cell
     float r_[NC], c0_[NC], c1_[NC], x0_[NC], x1_[NC], kp_[NC];
@@ -676,35 +683,40 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     float ka_[NOWN], kr_[NOWN], ku_[NOWN], kmx_[NOWN], kmy_[NOWN], kro_[NOWN], kx0_[NOWN], kx1_[NOWN];
 
     __syncthreads();  // LDS of the previous tile is no longer read
-    // ---- stage the region ----
+    // ---- stage the region: every cell's loads are issued before any is
+    // used, so their latencies overlap; a cell outside the grid loads the
+    // pair's first pixel (always valid) and keeps zero ----
+    float ga_[NC], gmx_[NC], gmy_[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       int rx, ry;
       region_cell<TH, H>(tid + k * BLOCK, rx, ry);
       const int gx = bx + rx, gy = by + ry;
       const bool in = ry < RH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-      const int l = l_[k];
       f_[k] = (in ? F_IN : 0) | ((BC & 1) == 0 && gx == nx - 1 ? F_ZX : 0) | ((BC & 1) == 0 && gy == ny - 1 ? F_ZY : 0);
-      float a = 0.f, mx = 0.f, my = 0.f;
-      r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
-      if (in) {
-        const long o = off + (long)gy * pitch + gx;
-        a = A.in.a[o];
-        mx = ((BC & 1) == 0 && gx == nx - 1) ? 0.f : A.in.Mx[o];
-        my = ((BC & 1) == 0 && gy == ny - 1) ? 0.f : A.in.My[o];
-        if (RES != R_BAL) r_[k] = A.in.r[o];
-        if (MODE == 0) {
-          c0_[k] = A.c[o];
-        } else {
-          c0_[k] = A.src[o];
-          c1_[k] = A.dst[o];
-          if (MODE == 1) x0_[k] = A.in.x0[o];
-          x1_[k] = A.in.x1[o];
-        }
+      const long o = off + (in ? (long)gy * pitch + gx : 0L);
+      ga_[k] = A.in.a[o];
+      gmx_[k] = A.in.Mx[o];
+      gmy_[k] = A.in.My[o];
+      r_[k] = RES != R_BAL ? A.in.r[o] : 0.f;
+      if (MODE == 0) {
+        c0_[k] = A.c[o];
+        c1_[k] = x0_[k] = x1_[k] = 0.f;
+      } else {
+        c0_[k] = A.src[o];
+        c1_[k] = A.dst[o];
+        x0_[k] = MODE == 1 ? A.in.x0[o] : 0.f;
+        x1_[k] = A.in.x1[o];
       }
-      sa[l] = a;
-      smx[l] = mx;
-      smy[l] = my;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const bool in = f_[k] & F_IN;
+      const int l = l_[k];
+      sa[l] = in ? ga_[k] : 0.f;
+      smx[l] = in && !(f_[k] & F_ZX) ? gmx_[k] : 0.f;
+      smy[l] = in && !(f_[k] & F_ZY) ? gmy_[k] : 0.f;
+      if (!in) r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
     }
     __syncthreads();
 
@@ -724,8 +736,13 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
 
     // one step over the region; KEEPSTEP: the step whose input iterate the
     // check compares with (the last), which keeps the owned cells' inputs
-    auto one_step = [&](auto keep_tag) {
+    // MASK: the region reaches past the grid or holds zero-flux cells, so
+    // the cells outside the grid are held at zero and the flux through the
+    // zero-flux edges at zero; without it (a region wholly inside the grid,
+    // away from those edges) the selects are no-ops and are left out
+    auto one_step = [&](auto keep_tag, auto mask_tag) {
       constexpr bool KEEPSTEP = decltype(keep_tag)::value;
+      constexpr bool MASK = decltype(mask_tag)::value;
       // ---- new flux: read every cell's inputs, then compute and write ----
       float ac_[NC], ar_[NC], au_[NC], mx_[NC], my_[NC];
 #pragma unroll
@@ -754,15 +771,15 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
       for (int k = 0; k < NC; ++k) {
         float gxx = ac_[k] - ar_[k];
         float gyy = ac_[k] - au_[k];
-        if ((BC & 1) == 0) {
+        if ((BC & 1) == 0 && MASK) {
           if (f_[k] & F_ZX) gxx = 0.f;
           if (f_[k] & F_ZY) gyy = 0.f;
         }
         const float vx = mx_[k] - tau1 * gxx;
         const float vy = my_[k] - tau1 * gyy;
         float ox, oy;
-        flux_shrink<BC>(vx, vy, tau1, t2, ox, oy);
-        const bool in = f_[k] & F_IN;
+        flux_shrink<BC>(vx, vy, tau1, ox, oy);
+        const bool in = !MASK || (f_[k] & F_IN);
         smx[l_[k]] = in ? ox : 0.f;
         smy[l_[k]] = in ? oy : 0.f;
       }
@@ -798,7 +815,7 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
           knew = dmn - c0_[k] + x1n;
         }
         if (RES != R_BAL) knew -= rn;
-        const bool in = f_[k] & F_IN;
+        const bool in = !MASK || (f_[k] & F_IN);
         sa[l_[k]] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
         kp_[k] = knew;
         r_[k] = rn;
@@ -807,12 +824,24 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
       }
       __syncthreads();
     };
-    if (CHK) {
-      // the host launches the check variant with 1 <= steps <= H - 1
-      for (int st = 0; st + 1 < steps; ++st) one_step(std::false_type{});
-      one_step(std::true_type{});
+    auto run = [&](auto mask_tag) {
+      if (CHK) {
+        // the host launches the check variant with 1 <= steps <= H - 1
+        for (int st = 0; st + 1 < steps; ++st) one_step(std::false_type{}, mask_tag);
+        one_step(std::true_type{}, mask_tag);
+      } else {
+        for (int st = 0; st < steps; ++st) one_step(std::false_type{}, mask_tag);
+      }
+    };
+    // a region inside the grid and away from its right and top edges needs
+    // no mask (the slots past the region read and write only zeros); the
+    // check variant always masks (a second copy of its steps would cost it
+    // registers and occupancy)
+    if constexpr (!CHK) {
+      if (bx >= 0 && by >= 0 && bx + RW <= nx - 1 && by + RH <= ny - 1) run(std::false_type{});
+      else run(std::true_type{});
     } else {
-      for (int st = 0; st < steps; ++st) one_step(std::false_type{});
+      run(std::true_type{});
     }
 
     if (CHK) {
@@ -915,7 +944,7 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
 // partial rows of the iterate pair of its last step (so the window needs
 // neither a single-step launch nor a separate check).
 template <int MODE, int RES, int BC, int TH, int H>
-__global__ __launch_bounds__(BLOCK) void cp_iter_tb_check_kernel(IterArgs A) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void cp_iter_tb_check_kernel(IterArgs A) {
   cp_iter_tb_body<MODE, RES, BC, TH, H, true>(A);
 }
 
