@@ -137,19 +137,22 @@ def golden_cases():
 @pytest.mark.parametrize("case", golden_cases(), ids=lambda c: c["name"])
 def test_unbalanced_blob_value_at_convergence(dev, case):
     """The seeded blob pair solved on the GPU to rel_res <= 1e-6 (adaptive
-    steps): its certified primal bound equals the oracle's certified value
-    to 1e-5 relative (plus the width of the oracle's interval), and the
-    GPU's certified interval contains the oracle's up to FP32 rounding."""
+    steps): its certified primal bound equals the value the oracle certified
+    (the midpoint of its [dual, primal] interval) to 1e-5 relative plus the
+    interval's half-width, and the GPU's certified interval overlaps the
+    oracle's up to 1e-5.  The oracle's interval is 1.4e-6 wide at 128^2
+    (4e5 FP64 iterations) and 1.75e-5 wide at 512^2 (3e5 iterations, 99
+    minutes on one core): there the value is pinned to about 2e-5."""
     side = case["side"]
     p, q = synth.unbalanced_pair(case["seed"], side=side, nblobs=case["blobs"], margin=min(24.0, side / 4))
-    s = G.Solver(G.Params(nx=side, ny=side, mu=case["mu"], max_iter=400000, check_every=20, tol=1e-6,
+    s = G.Solver(G.Params(nx=side, ny=side, mu=case["mu"], max_iter=600000, check_every=20, tol=1e-6,
                           flags=G.UOT_ADAPTIVE_STEPS))
     st, rep = s.solve(to_dev(p, dev), to_dev(q, dev))
     torch.cuda.synchronize()
     print(case["name"], {k: rep[k] for k in ("iters", "status_name", "rel_res", "primal", "dual", "objective")})
     assert rep["status_name"] == "CONVERGED", {k: rep[k] for k in ("iters", "rel_res", "primal", "dual")}
     lo, hi = case["dual"], case["primal"]
-    assert hi - lo <= 2e-6 * hi  # the oracle certified the value to this width
+    assert 0.0 <= hi - lo <= abs(case["rel_gap"]) * hi * (1 + 1e-9)
     vstar = 0.5 * (lo + hi)
     slack = 1e-5 * vstar + 0.5 * (hi - lo)
     assert abs(rep["primal"] - vstar) <= slack, (rep["primal"], lo, hi)
