@@ -71,23 +71,28 @@ BYTES = {(0, False): 36, (0, True): 28, (1, False): 56, (1, True): 48, (2, False
 FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False): 32, (2, True): 28}
 
 
-# HBM traffic of one launch of the fused kernel, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, averaged over the
-# dispatches of the timing launches) scaled by what the same counters read
-# for a 1 GiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid
-# only for the kernel sources they were taken on: any change to them makes
-# the figure unknown (null) until the counters are taken again.
+# Counters of one launch of the fused kernel, from rocprofv3 --pmc passes
+# over the graph-replayed timing launches of this script (the last 40
+# dispatches, every pair of a batch live): FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) scaled by what the same counters read for a 1 GiB device copy
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000), and the busy fractions of the
+# vector ALUs and the LDS, the mean waves per CU and the VALU instructions
+# issued.  Valid only for the kernel sources they were taken on: any change
+# to them makes every counter figure unknown (null) until they are taken
+# again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "4f23132b5edcbc675c3f9b1556cea5421652f4c9c46bb8e50f5fa9b6f8425002"
+TRAFFIC_SHA256 = "7397b837860edab2cde46d8ad13baceb1d22dae6780a4d1ec41564777e22f127"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
-# workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-TRAFFIC_KIB = {
-    "pair512": (4008, 2876.928, 4096.000),
-    "ragged256": (4016, 159274.156, 231696.491),
-    "sweep4096": (4016, 214475.684, 262148.915),
-    "video63": (4016, 64862.759, 96768.139),
+# workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB, VALUBusy %, LdsUtil %,
+#              MeanOccupancyPerCU, SQ_INSTS_VALU, TCC hit rate) per dispatch
+COUNTERS = {
+    "ragged256": (4016, 168936.303, 231696.375, 62.74, 53.31, 11.99, 74231688, 0.559),
+    "pair512": (4008, 2913.088, 4096.000, 19.32, 14.22, 3.18, 2106720, 0.670),
 }
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
+# 4 cycles (16 lanes), 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 / 4 * 2.4e9
 
 
 def kernel_sources_sha256():
@@ -99,11 +104,15 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(name, shape):
-    rec = TRAFFIC_KIB.get(name)
+def measured_counters(name, shape):
+    """The counter record of this workload's launch, or None when it was not
+    taken for this kernel shape and the current kernel sources."""
+    rec = COUNTERS.get(name)
     if rec is None or rec[0] != shape or kernel_sources_sha256() != TRAFFIC_SHA256:
         return None
-    return int(round((rec[1] * FETCH_SCALE + rec[2] * WRITE_SCALE) * 1024))
+    return {"traffic": int(round((rec[1] * FETCH_SCALE + rec[2] * WRITE_SCALE) * 1024)),
+            "valu_busy": rec[3] / 100.0, "lds_util": rec[4] / 100.0, "waves_per_cu": rec[5],
+            "valu_insts": rec[6], "l2_hit_rate": rec[7]}
 
 
 def kernel_name(mode, balanced, shape, residual_p=1, norm=0):
@@ -374,19 +383,43 @@ def main():
     bpp = BYTES[(W["mode"], W["balanced"])]
     px_launch = int(sum(npx))
     T = shape // 1000 if shape >= 1000 else 1  # iterations per launch
-    alg_bytes = bpp * px_launch * T            # per pixel-iteration bytes x pixel-iterations of a launch
-    achieved = alg_bytes / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, shape)
-    flops = FLOPS[(W["mode"], W["balanced"])] * px_launch * T / (ms * 1e-3) / 1e12
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_vs_algorithmic": round(traffic / alg_bytes, 4) if traffic else None,
-                "kernel": kernel_name(W["mode"], W["balanced"], shape, W.get("residual_p", 1), W.get("norm", 0)), "tile_rows": shape,
-                "iterations_per_launch": T, "bytes_per_pixel_iter": bpp, "pixels_per_launch": px_launch,
-                "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5),
-                "alu": {"achieved": round(flops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(flops / FP32_PEAK_TFLOPS, 4),
-                        "flops_per_pixel_iter": FLOPS[(W["mode"], W["balanced"])]}}
+    secs_launch = ms * 1e-3
+    fpp = FLOPS[(W["mode"], W["balanced"])]
+    # effective: the per-iteration algorithmic bytes of every iteration the
+    # launch runs (the metric's %HBM); a blocked launch can pass 1
+    eff = bpp * px_launch * T / secs_launch / 1e9
+    # physical: a launch must read and write the state once whatever T is
+    once = bpp * px_launch / secs_launch / 1e9
+    flops = fpp * px_launch * T / secs_launch / 1e12
+    cnt = measured_counters(args.workload, shape)
+    hbm_frac = (cnt["traffic"] / secs_launch / 1e9 / HBM_PEAK_GBS) if cnt else once / HBM_PEAK_GBS
+    # the bound is the unit the counters show busiest: the vector ALUs
+    # (issue) or HBM; without counters the one-iteration kernels are HBM
+    # streams and the blocked ones are taken as issue-bound
+    if cnt:
+        bound = "alu" if cnt["valu_busy"] >= hbm_frac else "hbm"
+    else:
+        bound = "alu" if T > 1 else "hbm"
+    if bound == "alu":
+        head = {"bound": "alu", "achieved": round(flops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(flops / FP32_PEAK_TFLOPS, 4)}
+    else:
+        head = {"bound": "hbm", "achieved": round(once, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(once / HBM_PEAK_GBS, 4)}
+    roofline = {**head, "traffic": cnt["traffic"] if cnt else None,
+                "kernel": kernel_name(W["mode"], W["balanced"], shape, W.get("residual_p", 1), W.get("norm", 0)),
+                "tile_rows": shape, "iterations_per_launch": T, "pixels_per_launch": px_launch,
+                "kernel_ms": round(ms, 5), "flops_per_pixel_iter": fpp, "bytes_per_pixel_iter": bpp,
+                "effective_hbm": {"achieved": round(eff, 1), "unit": "GB/s", "frac": round(eff / HBM_PEAK_GBS, 4),
+                                  "bytes_per_launch": bpp * px_launch * T},
+                "physical_hbm": {"achieved": round(cnt["traffic"] / secs_launch / 1e9, 1) if cnt else None,
+                                 "unit": "GB/s", "frac": round(hbm_frac, 4) if cnt else None,
+                                 "state_bytes_per_launch": bpp * px_launch,
+                                 "traffic_vs_state": round(cnt["traffic"] / (bpp * px_launch), 4) if cnt else None},
+                "counters": None if cnt is None else {
+                    "valu_busy": cnt["valu_busy"], "lds_util": cnt["lds_util"], "waves_per_cu": cnt["waves_per_cu"],
+                    "l2_hit_rate": cnt["l2_hit_rate"],
+                    "valu_issue_frac": round(cnt["valu_insts"] / secs_launch / VALU_ISSUE_PEAK, 4)}}
     out = {
         "metric": "pixel-iters/s (%HBM peak); time-to-1e-4 residual, warm-start vs cold",
         "value": value,
