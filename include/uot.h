@@ -92,6 +92,9 @@ enum { UOT_CONVERGED = 0, UOT_MAX_ITER = 1, UOT_DIVERGED = 2 };
 #define UOT_NO_GRAPH     0x10u /* launch kernels directly instead of replaying graphs */
 #define UOT_AUTOTUNE     0x20u /* time the tile shapes on first use of a size class   */
 #define UOT_ADAPTIVE_STEPS 0x40u /* rebalance tau1/tau2 at each check (needs tol > 0)  */
+#define UOT_WARM_FALLBACK 0x100u /* with UOT_WARM_START: a pair whose warm state holds a
+                                    non-finite value starts from zeros (its report says
+                                    cold_start) instead of failing the call               */
 #define UOT_RECORD_HISTORY 0x80u /* keep (iterations, rel_res) of every check of the last
                                     solve, per pair (uot_history); the checks then run
                                     every window even with tol <= 0, and the host waits
@@ -163,7 +166,7 @@ typedef struct uot_report {
   double seconds;      /* wall time of the call                                        */
   double tau1, tau2;   /* steps actually used                                          */
   int32_t tile_rows;   /* kernel shape that ran (a tile_rows code; 0 if no iteration)  */
-  int32_t reserved;
+  int32_t cold_start;  /* 1: UOT_WARM_FALLBACK replaced a non-finite warm state by zeros */
 } uot_report;
 
 typedef struct uot_handle uot_handle;

@@ -18,6 +18,7 @@ UOT_NO_GRAPH = 0x10
 UOT_AUTOTUNE = 0x20
 UOT_ADAPTIVE_STEPS = 0x40
 UOT_RECORD_HISTORY = 0x80
+UOT_WARM_FALLBACK = 0x100
 
 
 class Params(ctypes.Structure):
@@ -55,7 +56,7 @@ class Report(ctypes.Structure):
                 ("feas", ctypes.c_double), ("objective", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("tau1", ctypes.c_double),
                 ("tau2", ctypes.c_double), ("tile_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("cold_start", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

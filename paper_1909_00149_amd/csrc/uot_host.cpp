@@ -604,12 +604,19 @@ uot_status run_setup(uot_handle* h, const Job& J, const float* src, const float*
   return UOT_OK;
 }
 
-uot_status check_setup_sums(uot_handle* h, const Job& J, bool warm) {
+// cold: with UOT_WARM_FALLBACK, set for the pairs whose warm state holds a
+// non-finite value (they are restarted from zeros); otherwise such a pair
+// fails the call.
+uot_status check_setup_sums(uot_handle* h, const Job& J, bool warm, std::vector<int32_t>* cold = nullptr) {
   const uot_params& p = h->prm;
+  if (cold) cold->assign(J.B, 0);
   for (int b = 0; b < J.B; ++b) {
     const double* S = h->h_sums + (size_t)b * NS;
     if (S[U_NONFIN_IN] > 0) return UOT_ERR_NONFINITE;
-    if (warm && S[U_NONFIN_ST] > 0) return UOT_ERR_NONFINITE;
+    if (warm && S[U_NONFIN_ST] > 0) {
+      if (!cold || !(p.flags & UOT_WARM_FALLBACK)) return UOT_ERR_NONFINITE;
+      (*cold)[b] = 1;
+    }
     if (S[U_NEG] > 0 && !(p.flags & UOT_ALLOW_SIGNED)) return UOT_ERR_NEGATIVE;
     if (p.mode == UOT_DIST && p.balanced && p.bc == 0) {
       const double m = std::max({std::fabs(S[U_SUMS]), std::fabs(S[U_SUMD]), 1e-30});
@@ -991,8 +998,16 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, h->stream));
   s = run_setup(h, J, src, dst, st, warm, true);
   if (s != UOT_OK) return s;
-  s = check_setup_sums(h, J, warm);
+  std::vector<int32_t> cold;
+  s = check_setup_sums(h, J, warm, &cold);
   if (s != UOT_OK) return s;
+  if (std::find(cold.begin(), cold.end(), 1) != cold.end()) {
+    // the rejected warm states start from zeros, as a cold solve would
+    HIPCHK(hipMemcpyAsync(h->d_mask, cold.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_zero_pairs(planes_of(*st), h->d_pairs, h->d_tiles, (int)J.tiles.size(), J.ty, h->d_mask,
+                             aux_grid(h, (int)J.tiles.size()), h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
   const std::vector<double> scale = image_scales(h, B);
   if ((p.flags & UOT_AUTOTUNE) && p.tile_rows == 0 && !cached) {
     s = autotune(h, lay, src, dst, st, J);
@@ -1218,6 +1233,7 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     r.status = h->h_i32[2 * B + b];
     r.seconds = secs;
     r.tile_rows = J.shape;
+    r.cold_start = cold[b];
     // rel_res as the stopping rule last evaluated it (at the check where the
     // pair stopped, or at its last iterate)
     if (std::isfinite(relres[b])) r.rel_res = relres[b];

@@ -192,6 +192,8 @@ hipError_t launch_copy_active(const Planes& dst, const Planes& src, const PairIn
                               const Tile* tiles, int ntiles, int tile_rows, const int32_t* active,
                               int grid, hipStream_t s);
 hipError_t launch_dual(int grid, const DualArgs& a, hipStream_t s);
+hipError_t launch_zero_pairs(const Planes& st, const PairInfo* pairs, const Tile* tiles, int ntiles, int tile_rows,
+                             const int32_t* mask, int grid, hipStream_t s);
 hipError_t iter_occupancy(int mode, int resid, int bc, int ty, int* blocks_per_cu);
 // the same for the one-step check variant of a blocked shape
 hipError_t iter_chk_occupancy(int mode, int resid, int bc, int ty, int* blocks_per_cu);

@@ -190,6 +190,29 @@ __global__ __launch_bounds__(BLOCK) void copy_active_kernel(Planes dst, Planes s
   }
 }
 
+// Zeroes the state of the pairs whose flag is set (a cold start for pairs
+// whose warm state was rejected).
+__global__ __launch_bounds__(BLOCK) void zero_pairs_kernel(Planes st, const PairInfo* pairs, const Tile* tiles,
+                                                           int ntiles, int tile_rows, const int32_t* mask) {
+  const int lx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    if (!mask[tl.pair]) continue;
+    const PairInfo P = pairs[tl.pair];
+    for (int ly = wv; ly < tile_rows; ly += 4) {
+      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
+      if (gx >= P.nx || gy >= P.ny) continue;
+      const long o = P.off + (long)gy * P.pitch + gx;
+      st.Mx[o] = 0.f;
+      st.My[o] = 0.f;
+      st.a[o] = 0.f;
+      if (st.r) st.r[o] = 0.f;
+      if (st.x0) st.x0[o] = 0.f;
+      if (st.x1) st.x1[o] = 0.f;
+    }
+  }
+}
+
 // Dual value of the scaled multiplier a/s for the PROX modes: the infimum
 // over x >= 0 of the Lagrangian's x terms has the closed-form minimisers
 // max(p0 + rho a, 0) and max(p1 - rho a, 0).
@@ -295,6 +318,12 @@ hipError_t launch_copy_active(const Planes& dst, const Planes& src, const PairIn
                               int ntiles, int tile_rows, const int32_t* active, int grid, hipStream_t s) {
   hipLaunchKernelGGL(copy_active_kernel, dim3(grid), dim3(BLOCK), 0, s, dst, src, pairs, tiles, ntiles,
                      tile_rows, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_pairs(const Planes& st, const PairInfo* pairs, const Tile* tiles, int ntiles, int tile_rows,
+                             const int32_t* mask, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(zero_pairs_kernel, dim3(grid), dim3(BLOCK), 0, s, st, pairs, tiles, ntiles, tile_rows, mask);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ import torch
 
 from . import _lib
 from ._lib import (UOT_WARM_START, UOT_ALLOW_SIGNED, UOT_UNSAFE_STEPS, UOT_NO_GRAPH,  # noqa: F401
-                   UOT_AUTOTUNE, UOT_ADAPTIVE_STEPS, UOT_RECORD_HISTORY)
+                   UOT_AUTOTUNE, UOT_ADAPTIVE_STEPS, UOT_RECORD_HISTORY, UOT_WARM_FALLBACK)
 
 DIST, PROX, PROX_FIXED = 0, 1, 2
 NORM_ISO, NORM_ANISO = 0, 1

@@ -10,11 +10,15 @@ Targets are the solver's own iterates (flux and dual) at rel_res <= 1e-5
 in_scale q) and predicts (s_flux Mx, s_flux My, s_dual a); the start it
 gives is completed to a feasible one (r = D M + q - p) by the kernels.
 
-Evaluation solves the held-out pairs in one batched call per arm to
+Evaluation solves the held-out pairs in batched calls per arm to
 rel_res <= 1e-4: cold (zeros), Poisson-flux start, learned start.  The
-reported wall time of an arm includes building its start.  Fallback: a
-learned start that is rejected (non-finite) is replaced by the cold start;
-the cold solver's stopping rule decides convergence in every arm.
+reported wall time of an arm includes building its start.  The learned
+arm falls back to the cold start pair by pair: a pair whose start holds a
+non-finite value starts from zeros (UOT_WARM_FALLBACK), and a pair whose
+rel_res after the first check window (PROBE iterations) is worse than the
+cold start's after the same iterations is restarted from zeros; the cold
+solver's stopping rule decides convergence in every arm.  Each arm reports
+the certified primal and dual bounds at stop and their relative gap.
 """
 from __future__ import annotations
 
@@ -39,6 +43,7 @@ S_FLUX = NPX / 8.0
 S_DUAL = 1.0 / MU
 CH = (32, 64, 128, 128)
 EVAL_SEED0 = 1_000_000
+PROBE = 20  # iterations of the first check window, where the learned start is judged
 
 
 def _pair(seed):
@@ -53,7 +58,7 @@ def gen_pairs(seeds, workers=None):
     return np.stack([p for p, _ in out]), np.stack([q for _, q in out])
 
 
-def solve_targets(src, dst, dev, chunk=512, tol=1e-5, max_iter=8000, log=print):
+def solve_targets(src, dst, dev, chunk=512, tol=1e-5, max_iter=40000, log=print):
     """Solver iterates (Mx, My, a) for every pair: device tensors (n*NPX,)."""
     n = src.shape[0]
     out = {k: torch.empty(n * NPX, dtype=torch.float32, device=dev) for k in ("Mx", "My", "a")}
@@ -107,49 +112,75 @@ def train(net, src, dst, tgt, dev, epochs=4, batch=16, lr=1e-3, lr_min=2e-5, log
     return hist, time.perf_counter() - t0
 
 
+def _stats(reps, extra_iters=None):
+    it = np.array([r["iters"] for r in reps]) + (0 if extra_iters is None else extra_iters)
+    primal = np.array([r["primal"] for r in reps])
+    dual = np.array([r["dual"] for r in reps])
+    gap = np.array([r["rel_gap"] for r in reps])
+    return {"iters_median": float(np.median(it)), "iters_p90": float(np.percentile(it, 90)),
+            "iters_mean": float(it.mean()), "converged": int(sum(r["status"] == 0 for r in reps)),
+            "pairs": len(reps), "primal_mean": float(primal.mean()), "dual_mean": float(dual.mean()),
+            "rel_gap_mean": float(gap.mean()), "rel_gap_max": float(gap.max()),
+            "primal": primal.tolist(), "dual": dual.tolist()}
+
+
 def evaluate(net, src, dst, dev, tol=1e-4, max_iter=20000, arms=("cold", "poisson", "learned"), repeats=1):
-    """Batched solve of all pairs per arm; returns per-arm statistics."""
+    """Batched solve of all pairs per arm; returns per-arm statistics (the
+    per-pair certified bounds included)."""
     n = src.shape[0]
     S = torch.from_numpy(src.reshape(-1)).to(dev)
     D = torch.from_numpy(dst.reshape(-1)).to(dev)
     nx = [SIDE] * n
     offs = [b * NPX for b in range(n)]
+    prm = dict(mu=MU, check_every=20)
     res = {}
     for arm in arms:
-        flags = G.UOT_ADAPTIVE_STEPS | (0 if arm == "cold" else G.UOT_WARM_START)
-        s = G.Solver(G.Params(mu=MU, tol=tol, max_iter=max_iter, check_every=20, flags=flags))
         best = None
         for _ in range(repeats):
             st = G.new_state(G.DIST, False, n * NPX, dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if arm == "poisson":
+            fallback = 0
+            if arm == "cold":
+                s = G.Solver(G.Params(tol=tol, max_iter=max_iter, flags=G.UOT_ADAPTIVE_STEPS, **prm))
+                _, reps = s.solve_batched(S, D, nx, nx, offs, st)
+                t_start, pre = 0.0, None
+            elif arm == "poisson":
+                s = G.Solver(G.Params(tol=tol, max_iter=max_iter, flags=G.UOT_ADAPTIVE_STEPS | G.UOT_WARM_START, **prm))
                 s.init_poisson(S, D, st, nx=nx, ny=nx, offset=offs)
-            elif arm == "learned":
+                t_start = time.perf_counter() - t0
+                _, reps = s.solve_batched(S, D, nx, nx, offs, st)
+                pre = None
+            else:
                 for c0 in range(0, n, net.batch_max):
                     c1 = min(n, c0 + net.batch_max)
                     sub = {k: v[c0 * NPX:c1 * NPX] for k, v in st.items()}
                     net.warm_state(S[c0 * NPX:c1 * NPX], D[c0 * NPX:c1 * NPX], sub, IN_SCALE, S_FLUX, S_DUAL)
-            t_start = time.perf_counter() - t0
-            try:
+                t_start = time.perf_counter() - t0
+                # the first window from the learned start (non-finite starts
+                # begin from zeros) and from the cold start
+                warm = G.Solver(G.Params(tol=0.0, max_iter=PROBE,
+                                         flags=G.UOT_WARM_START | G.UOT_WARM_FALLBACK, **prm))
+                _, r1 = warm.solve_batched(S, D, nx, nx, offs, st)
+                cst = G.new_state(G.DIST, False, n * NPX, dev)
+                _, rc = G.Solver(G.Params(tol=0.0, max_iter=PROBE, **prm)).solve_batched(S, D, nx, nx, offs, cst)
+                del cst
+                lose = [b for b in range(n)
+                        if r1[b]["cold_start"] or not np.isfinite(r1[b]["rel_res"]) or r1[b]["rel_res"] > rc[b]["rel_res"]]
+                fallback = len(lose)
+                if lose:  # those pairs restart from zeros (a zero-iteration cold solve writes them)
+                    G.Solver(G.Params(tol=0.0, max_iter=0, **prm)).solve_batched(
+                        S, D, [SIDE] * len(lose), [SIDE] * len(lose), [offs[b] for b in lose], st)
+                s = G.Solver(G.Params(tol=tol, max_iter=max_iter - PROBE,
+                                      flags=G.UOT_ADAPTIVE_STEPS | G.UOT_WARM_START, **prm))
                 _, reps = s.solve_batched(S, D, nx, nx, offs, st)
-            except G.UOTError as e:
-                if e.code != 4 or arm == "cold":
-                    raise
-                # rejected start: fall back to the cold start
-                cold = G.Solver(G.Params(mu=MU, tol=tol, max_iter=max_iter, check_every=20,
-                                         flags=G.UOT_ADAPTIVE_STEPS))
-                _, reps = cold.solve_batched(S, D, nx, nx, offs, st)
+                pre = np.full(n, PROBE)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             if best is None or wall < best[0]:
-                best = (wall, t_start, reps)
-        wall, t_start, reps = best
-        it = np.array([r["iters"] for r in reps])
-        res[arm] = {"wall_s": wall, "start_s": t_start, "iters_median": float(np.median(it)),
-                    "iters_p90": float(np.percentile(it, 90)), "iters_mean": float(it.mean()),
-                    "converged": int(sum(r["status"] == 0 for r in reps)), "pairs": n,
-                    "primal_mean": float(np.mean([r["primal"] for r in reps]))}
+                best = (wall, t_start, reps, pre, fallback)
+        wall, t_start, reps, pre, fallback = best
+        res[arm] = {"wall_s": wall, "start_s": t_start, "fallback": fallback, **_stats(reps, pre)}
     return res
 
 
@@ -173,7 +204,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--target-iters", type=int, default=8000)
+    ap.add_argument("--target-iters", type=int, default=40000)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "data", "warmstart_256.npz"))
     ap.add_argument("--report", default=None)
     ap.add_argument("--load", default=None, help="skip training, evaluate saved parameters")
@@ -194,6 +225,7 @@ def main():
         t = time.perf_counter()
         tgt, iters = solve_targets(src, dst, dev, max_iter=args.target_iters, log=log)
         report["targets"] = {"seconds": time.perf_counter() - t, "iters_median": float(np.median(iters)),
+                             "iters_max": int(iters.max()), "tol": 1e-5, "cap": args.target_iters,
                              "rms_Mx": float(tgt["Mx"].float().pow(2).mean().sqrt()) * S_FLUX,
                              "rms_a": float(tgt["a"].float().pow(2).mean().sqrt()) * S_DUAL}
         log(json.dumps(report["targets"]))
@@ -205,7 +237,8 @@ def main():
         del tgt, src, dst
         torch.cuda.empty_cache()
     report["eval"] = evaluate(net, esrc, edst, dev)
-    log(json.dumps(report["eval"]))
+    log(json.dumps({arm: {k: v for k, v in r.items() if k not in ("primal", "dual")}
+                    for arm, r in report["eval"].items()}))
     if args.report:
         with open(args.report, "w") as f:
             json.dump(report, f, indent=1)

@@ -21,11 +21,13 @@ from paper_1909_00149_amd import synth  # noqa: E402
 
 # (name, seed, side, blobs, mu): the 512^2 pair and a 128^2 cut-down with
 # the blob density of the 512^2 recipe scaled up to keep it non-trivial
-CASES = [("pair128", 7, 128, 6, 8.0), ("pair512", 0, 512, 20, 8.0)]
+CASES = [("pair128", 7, 128, 6, 8.0), ("pair512", 0, 512, 20, 8.0),
+         # two held-out pairs of the learned-start evaluation (256^2 recipe)
+         ("heldout256a", 1005000, 256, 20, 8.0), ("heldout256b", 1005001, 256, 20, 8.0)]
 
 
-def main(names=None, max_iter=300000, gap_tol=1e-10):
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "converged_values.json")
+def main(names=None, max_iter=300000, gap_tol=1e-10, out=None):
+    path = out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "converged_values.json")
     old = {}
     if os.path.exists(path):
         with open(path) as f:
@@ -50,4 +52,12 @@ def main(names=None, max_iter=300000, gap_tol=1e-10):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or None)
+    # python tests/golden/make_converged.py [names...] [--out file.json] [--iters N]
+    argv = sys.argv[1:]
+    kw = {}
+    for flag, key, conv in (("--out", "out", str), ("--iters", "max_iter", int)):
+        if flag in argv:
+            i = argv.index(flag)
+            kw[key] = conv(argv[i + 1])
+            del argv[i:i + 2]
+    main(argv or None, **kw)

@@ -39,14 +39,15 @@ def test_learned_start_beats_cold_start(dev):
 
 def test_rejected_start_falls_back_to_cold(dev):
     """A network producing non-finite values gives a start the solver
-    rejects; the evaluation falls back to the cold start and converges."""
+    rejects; every pair of the learned arm falls back to the cold start and
+    converges."""
     net = WS.load_net(WEIGHTS, dev, batch_max=16)
     bad = net.get_params()
     bad[:] = np.nan
     net.set_params(bad)
     src, dst = heldout(4, first=WS.EVAL_SEED0 + 9000)
     res = WS.evaluate(net, src, dst, dev, arms=("learned",))
-    assert res["learned"]["converged"] == 4
+    assert res["learned"]["converged"] == 4 and res["learned"]["fallback"] == 4
     # and the warm solve by itself reports the rejection
     S = torch.from_numpy(src.reshape(-1)).to(dev)
     D = torch.from_numpy(dst.reshape(-1)).to(dev)
@@ -56,3 +57,33 @@ def test_rejected_start_falls_back_to_cold(dev):
     with pytest.raises(G.UOTError) as e:
         s.solve_batched(S, D, [WS.SIDE] * 4, [WS.SIDE] * 4, [b * WS.NPX for b in range(4)], st)
     assert e.value.code == 4
+
+
+def test_warm_fallback_per_pair(dev):
+    """UOT_WARM_FALLBACK: in a batch whose second pair's warm state holds a
+    NaN, that pair starts from zeros (cold_start in its report, iterates
+    bitwise those of a cold solve) while the others start from their warm
+    states (bitwise those of their own warm solves)."""
+    src, dst = heldout(3, first=WS.EVAL_SEED0 + 9100)
+    n = WS.NPX
+    S = torch.from_numpy(src.reshape(-1)).to(dev)
+    D = torch.from_numpy(dst.reshape(-1)).to(dev)
+    rng = np.random.default_rng(5)
+    warm = {k: torch.from_numpy((rng.standard_normal(3 * n) * 1e-4).astype(np.float32)).to(dev)
+            for k in ("Mx", "My", "r", "a")}
+    warm["a"].mul_(1e3)
+    bad = {k: v.clone() for k, v in warm.items()}
+    bad["a"][n + 17] = float("nan")
+    sides, offs = [WS.SIDE] * 3, [0, n, 2 * n]
+    kw = dict(mu=WS.MU, tol=1e-4, max_iter=400, check_every=20)
+    st, reps = G.Solver(G.Params(flags=G.UOT_WARM_START | G.UOT_WARM_FALLBACK, **kw)).solve_batched(
+        S, D, sides, sides, offs, {k: v.clone() for k, v in bad.items()})
+    assert [r["cold_start"] for r in reps] == [0, 1, 0]
+    cold, rc = G.Solver(G.Params(**kw)).solve_batched(S, D, sides, sides, offs)
+    ref, rw = G.Solver(G.Params(flags=G.UOT_WARM_START, **kw)).solve_batched(
+        S, D, sides, sides, offs, {k: v.clone() for k, v in warm.items()})
+    torch.cuda.synchronize()
+    for k in ("Mx", "My", "r", "a"):
+        assert torch.equal(st[k][n:2 * n], cold[k][n:2 * n]), k
+        assert torch.equal(st[k][:n], ref[k][:n]) and torch.equal(st[k][2 * n:], ref[k][2 * n:]), k
+    assert reps[1]["iters"] == rc[1]["iters"] and reps[0]["iters"] == rw[0]["iters"]
