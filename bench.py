@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--workload", default="ragged256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=400)
-    ap.add_argument("--warm-pairs", type=int, default=64,
+    ap.add_argument("--warm-pairs", type=int, default=1000,
                     help="held-out 256x256 pairs for the warm-vs-cold time to 1e-4 (0: skip)")
     ap.add_argument("--prox-iters", default=None,
                     help="rpca, rpca_signed: comma-separated prox passes per ADMM iteration to study (default: all)")
@@ -753,11 +753,14 @@ def warm_vs_cold(dev, n):
     net = WS.load_net(path, dev, batch_max=16)
     res = WS.evaluate(net, src, dst, dev, arms=("cold", "learned"), repeats=3)
     c, l = res["cold"], res["learned"]
+    cp, lp = np.array(c["primal"]), np.array(l["primal"])
     return {"pairs": n, "side": WS.SIDE, "tol": 1e-4,
             "cold_ms": round(1e3 * c["wall_s"], 3), "learned_ms": round(1e3 * l["wall_s"], 3),
             "learned_start_ms": round(1e3 * l["start_s"], 3),
             "cold_iters_median": c["iters_median"], "learned_iters_median": l["iters_median"],
-            "converged": [c["converged"], l["converged"]],
+            "converged": [c["converged"], l["converged"]], "learned_fell_back": l["fallback"],
+            "rel_gap_mean": [round(c["rel_gap_mean"], 5), round(l["rel_gap_mean"], 5)],
+            "learned_primal_above_cold_mean": float(np.mean((lp - cp) / cp)),
             "speedup": round(c["wall_s"] / l["wall_s"], 3)}
 
 

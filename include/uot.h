@@ -275,6 +275,22 @@ uot_status uot_init_poisson_pitched(uot_handle *h, int32_t B, const int32_t *nx,
                                     const int32_t *pitch, const int64_t *offset, const float *src,
                                     const float *dst, uot_state *packed);
 
+/* Advances the state `in` by `iters` iterations of Algorithm 1 into `out`,
+ * with no stopping rule and no checks: the fixed number of warm-started
+ * prox passes an outer solver makes per outer iteration (Sec. IV, Algorithms
+ * 2 and 3 call the prox that way).  One fused launch per up to T iterations
+ * (the handle's kernel shape), alternating between `out` and the handle's
+ * shadow copy so that the first launch reads `in` and the last writes `out`.
+ * `in` is only read: it is validated like a warm start (a non-finite value
+ * gives UOT_ERR_NONFINITE) and its structural boundary zeros are taken as
+ * zero whatever it holds there.  No plane of `out` may be a plane of `in`
+ * (UOT_ERR_ARG).  One grid (uot_params nx, ny, pitch); the steps are the
+ * handle's (tau1, tau2, or the scaled default of the images; no residual
+ * balancing).  iters = 0 copies `in` to `out`.  src/dst as for uot_solve.
+ * Synchronous. */
+uot_status uot_step(uot_handle *h, const float *src, const float *dst, const uot_state *in, uot_state *out,
+                    int32_t iters);
+
 /* Profiling aid: captures n (rounded up to even) back-to-back launches of
  * the fused iteration kernel on the handle's grid and stream into a graph,
  * replays it once untimed and once bracketed by HIP events, starting from

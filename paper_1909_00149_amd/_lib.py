@@ -144,6 +144,8 @@ SIGNATURES = {
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State)]),
+    "uot_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(State),
+                                ctypes.POINTER(State), ctypes.c_int32]),
     "uot_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(State), ctypes.POINTER(Report)]),
     "uot_destroy": (None, [ctypes.c_void_p]),

@@ -17,26 +17,12 @@
 
 #include "../../include/uot.h"
 #include "uot_internal.hpp"
+#include "uot_plan.hpp"
 
 using namespace uot;
+using namespace uot::planner;
 
 namespace {
-
-constexpr double kPi = 3.14159265358979323846;
-
-double lam1d(int n, int bc) {
-  if (bc == 0) {
-    const double s = std::sin(kPi * (n - 1) / (2.0 * n));
-    return 4.0 * s * s;
-  }
-  const double s = std::sin(kPi * (2.0 * n - 1) / (2.0 * (2.0 * n + 1)));
-  return 4.0 * s * s;
-}
-
-int n_identity(int mode, int balanced) {
-  const int base = mode == UOT_DIST ? 1 : (mode == UOT_PROX ? 3 : 2);
-  return base - (balanced ? 1 : 0);
-}
 
 int resid_of(const uot_params& p) { return p.balanced ? R_BAL : (p.residual_p == 2 ? R_P2 : R_P1); }
 
@@ -84,85 +70,6 @@ void tune_store_locked() {
     std::fprintf(f, "  \"%s\" : %d%s\n", kv.first.c_str(), kv.second, ++i < g_tune_cache.size() ? "," : "");
   std::fprintf(f, "}\n");
   std::fclose(f);
-}
-
-// Default kernel shape by size (the codes are listed with shape_rows below).
-// Measured on one MI355X, per iteration: the blocked kernels take 1.55 us at
-// 256^2 with 64 x 4 tiles (1.78 with 64 x 8; single-step: 3.7 us, the launch
-// floor), 2.1 us at 512^2 with 64 x 8 (2.5 with 64 x 4), 60 us at 4096^2
-// (121) and 56 us on a 14.7 Mpx ragged batch (110).
-int heuristic_shape(long npx) {
-  // temporally blocked, 4 iterations per launch: the smaller the grid, the
-  // smaller the tile, so that enough workgroups hide the latency of the
-  // steps' barriers; above 2^18 pixels 64 x 16 tiles (less halo work)
-  return npx <= (1L << 16) ? 4004 : (npx <= (1L << 18) ? 4008 : 4016);
-}
-
-// Kernel shape codes: rows (4, 8, 16, 32) = the scalar kernel; 100 + rows =
-// the vectorised kernel; 300 + rows = the same with non-temporal stores;
-// 1000 * T + rows = T iterations per launch (temporally blocked), whose
-// single steps run the vectorised kernel of the same rows (the scalar one
-// for 8 rows, which the vectorised form does not have).
-int shape_rows(int code) { return code >= 1000 ? code % 1000 : code % 100; }
-int shape_steps(int code) { return code >= 1000 ? code / 1000 : 1; }
-int shape_single(int code) {
-  if (code < 1000) return code;
-  const int rows = code % 1000;
-  return rows % 16 == 0 ? 100 + rows : rows;
-}
-// Steps of the check variant of a blocked shape (the window's last launch,
-// halo one more than that): 4 for the 4- and 8-step shapes of 4 to 16
-// rows, 2 for 2016 and the 32-row shapes (fewer registers).
-int shape_chk_steps(int code) {
-  switch (code) {
-    case 4004: case 4008: case 4016: case 8016: return 4;
-    case 2016: case 4032: case 8032: return 2;
-  }
-  return 1;
-}
-bool shape_known(int code) {
-  switch (code) {
-    case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
-    case 4004: case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: return true;
-  }
-  return false;
-}
-
-// Iterations per launch for n iterations with up to T per launch.  With
-// last_single the final launch runs one iteration (the convergence check
-// compares the last two iterates, which must both be in the ping-pong
-// buffers); with even the number of launches is even, so the iterate ends in
-// the buffer it started in.  The iterations are spread evenly over the
-// launches.
-std::vector<int> step_schedule(int n, int T, bool last_single, bool even) {
-  std::vector<int> v;
-  if (n <= 0) return v;
-  if (T <= 1) return std::vector<int>(n, 1);
-  const int R = last_single ? n - 1 : n;
-  int k = (R + T - 1) / T;
-  int total = k + (last_single ? 1 : 0);
-  if (even && (total & 1)) {
-    if (k + 1 > R) return std::vector<int>(n, 1);
-    ++k;
-  }
-  for (int i = 0; i < k; ++i) v.push_back(R / k + (i < R % k ? 1 : 0));
-  if (last_single) v.push_back(1);
-  return v;
-}
-
-// A check window of n iterations on a blocked shape: launches of up to T
-// iterations, the last one (the check variant) of up to F, spread evenly.
-// The number of launches may be odd: the window then ends in the other
-// copy of the state.
-std::vector<int> fused_schedule(int n, int T, int F) {
-  std::vector<int> v;
-  if (n <= 0) return v;
-  const int f = std::min(F, n);
-  const int R = n - f;
-  const int k = (R + T - 1) / T;
-  for (int i = 0; i < k; ++i) v.push_back(R / k + (i < R % k ? 1 : 0));
-  v.push_back(f);
-  return v;
 }
 
 bool aligned4(const void* p) { return p == nullptr || ((uintptr_t)p & 3u) == 0; }
@@ -298,38 +205,10 @@ const char* uot_status_string(uot_status s) {
 }
 
 double uot_knorm2(int32_t nx, int32_t ny, int32_t mode, int32_t balanced, int32_t bc) {
-  if (nx < 1 || ny < 1 || mode < 0 || mode > 2 || bc < 0 || bc > 1) return -1.0;
-  return lam1d(nx, bc) + lam1d(ny, bc) + n_identity(mode, balanced ? 1 : 0);
+  return planner::knorm2_of(nx, ny, mode, balanced, bc);
 }
 
-uot_status uot_check_params(const uot_params* p) {
-  if (!p) return UOT_ERR_ARG;
-  if (p->mode < 0 || p->mode > 2) return UOT_ERR_ARG;
-  if (p->balanced != 0 && p->balanced != 1) return UOT_ERR_ARG;
-  if (!p->balanced && p->residual_p != 1 && p->residual_p != 2) return UOT_ERR_ARG;
-  if (p->bc != 0 && p->bc != 1) return UOT_ERR_ARG;
-  if (p->norm != UOT_NORM_ISO && p->norm != UOT_NORM_ANISO) return UOT_ERR_ARG;
-  if (!p->balanced && !(p->mu > 0.0 && std::isfinite(p->mu))) return UOT_ERR_ARG;
-  if (p->mode != UOT_DIST && !(p->rho > 0.0 && std::isfinite(p->rho))) return UOT_ERR_ARG;
-  if (!(p->tau1 >= 0.0 && p->tau2 >= 0.0) || !std::isfinite(p->tau1) || !std::isfinite(p->tau2)) return UOT_ERR_ARG;
-  if ((p->tau1 == 0.0) != (p->tau2 == 0.0)) return UOT_ERR_ARG;
-  if (p->max_groups < 0) return UOT_ERR_ARG;
-  if (p->max_iter < 0 || p->check_every < 0) return UOT_ERR_ARG;
-  if (!std::isfinite(p->tol)) return UOT_ERR_ARG;
-  switch (p->tile_rows) {
-    case 0: case 4: case 8: case 16: case 32: case 116: case 132: case 316: case 332:
-    case 4004: case 4008: case 2016: case 4016: case 8016: case 4032: case 8032: break;
-    default: return UOT_ERR_ARG;
-  }
-  if ((p->flags & UOT_ALLOW_SIGNED) && p->mode != UOT_DIST) return UOT_ERR_ARG;
-  if (p->nx < 0 || p->ny < 0) return UOT_ERR_SHAPE;
-  if (p->pitch != 0 && p->pitch < p->nx) return UOT_ERR_SHAPE;
-  if (p->nx > 0 && p->ny > 0 && p->tau1 > 0.0 && !(p->flags & UOT_UNSAFE_STEPS)) {
-    const double k2 = uot_knorm2(p->nx, p->ny, p->mode, p->balanced, p->bc);
-    if (p->tau1 * p->tau2 * k2 >= 1.0) return UOT_ERR_STEP;
-  }
-  return UOT_OK;
-}
+uot_status uot_check_params(const uot_params* p) { return planner::check_params(p); }
 
 uot_status uot_create(const uot_params* prm, void* hip_stream, uot_handle** out) {
   if (!out) return UOT_ERR_ARG;
@@ -374,21 +253,6 @@ namespace {
     }                                               \
   } while (0)
 
-// Default steps (tau1 = tau2 = 0 in the params).  The problem is
-// 1-homogeneous in the images: scaling p and q by t scales M and r by t and
-// leaves the multiplier a unchanged, and running the iteration on the
-// scaled images is running it on the originals with tau1 / t and tau2 t.
-// The default therefore follows the image scale s (the largest |pixel| of
-// the pair's two images; 1 if that is zero):
-//   tau1 = 0.99 s / ||K||,   tau2 = 0.99 / (s ||K||),
-// so the iterates of scaled images are the scaled iterates, and the
-// product tau1 tau2 ||K||^2 = 0.98 < 1 (Theorem 1) whatever s is.
-void default_steps(double k2, double scale, double* t1, double* t2) {
-  const double k = std::sqrt(k2);
-  *t1 = 0.99 * scale / k;
-  *t2 = 0.99 / (scale * k);
-}
-
 double image_scale(const double* setup_sums) {
   const double s = setup_sums[U_MAXIN];
   return std::isfinite(s) && s > 0.0 ? s : 1.0;
@@ -423,12 +287,7 @@ Planes planes_of(const uot_state& s) { return Planes{s.Mx, s.My, s.r, s.a, s.x0,
 // reading, bit 1 the anisotropic flux norm.
 int bcn_of(const uot_params& p) { return p.bc | (p.norm == UOT_NORM_ANISO ? 2 : 0); }
 
-// The caller's cap on the persistent grids (uot_params.max_groups), rounded
-// down to a multiple of the 8 XCDs, at least 8; no cap when 0.
-long group_cap(const uot_handle* h) {
-  const int m = h->prm.max_groups;
-  return m > 0 ? std::max(8, m / 8 * 8) : LONG_MAX;
-}
+long group_cap(const uot_handle* h) { return planner::group_cap_of(h->prm.max_groups); }
 
 int iter_grid(uot_handle* h, int mode, int resid, int bc, int ty, int ntiles, bool chk = false) {
   int occ = 0;
@@ -471,18 +330,9 @@ uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* 
   J.B = B;
   J.pairs.resize(B);
   J.knorm2.resize(B);
-  std::vector<std::pair<int64_t, int64_t>> ranges(B);
   long total = 0, npx = 0;
-  for (int b = 0; b < B; ++b) {
-    if (nx[b] < 1 || ny[b] < 1 || offset[b] < 0 || L.pitch_of(b) < nx[b]) return UOT_ERR_SHAPE;
-    const int64_t extent = (int64_t)L.pitch_of(b) * (ny[b] - 1) + nx[b];
-    ranges[b] = {offset[b], offset[b] + extent};
-    total = std::max<long>(total, offset[b] + extent);
-    npx += (long)nx[b] * ny[b];
-  }
-  std::sort(ranges.begin(), ranges.end());
-  for (int b = 1; b < B; ++b)
-    if (ranges[b].first < ranges[b - 1].second) return UOT_ERR_SHAPE;
+  const uot_status ls = planner::check_layout(B, nx, ny, L.pitch, offset, &total, &npx);
+  if (ls != UOT_OK) return ls;
   J.total_px = total;
   J.npx = npx;
   J.vec_ok = ptrs_aligned;
@@ -1244,6 +1094,73 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   return UOT_OK;
 }
 
+// iters iterations from `in` into `out` (see uot_step).
+uot_status step_core(uot_handle* h, const Layout& L, const float* src, const float* dst, const uot_state* in,
+                     uot_state* out, int32_t iters) {
+  const uot_params& p = h->prm;
+  if (!src || !dst || !in || !out || iters < 0) return UOT_ERR_ARG;
+  uot_status s = validate_state(p, in);
+  if (s != UOT_OK) return s;
+  s = validate_state(p, out);
+  if (s != UOT_OK) return s;
+  const Planes pi = planes_of(*in), po = planes_of(*out);
+  const float* const vin[6] = {pi.Mx, pi.My, pi.r, pi.a, pi.x0, pi.x1};
+  const float* const vout[6] = {po.Mx, po.My, po.r, po.a, po.x0, po.x1};
+  for (const float* a : vin)
+    for (const float* b : vout)
+      if (a && a == b) return UOT_ERR_ARG;
+  Job J;
+  const bool ptrs_aligned = aligned4(src) && aligned4(dst) && aligned4(in->Mx) && aligned4(in->My) &&
+                            aligned4(in->r) && aligned4(in->a) && aligned4(in->x0) && aligned4(in->x1) &&
+                            aligned4(out->Mx) && aligned4(out->My) && aligned4(out->r) && aligned4(out->a) &&
+                            aligned4(out->x0) && aligned4(out->x1);
+  s = plan(h, L, J, 0, nullptr, ptrs_aligned);
+  if (s != UOT_OK) return s;
+  if (hipSetDevice(h->device) != hipSuccess) return UOT_ERR_DEVICE;
+  const int resid = resid_of(p);
+  const bool need[6] = {true, true, resid != R_BAL, true, p.mode == UOT_PROX, p.mode != UOT_DIST};
+  if (iters == 0) {
+    const size_t n = (size_t)J.total_px * sizeof(float);
+    float* const dsts[6] = {po.Mx, po.My, po.r, po.a, po.x0, po.x1};
+    for (int i = 0; i < 6; ++i)
+      if (need[i]) HIPCHK(hipMemcpyAsync(dsts[i], vin[i], n, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return UOT_OK;
+  }
+  s = ensure_workspace(h, J);
+  if (s != UOT_OK) return s;
+  HIPCHK(hipMemcpyAsync(h->d_pairs, J.pairs.data(), J.B * sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->d_tiles, J.tiles.data(), J.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                        h->stream));
+  s = run_setup(h, J, src, dst, in, true, false);  // validates `in`, writes c; the state is only read
+  if (s != UOT_OK) return s;
+  s = check_setup_sums(h, J, true);
+  if (s != UOT_OK) return s;
+  s = scale_default_steps(h, J, image_scales(h, J.B));
+  if (s != UOT_OK) return s;
+  for (int b = 0; b < J.B; ++b) h->h_i32[b] = 1;
+  HIPCHK(hipMemcpyAsync(h->d_i32, h->h_i32, (size_t)J.B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  s = upload_live(h, J, h->h_i32);
+  if (s != UOT_OK) return s;
+  const int grid = iter_grid(h, p.mode, resid, bcn_of(p), J.shape, (int)J.tiles.size());
+  const int grid1 = iter_grid(h, p.mode, resid, bcn_of(p), shape_single(J.shape), (int)J.tiles.size());
+  const Planes sh = shadow_planes(h);
+  const float* cptr = p.mode == UOT_DIST ? h->cplane : nullptr;
+  // launch i writes `out` when an even number of launches follows it, else
+  // the shadow; the first reads `in`, every other one its predecessor's output
+  const std::vector<int> sched = step_schedule(iters, shape_steps(J.shape), false, false);
+  const int n = (int)sched.size();
+  Planes from = pi;
+  for (int i = 0; i < n; ++i) {
+    const Planes to = ((n - 1 - i) % 2 == 0) ? po : sh;
+    const IterArgs a{from, to, cptr, src, dst, h->d_pairs, h->d_live, h->d_nlive, h->d_i32};
+    HIPCHK(launch_steps(h, resid, J.shape, sched[i], grid, grid1, a));
+    from = to;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return UOT_OK;
+}
+
 // Back-to-back fused-iteration launches over a batch layout, replayed from one
 // captured graph and bracketed by events (every pair live).
 uot_status time_core(uot_handle* h, const Layout& L, const float* src, const float* dst, uot_state* st,
@@ -1445,6 +1362,20 @@ uot_status uot_solve_batched_pitched(uot_handle* h, int32_t B, const int32_t* nx
   if (!h) return UOT_ERR_ARG;
   try {
     return solve_core(h, Layout{B, nx, ny, pitch, offset}, src, dst, packed, reps);
+  } catch (...) {
+    return UOT_ERR_OOM;
+  }
+}
+
+uot_status uot_step(uot_handle* h, const float* src, const float* dst, const uot_state* in, uot_state* out,
+                    int32_t iters) {
+  if (!h) return UOT_ERR_ARG;
+  const uot_params& p = h->prm;
+  if (p.nx < 1 || p.ny < 1) return UOT_ERR_SHAPE;
+  const int32_t nx = p.nx, ny = p.ny, pitch = p.pitch > 0 ? p.pitch : p.nx;
+  const int64_t off = 0;
+  try {
+    return step_core(h, Layout{1, &nx, &ny, &pitch, &off}, src, dst, in, out, iters);
   } catch (...) {
     return UOT_ERR_OOM;
   }

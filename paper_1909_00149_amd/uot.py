@@ -142,6 +142,18 @@ class Solver:
             raise UOTError(rc, "uot_solve")
         return state, rep.as_dict()
 
+    def step(self, src, dst, state_in, iters, state_out=None):
+        """uot_step: `iters` iterations from state_in into state_out (state_in
+        is only read); returns state_out."""
+        p = self.params
+        if state_out is None:
+            state_out = new_state(p.mode, p.balanced, src.shape, src.device)
+        ci, co = _cstate(state_in), _cstate(state_out)
+        rc = self.lib.uot_step(self._h, _ptr(src), _ptr(dst), ctypes.byref(ci), ctypes.byref(co), int(iters))
+        if rc != 0:
+            raise UOTError(rc, "uot_step")
+        return state_out
+
     def solve_batched(self, src, dst, nx, ny, offset, state=None, pitch=None):
         """uot_solve_batched (uot_solve_batched_pitched when pitch is given) on
         packed 1-D planes; returns (state, [reports])."""
