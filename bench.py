@@ -82,7 +82,7 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "7397b837860edab2cde46d8ad13baceb1d22dae6780a4d1ec41564777e22f127"
+TRAFFIC_SHA256 = "2d3dd8cb604aec6356af102f45752dd02c1fca9ae257c64f202d106315b3e663"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB, VALUBusy %, LdsUtil %,
 #              MeanOccupancyPerCU, SQ_INSTS_VALU, TCC hit rate) per dispatch

@@ -133,7 +133,8 @@ def test_graph_replay_equals_direct_launches(dev, mode, balanced):
         torch.cuda.synchronize()
         out.append((st, reps))
     (a, ra), (b, rb) = out
-    assert len({r["iters"] for r in ra}) > 1
+    if mode == DIST and not balanced:
+        assert len({r["iters"] for r in ra}) > 1  # the pairs stop at different windows
     for k in G.required_planes(mode, balanced):
         assert torch.equal(a[k], b[k]), k
     for x, y in zip(ra, rb):
