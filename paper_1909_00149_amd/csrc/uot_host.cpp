@@ -595,19 +595,25 @@ hipError_t launch_steps(uot_handle* h, int resid, int shape, int steps, int grid
   return launch_iter(p.mode, resid, bcn_of(p), shape, grid_multi, a, h->stream);
 }
 
+// The launches of one window of W iterations.  With a check on a blocked
+// shape the window's last launch is the check variant (fused_schedule);
+// with a check on a one-step shape every launch runs one iteration and the
+// separate check kernel compares the last two; without a check the window
+// is plain launches of up to T iterations.  The number of launches may be
+// odd: the window then ends in the other copy of the state.
+std::vector<int> window_schedule(const Launch& L, int W, bool check) {
+  const int T = shape_steps(L.J->shape);
+  if (check && T > 1) return fused_schedule(W, T, shape_chk_steps(L.J->shape));
+  return step_schedule(W, T, check, false);
+}
+
 // Launches of one window of W iterations starting from copy `parity` (0:
-// the caller's planes, 1: the shadow).  With a check on a blocked shape the
-// window's last launch is the check variant (fused_schedule; the window may
-// end in the other copy); otherwise its last launch runs one iteration and
-// the window has an even number of launches (step_schedule), followed by
-// the separate check kernel when there is a check.
+// the caller's planes, 1: the shadow), then the check when there is one.
 uot_status enqueue_window(Launch& L, int W, bool check, int parity) {
   uot_handle* h = L.h;
   const uot_params& p = h->prm;
-  const int T = shape_steps(L.J->shape);
-  const bool fused = check && T > 1;
-  const std::vector<int> sched =
-      fused ? fused_schedule(W, T, shape_chk_steps(L.J->shape)) : step_schedule(W, T, true, true);
+  const bool fused = check && shape_steps(L.J->shape) > 1;
+  const std::vector<int> sched = window_schedule(L, W, check);
   for (size_t i = 0; i < sched.size(); ++i) {
     IterArgs a = ((i + parity) & 1) ? L.bwd : L.fwd;
     if (fused && i + 1 == sched.size()) {
@@ -626,11 +632,7 @@ uot_status enqueue_window(Launch& L, int W, bool check, int parity) {
 }
 
 // Launches per window (its parity decides which copy a window ends in).
-int window_launches(const Launch& L, int W, bool check) {
-  const int T = shape_steps(L.J->shape);
-  if (check && T > 1) return (int)fused_schedule(W, T, shape_chk_steps(L.J->shape)).size();
-  return (int)step_schedule(W, T, true, true).size();
-}
+int window_launches(const Launch& L, int W, bool check) { return (int)window_schedule(L, W, check).size(); }
 
 uot_status get_graph(Launch& L, int W, bool check, int reps, int parity, hipGraphExec_t* out) {
   uot_handle* h = L.h;

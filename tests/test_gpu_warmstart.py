@@ -1,5 +1,6 @@
 """What the trained warm-start network gains over the method without it, on
 held-out pairs (seeds never used in training), and the fallback path."""
+import json
 import os
 
 import numpy as np
@@ -13,6 +14,15 @@ from paper_1909_00149_amd import warmstart as WS
 pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(WS.__file__), "data", "warmstart_256.npz")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "converged_values.json")
+
+
+def certified_heldout():
+    """Oracle-certified optimal values of held-out pairs: {seed: (dual, primal)}."""
+    with open(GOLDEN) as f:
+        cases = json.load(f)["cases"]
+    return {c["seed"]: (c["dual"], c["primal"]) for c in cases
+            if c["name"].startswith("heldout") and c["side"] == WS.SIDE and c["mu"] == WS.MU}
 
 
 @pytest.fixture(scope="module")
@@ -35,6 +45,22 @@ def test_learned_start_beats_cold_start(dev):
     assert learned["iters_median"] <= 0.8 * cold["iters_median"], res
     # both arms reach the same optimal values (the stopping rule decides)
     assert abs(learned["primal_mean"] - cold["primal_mean"]) <= 1e-3 * cold["primal_mean"], res
+    # and on the pairs whose optimum the FP64 oracle certified, each arm's
+    # certified primal bound lies above the oracle's lower bound and within
+    # 1e-3 relative of the optimum: the learned start converges to the
+    # problem's solution, not merely to a small residual
+    cert = certified_heldout()
+    first = WS.EVAL_SEED0 + 5000
+    assert len(cert) >= 2
+    for seed, (lo, hi) in cert.items():
+        i = seed - first
+        assert 0 <= i < 32
+        vstar = 0.5 * (lo + hi)
+        for arm in (cold, learned):
+            pr = arm["primal"][i]
+            assert pr >= lo * (1 - 1e-5), (seed, pr, lo, hi)
+            assert pr - vstar <= 1e-3 * vstar, (seed, pr, lo, hi)
+        print(seed, "optimum", vstar, "cold", cold["primal"][i], "learned", learned["primal"][i])
 
 
 def test_rejected_start_falls_back_to_cold(dev):
