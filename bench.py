@@ -29,7 +29,8 @@ already resident in HBM.  The printed JSON line carries:
 Workloads (seeded synthetic inputs):
   ragged256 (default) 256 pairs with sides log-uniform in [32, 512] in
             one batched solve, rel_res <= 1e-4 or 20000 iterations per pair
-            (batches are packed with rows padded to 256-byte boundaries)
+            (batches are packed with rows padded to 256-byte boundaries);
+            the tolerance workloads check every 40 iterations (--check-every)
   pair512   one unbalanced 512x512 blob pair, mu = 8, stop at
             rel_res <= 1e-4 or 2000 iterations, adaptive step balance
   balanced64  one balanced 64x64 pair, exactly 500 iterations
@@ -133,19 +134,19 @@ def workload(name):
         return dict(desc="single unbalanced pair 512x512, 20 blobs, Poisson-noised target, mu=8, "
                          "stop at rel_res<=1e-4 or 2000 iterations",
                     pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
-                    adaptive=True)
+                    adaptive=True, check_every=40)
     if name == "pair512p2":
         p, q = synth.unbalanced_pair(0, side=512)
         return dict(desc="single unbalanced pair 512x512, 20 blobs, Poisson-noised target, mu=8, squared "
                          "l2 source term (p=2), stop at rel_res<=1e-4 or 2000 iterations",
                     pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
-                    adaptive=True, residual_p=2)
+                    adaptive=True, residual_p=2, check_every=40)
     if name == "pair512aniso":
         p, q = synth.unbalanced_pair(0, side=512)
         return dict(desc="single unbalanced pair 512x512, 20 blobs, Poisson-noised target, mu=8, anisotropic "
                          "l1,1 flux norm, stop at rel_res<=1e-4 or 2000 iterations",
                     pairs=[(p, q)], mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=2000,
-                    adaptive=True, norm=1)
+                    adaptive=True, norm=1, check_every=40)
     if name == "balanced64":
         p, q = synth.balanced_pair(0)
         return dict(desc="single balanced pair 64x64, 3 blobs, exactly 500 iterations",
@@ -154,16 +155,16 @@ def workload(name):
     if name == "ragged256":
         sides, pairs = synth.ragged_batch(0, batch=256)
         return dict(desc="ragged batch of 256 unbalanced pairs, sides log-uniform 32..512, mu=8, "
-                         "rel_res<=1e-4 or 20000 iterations per pair",
+                         "rel_res<=1e-4 (checked every 40 iterations) or 20000 iterations per pair",
                     pairs=pairs, mode=0, balanced=False, mu=8.0, rho=1.0, tol=1e-4, max_iter=20000,
-                    adaptive=True)
+                    adaptive=True, check_every=40)
     if name == "video63":
         S, _, _ = synth.video_frames(0)
         pairs = [(S[t], S[t + 1]) for t in range(S.shape[0] - 1)]
         return dict(desc="63 frame pairs of a 64-frame 256x256 video, prox mode rho=1 mu=2, "
                          "rel_res<=1e-4 or 2000 iterations",
                     pairs=pairs, mode=1, balanced=False, mu=2.0, rho=1.0, tol=1e-4, max_iter=2000,
-                    adaptive=True)
+                    adaptive=True, check_every=40)
     if name.startswith("sweep"):
         side = int(name[5:])
         p, q = synth.sweep_pair(0, side)
@@ -266,6 +267,8 @@ def main():
     ap.add_argument("--workload", default="ragged256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=400)
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="iterations between convergence checks (default: the workload's)")
     ap.add_argument("--warm-pairs", type=int, default=1000,
                     help="held-out 256x256 pairs for the warm-vs-cold time to 1e-4 (0: skip)")
     ap.add_argument("--prox-iters", default=None,
@@ -327,6 +330,7 @@ def main():
     imgs_p = [torch.from_numpy(np.ascontiguousarray(p)).to(dev) for p, _ in pairs]
     imgs_q = [torch.from_numpy(np.ascontiguousarray(q)).to(dev) for _, q in pairs]
     flags = G.UOT_ADAPTIVE_STEPS if W["adaptive"] else 0
+    check_every = args.check_every or W.get("check_every", 20)
     batched = len(pairs) > 1
     if batched:
         # every row starts on a 256-byte boundary (one 64-pixel tile row), so
@@ -335,14 +339,14 @@ def main():
         src, nx, ny, pitch, offs = G.pack_pitched(imgs_p, align=64)
         dst, _, _, _, _ = G.pack_pitched(imgs_q, align=64)
         prm = G.Params(mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"], tol=W["tol"],
-                       max_iter=W["max_iter"], check_every=20, flags=flags, residual_p=W.get("residual_p", 1),
+                       max_iter=W["max_iter"], check_every=check_every, flags=flags, residual_p=W.get("residual_p", 1),
                        norm=W.get("norm", 0))
         state = G.new_state(W["mode"], W["balanced"], src.numel(), dev)
     else:
         src, dst = imgs_p[0], imgs_q[0]
         ny0, nx0 = src.shape
         prm = G.Params(nx=nx0, ny=ny0, mode=W["mode"], balanced=W["balanced"], mu=W["mu"], rho=W["rho"],
-                       tol=W["tol"], max_iter=W["max_iter"], check_every=20, flags=flags,
+                       tol=W["tol"], max_iter=W["max_iter"], check_every=check_every, flags=flags,
                        residual_p=W.get("residual_p", 1), norm=W.get("norm", 0))
         state = G.new_state(W["mode"], W["balanced"], src.shape, dev)
     solver = G.Solver(prm)
@@ -436,7 +440,7 @@ def main():
         "config": {"workload": args.workload, "description": W["desc"], "pairs": len(pairs),
                    "pixels": int(sum(npx)), "mode": ["DIST", "PROX", "PROX_FIXED"][W["mode"]],
                    "balanced": W["balanced"], "residual_p": W.get("residual_p", 1),
-                   "flux_norm": ["l2,1", "l1,1"][W.get("norm", 0)]},
+                   "flux_norm": ["l2,1", "l1,1"][W.get("norm", 0)], "check_every": check_every},
         "effective_hbm_frac_step": round(value * bpp / (HBM_PEAK_GBS * 1e9), 4),
         "tol": W["tol"], "max_iter": W["max_iter"],
         "iters_quantiles": {q: int(np.percentile(its, pq, method="nearest"))
