@@ -179,8 +179,14 @@ uot_status uot_check_params(const uot_params *prm);
  * number of identity blocks of K.  Host only; returns -1 on bad arguments. */
 double uot_knorm2(int32_t nx, int32_t ny, int32_t mode, int32_t balanced, int32_t bc);
 
-/* Creates a handle bound to hip_stream (a hipStream_t; NULL = default stream)
- * on the current device.  *out is set to NULL on error. */
+/* Creates a handle bound to hip_stream (a hipStream_t; NULL: the handle
+ * creates and owns a stream of its own) on the current device.  *out is set
+ * to NULL on error.  With the environment variable UOT_PROFILE set at this
+ * call, every uot_solve / uot_solve_batched of the handle writes one line
+ * per check window (its GPU time from events, the iterations so far, the
+ * live and stopped pairs) plus a setup and an end line: UOT_PROFILE=1 to
+ * stderr, any other value except 0 appended to the file it names.  The host
+ * then waits for every window, so profiled solves run slower. */
 uot_status uot_create(const uot_params *prm, void *hip_stream, uot_handle **out);
 
 /* One grid of nx x ny (from the params).  src/dst: device images (see the

@@ -4,7 +4,28 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libuot.so")
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libuot.so")
+# digest of the sources libuot.so was built from, written by build.py beside it
+DIGEST_PATH = LIB_PATH + ".sources"
+
+
+def sources_digest():
+    """SHA-256 over the library's sources (csrc/, include/) and build script,
+    in a fixed file order."""
+    import hashlib
+    root = os.path.dirname(_PKG)
+    files = []
+    for d, exts in ((os.path.join(_PKG, "csrc"), (".hip", ".hpp", ".cpp", ".h")),
+                    (os.path.join(root, "include"), (".h",))):
+        files += sorted(os.path.join(d, f) for f in os.listdir(d) if f.endswith(exts))
+    files.append(os.path.join(_PKG, "build.py"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.relpath(f, root).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 UOT_OK, UOT_ERR_ARG, UOT_ERR_SHAPE, UOT_ERR_STEP, UOT_ERR_NONFINITE = 0, 1, 2, 3, 4
 UOT_ERR_NEGATIVE, UOT_ERR_DEVICE, UOT_ERR_OOM, UOT_ERR_MASS, UOT_ERR_TOO_LARGE = 5, 6, 7, 8, 9
@@ -173,6 +194,16 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1909_00149_amd.build`")
+    # the library must have been built from the sources in this tree
+    try:
+        with open(DIGEST_PATH) as f:
+            built = f.read().strip()
+    except OSError:
+        built = None
+    if built != sources_digest():
+        raise RuntimeError(f"{LIB_PATH} was not built from the current sources "
+                           f"({'no ' + DIGEST_PATH if built is None else 'source digest differs'}): "
+                           "rebuild it with `python -m paper_1909_00149_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -65,6 +65,10 @@ def _compile(entry):
 
 
 def build(verbose=False):
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    from paper_1909_00149_amd._lib import DIGEST_PATH, sources_digest
+    digest = sources_digest()  # of the sources as they are when the compile starts
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -74,6 +78,9 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    with open(DIGEST_PATH + ".tmp", "w") as f:
+        f.write(digest + "\n")
+    os.replace(DIGEST_PATH + ".tmp", DIGEST_PATH)
     if verbose:
         print("built", LIB)
     return LIB

@@ -161,8 +161,17 @@ struct uot_handle {
   int32_t* d_mask = nullptr;    // per-pair flags of a masked copy
   size_t cap_mask = 0;
 
+  // UOT_PROFILE: per-window timing lines (stderr, or appended to a file)
+  FILE* prof = nullptr;
+  bool prof_own = false;
+  hipEvent_t pev[2] = {nullptr, nullptr};
+  long prof_solves = 0;
+
   ~uot_handle() {
+    if (prof_own && prof) std::fclose(prof);
     if (borrowed) return;
+    for (auto& e : pev)
+      if (e) (void)hipEventDestroy(e);
     for (auto& row : gexec)
       for (auto& g : row)
         if (g) (void)hipGraphExecDestroy(g);
@@ -232,6 +241,18 @@ uot_status uot_create(const uot_params* prm, void* hip_stream, uot_handle** out)
       return UOT_ERR_DEVICE;
     }
     h->own_stream = true;
+  }
+  // UOT_PROFILE=1: per-window timing on stderr; any other value except 0
+  // names a file the lines are appended to
+  if (const char* pv = std::getenv("UOT_PROFILE")) {
+    if (pv[0] && std::strcmp(pv, "0") != 0) {
+      if (std::strcmp(pv, "1") == 0) {
+        h->prof = stderr;
+      } else {
+        h->prof = std::fopen(pv, "a");
+        h->prof_own = h->prof != nullptr;
+      }
+    }
   }
   *out = h;
   return UOT_OK;
@@ -937,7 +958,18 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   // between polls replays one captured graph (an even number of windows when
   // a window flips the copy, so a burst starts and ends in the same copy); a
   // shorter last burst replays the one-window graphs.
-  int poll = record ? 1 : std::min(32, std::max(1, 256 / W));
+  // UOT_PROFILE: one window per poll, each bracketed by events
+  const bool prof = h->prof != nullptr && !h->borrowed;
+  long solve_no = 0;
+  if (prof) {
+    for (auto& e : h->pev)
+      if (!e) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    solve_no = ++h->prof_solves;
+    std::fprintf(h->prof, "uot_profile solve=%ld setup pairs=%d tiles=%zu shape=%d window=%d check=%d host_ms=%.3f\n",
+                 solve_no, B, J.tiles.size(), J.shape, W, check ? 1 : 0, 1e3 * timer.seconds());
+  }
+  int poll = (record || prof) ? 1 : std::min(32, std::max(1, 256 / W));
   if ((per & 1) && poll > 1) poll += poll & 1;
   hipGraphExec_t gx[2] = {nullptr, nullptr}, gxn = nullptr;
   if (n_active > 0 && nwin > 0 && use_graph) {
@@ -961,6 +993,7 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
   int par = 0;  // copy holding the iterate of the pairs still running
   while (w < nwin && n_active > 0) {
     const int burst = std::min(poll, nwin - w);
+    if (prof) HIPCHK(hipEventRecord(h->pev[0], h->stream));
     if (gxn && burst == poll) {
       HIPCHK(hipGraphLaunch(gxn, h->stream));
       par ^= (burst * per) & 1;
@@ -977,6 +1010,15 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     }
     w += burst;
     done_iters += burst * W;
+    float prof_ms = 0.f;
+    if (prof) {
+      HIPCHK(hipEventRecord(h->pev[1], h->stream));
+      HIPCHK(hipEventSynchronize(h->pev[1]));
+      HIPCHK(hipEventElapsedTime(&prof_ms, h->pev[0], h->pev[1]));
+      if (!check)
+        std::fprintf(h->prof, "uot_profile solve=%ld window=%d iters=%d live_pairs=%d gpu_ms=%.4f\n", solve_no, w,
+                     done_iters, n_active, prof_ms);
+    }
     if (check) {
       if (record) {
         for (int b = 0; b < B; ++b) hprev_active[b] = h_active[b];
@@ -990,6 +1032,9 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
           if (hprev_active[b]) h->hist[b].emplace_back(h->h_i32[B + b], hrel[b]);
       int now = 0;
       for (int b = 0; b < B; ++b) now += h_active[b] ? 1 : 0;
+      if (prof)
+        std::fprintf(h->prof, "uot_profile solve=%ld window=%d iters=%d live_pairs=%d stopped=%d gpu_ms=%.4f\n",
+                     solve_no, w, done_iters, n_active, n_active - now, prof_ms);
       if (now == 0) {
         n_active = 0;
         break;
@@ -1076,6 +1121,11 @@ uot_status solve_core(uot_handle* h, const Layout& lay, const float* src, const 
     if (s != UOT_OK) return s;
   }
   const double secs = timer.seconds();
+  if (prof) {
+    std::fprintf(h->prof, "uot_profile solve=%ld end windows=%d tail=%d host_ms=%.3f\n", solve_no, w,
+                 run_tail ? tail : 0, 1e3 * secs);
+    std::fflush(h->prof);
+  }
   for (int b = 0; b < B; ++b) {
     uot_report& r = reps[b];
     std::memset(&r, 0, sizeof(r));

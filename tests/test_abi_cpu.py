@@ -99,3 +99,14 @@ def test_uotdf_check_params(kw, ok):
 def test_rpca_check_params(kw, ok):
     from paper_1909_00149_amd.admm import Rpca
     assert (Rpca.check(**kw) == 0) == ok
+
+
+def test_library_matches_its_sources(monkeypatch):
+    """The loader refuses a libuot.so whose recorded source digest is not
+    the digest of the sources in the tree (a stale build)."""
+    with open(_lib.DIGEST_PATH) as f:
+        assert f.read().strip() == _lib.sources_digest()
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "sources_digest", lambda: "0" * 64)
+    with pytest.raises(RuntimeError, match="not built from the current sources"):
+        _lib.load()

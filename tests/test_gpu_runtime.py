@@ -140,3 +140,43 @@ def test_graph_replay_equals_direct_launches(dev, mode, balanced):
     for x, y in zip(ra, rb):
         for f in ("iters", "status", "rel_res", "objective"):
             assert x[f] == y[f], f
+
+
+def test_profile_lines(dev, tmp_path, monkeypatch):
+    """UOT_PROFILE=<file>: a handle created with it writes a setup line, one
+    line per check window (iterations so far, live and stopped pairs, the
+    window's GPU time) and an end line per solve; the profiled solve gives
+    bitwise the iterates and reports of an unprofiled one."""
+    shapes = [(30, 40), (64, 64), (9, 130), (100, 33)]
+    pairs = [inputs(sh, 40 + i) for i, sh in enumerate(shapes)]
+    offs, o = [], 0
+    for sh in shapes:
+        offs.append(o)
+        o += sh[0] * sh[1]
+    S = torch.cat([t(pp, dev).reshape(-1) for pp, _ in pairs])
+    D = torch.cat([t(qq, dev).reshape(-1) for _, qq in pairs])
+    nx, ny = [sh[1] for sh in shapes], [sh[0] for sh in shapes]
+    kw = dict(mu=1.2, max_iter=3000, check_every=20, tol=1e-4, flags=G.UOT_ADAPTIVE_STEPS)
+    path = tmp_path / "prof.txt"
+    monkeypatch.setenv("UOT_PROFILE", str(path))
+    prof_solver = G.Solver(G.Params(**kw))
+    monkeypatch.delenv("UOT_PROFILE")
+    a, ra = prof_solver.solve_batched(S, D, nx, ny, offs)
+    b, rb = G.Solver(G.Params(**kw)).solve_batched(S, D, nx, ny, offs)
+    torch.cuda.synchronize()
+    prof_solver.close()
+    for k in G.required_planes(DIST, False):
+        assert torch.equal(a[k], b[k]), k
+    for x, y in zip(ra, rb):
+        assert x["iters"] == y["iters"] and x["status"] == y["status"] and x["rel_res"] == y["rel_res"]
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("uot_profile solve=1 setup pairs=4 ") and "window=20 check=1" in lines[0]
+    assert lines[-1].startswith("uot_profile solve=1 end ")
+    wins = [dict(kv.split("=") for kv in ln.split()[1:] if "=" in kv) for ln in lines[1:-1]]
+    assert wins and all("gpu_ms" in w for w in wins)
+    assert [int(w["iters"]) for w in wins] == [20 * (i + 1) for i in range(len(wins))]
+    assert all(float(w["gpu_ms"]) > 0.0 for w in wins)
+    # every pair that stopped at a check is counted once, in its window
+    stopped_at_checks = sum(int(w["stopped"]) for w in wins)
+    assert stopped_at_checks == sum(r["status_name"] == "CONVERGED" and r["iters"] % 20 == 0 for r in ra)
+    assert int(wins[0]["live_pairs"]) == 4
