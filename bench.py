@@ -83,13 +83,13 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "2d3dd8cb604aec6356af102f45752dd02c1fca9ae257c64f202d106315b3e663"
+TRAFFIC_SHA256 = "fe6abb591f73e31adf7672b930ef79bdc8dc5c98314ad51ac459fc2ccc86a6cf"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB, VALUBusy %, LdsUtil %,
 #              MeanOccupancyPerCU, SQ_INSTS_VALU, TCC hit rate) per dispatch
 COUNTERS = {
-    "ragged256": (4016, 168936.303, 231696.375, 62.74, 53.31, 11.99, 74231688, 0.559),
-    "pair512": (4008, 2913.088, 4096.000, 19.32, 14.22, 3.18, 2106720, 0.670),
+    "ragged256": (4016, 173151.855, 231696.375, 65.37, 47.60, 12.18, 77294607, 0.553),
+    "pair512": (4008, 2923.878, 4096.000, 19.71, 12.24, 3.16, 2101824, 0.673),
 }
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
 # 4 cycles (16 lanes), 2.4 GHz

@@ -368,6 +368,7 @@ uot_status plan(uot_handle* h, const Layout& L, Job& J, int force_ty = 0, bool* 
     if (cached) *cached = it != g_tune_cache.end();
     ty = it != g_tune_cache.end() ? it->second : heuristic_shape(npx);
   }
+  if (ty >= 1000 && !planner::blocked_pitch_ok(B, nx, L.pitch)) ty = shape_single(ty);
   // the vectorised kernels (100 * variant + rows) take any row layout but
   // need every plane 4-byte aligned; otherwise the scalar kernel of the same
   // rows runs

@@ -596,6 +596,30 @@ __device__ __forceinline__ void region_cell(int idx, int& rx, int& ry) {
   rx = j - 2 * SIDE;
 }
 
+// A plane's pixels as seen from a tile: `base` is the plane's address of
+// region cell (0, 0), uniform over the workgroup, formed in integer
+// arithmetic since it may lie before the pair (the region reaches past the
+// grid); cells are read and written at 32-bit byte offsets from it, so the
+// per-cell address arithmetic stays 32-bit.
+struct RegionPlane {
+  using gbyte = __attribute__((address_space(1))) char;  // global memory
+  gbyte* base;
+  __device__ __forceinline__ RegionPlane(const float* p, long rbase)
+      : base((gbyte*)((uintptr_t)p + (uintptr_t)(rbase * (long)sizeof(float)))) {}
+  __device__ __forceinline__ float ld(unsigned bo) const {
+    return *(const __attribute__((address_space(1))) float*)(base + bo);
+  }
+  __device__ __forceinline__ void st(unsigned bo, float v) const {
+    *(__attribute__((address_space(1))) float*)(base + bo) = v;
+  }
+  // a direct load into LDS: lane i of the wave writes lds[i], lds being
+  // the same for the whole wave
+  __device__ __forceinline__ void to_lds(unsigned bo, float* lds) const {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(base + bo),
+                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+  }
+};
+
 // H: the halo, so up to H steps per launch keep the owned tile exact.  CHK:
 // the launch also evaluates the convergence check of the iterate pair of its
 // last step (steps <= H - 1, so that the new iterate is exact one cell
@@ -608,16 +632,21 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   constexpr int NOWN = TX * TH / BLOCK;  // owned cells per thread: the first NOWN
   static_assert(TX * TH % BLOCK == 0, "whole tile rows per thread");
   static_assert(!CHK || H >= 2, "the check needs one exact cell beyond the tile");
-  // LDS rows of RW cells plus a zero border; the slots past the region use
-  // spare rows above the top border (always written zero, read only by
-  // themselves)
+  // LDS: the region's RH rows of RW cells back to back, so that the
+  // region in row-major order is one run of LDS words (cell (rx, ry) at
+  // (ry + 1) RW + rx + 1), between a zero row below and a zero row above;
+  // the slots past the region follow the upper zero row (always zero, read
+  // only by themselves).  A cell at the region's left or right edge reads
+  // the neighbouring row's end as its neighbour: such cells are never
+  // exact, and the owned tile does not depend on them.
   constexpr int PAD = NC * BLOCK - NCELL;
-  constexpr int LW = RW + 2, LH = RH + 3 + (PAD + RW - 1) / RW;
-  constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4;  // per-cell flags
+  constexpr int LW = RW;
+  constexpr int NCHUNK = (NCELL + 63) / 64;  // 64-cell runs of the region, one per direct load
+  constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4, F_PAD = 8;  // per-cell flags
   // a, Mx, My planes of the region; CHK: also the check's reduction buffer,
   // used only between tiles (after the write of one, before the staging of
   // the next)
-  constexpr int PLANE = LH * LW;
+  constexpr int PLANE = (RH + 4) * RW + PAD + 2;
   constexpr int POOL = CHK && NS * BLOCK > (3 * PLANE + 1) / 2 ? NS * BLOCK : (3 * PLANE + 1) / 2;
   __shared__ double pool[POOL];
   float* const sa = reinterpret_cast<float*>(pool);
@@ -634,7 +663,7 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   for (int k = 0; k < NC; ++k) {
     int rx, ry;
     region_cell<TH, H>(tid + k * BLOCK, rx, ry);
-    l_[k] = ry < RH ? (ry + 1) * LW + rx + 1 : (RH + 2 + rx / RW) * LW + rx % RW + 1;
+    l_[k] = ry < RH ? (ry + 1) * RW + rx + 1 : (RH + 2) * RW + 1 + rx;
   }
   // CHK: per-thread check sums over the block's run of tiles of one pair,
   // reduced once per run into the row of its first tile (the run's other
@@ -682,43 +711,83 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     // CHK: the last step's input values of the owned cells
     float ka_[NOWN], kr_[NOWN], ku_[NOWN], kmx_[NOWN], kmy_[NOWN], kro_[NOWN], kx0_[NOWN], kx1_[NOWN];
 
+    // the planes from region cell (0, 0); byte offsets of region cells are
+    // below 4 GiB because the host runs blocked shapes only for pitches
+    // that keep (RH + 1) rows under it
+    const long rbase = off + (long)by * pitch + bx;
+    const RegionPlane pa(A.in.a, rbase), pmx(A.in.Mx, rbase), pmy(A.in.My, rbase), pr(A.in.r, rbase);
+    const RegionPlane pc(MODE == 0 ? A.c : A.src, rbase), pd(A.dst, rbase), px0(A.in.x0, rbase),
+        px1(A.in.x1, rbase);
+
     __syncthreads();  // LDS of the previous tile is no longer read
-    // ---- stage the region: every cell's loads are issued before any is
-    // used, so their latencies overlap; a cell outside the grid loads the
-    // pair's first pixel (always valid) and keeps zero ----
-    float ga_[NC], gmx_[NC], gmy_[NC];
+    // ---- stage the region.  The a, Mx and My planes go to LDS by direct
+    // loads, each wave instruction filling a run of 64 region cells; the
+    // element-wise planes go to registers.  Every load is issued before any
+    // value is used.  A cell outside the grid loads the nearest pixel of
+    // the pair (always valid) and is set to zero afterwards. ----
+    {
+      const int lane = tid & 63;
+      for (int j = tid >> 6; j < NCHUNK; j += BLOCK / 64) {
+        const int f = j * 64 + lane;
+        if (f < NCELL) {
+          const int ry = f / RW, rx = f - ry * RW;
+          const int cx = min(max(bx + rx, 0), nx - 1), cy = min(max(by + ry, 0), ny - 1);
+          const unsigned bo = ((unsigned)(cy - by) * (unsigned)pitch + (unsigned)(cx - bx)) * 4u;
+          const int l0 = RW + 1 + j * 64;  // the run's first LDS word (uniform over the wave)
+          pa.to_lds(bo, sa + l0);
+          pmx.to_lds(bo, smx + l0);
+          pmy.to_lds(bo, smy + l0);
+        }
+      }
+    }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       int rx, ry;
       region_cell<TH, H>(tid + k * BLOCK, rx, ry);
       const int gx = bx + rx, gy = by + ry;
-      const bool in = ry < RH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-      f_[k] = (in ? F_IN : 0) | ((BC & 1) == 0 && gx == nx - 1 ? F_ZX : 0) | ((BC & 1) == 0 && gy == ny - 1 ? F_ZY : 0);
-      const long o = off + (in ? (long)gy * pitch + gx : 0L);
-      ga_[k] = A.in.a[o];
-      gmx_[k] = A.in.Mx[o];
-      gmy_[k] = A.in.My[o];
-      r_[k] = RES != R_BAL ? A.in.r[o] : 0.f;
+      const bool in = ry < RH && (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny;
+      f_[k] = (in ? F_IN : 0) | ((BC & 1) == 0 && gx == nx - 1 ? F_ZX : 0) |
+              ((BC & 1) == 0 && gy == ny - 1 ? F_ZY : 0) | (ry >= RH ? F_PAD : 0);
+      const int cx = min(max(gx, 0), nx - 1), cy = min(max(gy, 0), ny - 1);
+      const unsigned bo = ((unsigned)(cy - by) * (unsigned)pitch + (unsigned)(cx - bx)) * 4u;
+      r_[k] = RES != R_BAL ? pr.ld(bo) : 0.f;
       if (MODE == 0) {
-        c0_[k] = A.c[o];
+        c0_[k] = pc.ld(bo);
         c1_[k] = x0_[k] = x1_[k] = 0.f;
       } else {
-        c0_[k] = A.src[o];
-        c1_[k] = A.dst[o];
-        x0_[k] = MODE == 1 ? A.in.x0[o] : 0.f;
-        x1_[k] = A.in.x1[o];
+        c0_[k] = pc.ld(bo);
+        c1_[k] = pd.ld(bo);
+        x0_[k] = MODE == 1 ? px0.ld(bo) : 0.f;
+        x1_[k] = px1.ld(bo);
       }
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const bool in = f_[k] & F_IN;
-      const int l = l_[k];
-      sa[l] = in ? ga_[k] : 0.f;
-      smx[l] = in && !(f_[k] & F_ZX) ? gmx_[k] : 0.f;
-      smy[l] = in && !(f_[k] & F_ZY) ? gmy_[k] : 0.f;
-      if (!in) r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
+      if (!(f_[k] & F_IN)) r_[k] = c0_[k] = c1_[k] = x0_[k] = x1_[k] = 0.f;
+      if (f_[k] & F_PAD) {  // slots past the region: no direct load writes them
+        const int l = l_[k];
+        sa[l] = smx[l] = smy[l] = 0.f;
+      }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have reached LDS
     __syncthreads();
+    // a region reaching past the grid or holding zero-flux cells: the cells
+    // outside the grid are zero, and so is the flux through those edges
+    const bool interior = bx >= 0 && by >= 0 && bx + RW <= nx - 1 && by + RH <= ny - 1;
+    if (!interior) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int l = l_[k];
+        const int fl = f_[k];
+        if (!(fl & F_IN)) {
+          sa[l] = smx[l] = smy[l] = 0.f;
+        } else {
+          if (fl & F_ZX) smx[l] = 0.f;
+          if (fl & F_ZY) smy[l] = 0.f;
+        }
+      }
+      __syncthreads();
+    }
 
     // ---- K(z^k) of every cell ----
 #pragma unroll
@@ -838,7 +907,7 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     // check variant always masks (a second copy of its steps would cost it
     // registers and occupancy)
     if constexpr (!CHK) {
-      if (bx >= 0 && by >= 0 && bx + RW <= nx - 1 && by + RH <= ny - 1) run(std::false_type{});
+      if (interior) run(std::false_type{});
       else run(std::true_type{});
     } else {
       run(std::true_type{});
@@ -914,18 +983,20 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     }
 
     // ---- write the owned tile ----
+    const RegionPlane qa(A.out.a, rbase), qmx(A.out.Mx, rbase), qmy(A.out.My, rbase), qr(A.out.r, rbase),
+        qx0(A.out.x0, rbase), qx1(A.out.x1, rbase);
 #pragma unroll
     for (int k = 0; k < NOWN; ++k) {
       if (!(f_[k] & F_IN)) continue;
       const int l = l_[k];
       const int idx = tid + k * BLOCK;  // an owned cell: row idx / 64 of the tile
-      const long o = off + (long)(tl.y0 + idx / TX) * pitch + (tl.x0 + idx % TX);
-      A.out.Mx[o] = smx[l];
-      A.out.My[o] = smy[l];
-      A.out.a[o] = sa[l];
-      if (RES != R_BAL) A.out.r[o] = r_[k];
-      if (MODE == 1) A.out.x0[o] = x0_[k];
-      if (MODE != 0) A.out.x1[o] = x1_[k];
+      const unsigned bo = ((unsigned)(H + idx / TX) * (unsigned)pitch + (unsigned)(H + idx % TX)) * 4u;
+      qmx.st(bo, smx[l]);
+      qmy.st(bo, smy[l]);
+      qa.st(bo, sa[l]);
+      if (RES != R_BAL) qr.st(bo, r_[k]);
+      if (MODE == 1) qx0.st(bo, x0_[k]);
+      if (MODE != 0) qx1.st(bo, x1_[k]);
     }
   }
   if (CHK && run_pair >= 0) {

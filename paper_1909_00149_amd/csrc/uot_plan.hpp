@@ -82,6 +82,17 @@ inline int shape_single(int code) {
   const int rows = code % 1000;
   return rows % 16 == 0 ? 100 + rows : rows;
 }
+// The blocked kernels address a tile's region by 32-bit byte offsets from
+// its first cell, which hold (region rows + 1) x pitch pixels for every
+// blocked shape (at most 49 rows) while the pitch is at most 2^24; wider
+// rows run the single-step kernel of the same rows.
+constexpr long kBlockedMaxPitch = 1L << 24;
+inline bool blocked_pitch_ok(int B, const int32_t* nx, const int32_t* pitch) {
+  for (int b = 0; b < B; ++b)
+    if ((long)(pitch ? pitch[b] : nx[b]) > kBlockedMaxPitch) return false;
+  return true;
+}
+
 // Steps of the check variant of a blocked shape (the window's last launch,
 // halo one more than that): 4 for the 4- and 8-step shapes of 4 to 16
 // rows, 2 for 2016 and the 32-row shapes (fewer registers).

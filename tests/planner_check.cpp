@@ -181,6 +181,18 @@ int main() {
     EXPECT(shape_chk_steps(code) <= shape_steps(code) || shape_steps(code) == 1, "check steps %d", code);
   }
   EXPECT(group_cap_of(0) == LONG_MAX && group_cap_of(1) == 8 && group_cap_of(17) == 16, "group cap");
+  // 32-bit byte offsets of a blocked kernel's region: (region rows + 1)
+  // rows of the widest pitch allowed, for the plain and the check variant
+  for (int code : {4004, 4008, 2016, 4016, 8016, 4032, 8032}) {
+    const long H = std::max(shape_steps(code), shape_chk_steps(code) + 1);
+    const long rows = shape_rows(code) + 2 * H + 1;
+    EXPECT((rows * kBlockedMaxPitch + 64 + 2 * H) * 4 < (1L << 32), "region offsets of %d", code);
+  }
+  {
+    const int32_t w[2] = {300, (int32_t)kBlockedMaxPitch}, w2[2] = {300, (int32_t)kBlockedMaxPitch + 1};
+    EXPECT(blocked_pitch_ok(2, w, nullptr) && !blocked_pitch_ok(2, w2, nullptr) && blocked_pitch_ok(2, w2, w),
+           "blocked pitch");
+  }
   // ---- batch layouts ----
   {
     std::mt19937 rng(3);
