@@ -162,3 +162,19 @@ def test_pitched_timing_matches_solve(dev):
     assert ran == 316 and ms > 0
     for k in ref:
         assert torch.equal(ref[k], st[k]), k
+
+
+def test_wide_pitch_runs_the_single_step_kernel(dev):
+    """Row pitches above 2^24 pixels: the blocked kernels address a region
+    by 32-bit byte offsets, so the solver runs the single-step kernel of the
+    same rows instead, and the iterates equal those of the blocked kernel on
+    the packed layout bit for bit."""
+    pairs = pairs_of([(3, 100), (2, 70)], 300)
+    wide = (1 << 24) + 64
+    st, reps = solve_layout(dev, pairs, lambda a: wide, DIST, False, 4016, 30)
+    ref, rr = solve_layout(dev, pairs, lambda a: a, DIST, False, 4016, 30)
+    assert all(r["tile_rows"] < 1000 for r in reps), [r["tile_rows"] for r in reps]
+    assert all(r["tile_rows"] == 4016 for r in rr)
+    for a, b in zip(st, ref):
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
