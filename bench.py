@@ -754,7 +754,7 @@ def warm_vs_cold(dev, n):
     pairs = [WS._pair(s) for s in range(WS.EVAL_SEED0, WS.EVAL_SEED0 + n)]
     src = np.stack([p for p, _ in pairs])
     dst = np.stack([q for _, q in pairs])
-    net = WS.load_net(path, dev, batch_max=16)
+    net = WS.load_net(path, dev, batch_max=64)  # inference in chunks of 64 pairs
     res = WS.evaluate(net, src, dst, dev, arms=("cold", "learned"), repeats=3)
     c, l = res["cold"], res["learned"]
     cp, lp = np.array(c["primal"]), np.array(l["primal"])

@@ -230,6 +230,28 @@ __global__ void pool2_kernel(const uint16_t* x, int N, int H, int W, int C, uint
   }
 }
 
+// The same, 8 channels (16 bytes) per thread with 32-bit pixel indices
+// (C a multiple of 8, 16-byte aligned tensors, N H W < 2^31): the same sum
+// per element in the same order.
+__global__ void pool2_v8_kernel(const uint16_t* x, int N, int H, int W, int C, uint16_t* y) {
+  const int Ho = H / 2, Wo = W / 2, G = C / 8;
+  const long n = (long)N * Ho * Wo * G;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const unsigned q = (unsigned)(e / G);  // output pixel
+    const int c = (int)(e - (long)q * G) * 8;
+    const unsigned xo = q % Wo, r = q / Wo, yo = r % Ho, b = r / Ho;
+    const long base = ((long)(b * H + 2 * yo) * W + 2 * xo) * C + c;
+    const u16x8 v0 = *reinterpret_cast<const u16x8*>(x + base);
+    const u16x8 v1 = *reinterpret_cast<const u16x8*>(x + base + C);
+    const u16x8 v2 = *reinterpret_cast<const u16x8*>(x + base + (long)W * C);
+    const u16x8 v3 = *reinterpret_cast<const u16x8*>(x + base + (long)W * C + C);
+    u16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = f2bf(0.25f * (bf2f(v0[i]) + bf2f(v1[i]) + bf2f(v2[i]) + bf2f(v3[i])));
+    *reinterpret_cast<u16x8*>(y + (long)q * C + c) = o;
+  }
+}
+
 // Gradient through the pooling, masked by the ReLU of the pooled tensor,
 // plus an optional (already masked) skip gradient.
 __global__ void pool2_bwd_kernel(const uint16_t* gy, const uint16_t* mask, const uint16_t* add, int N, int H, int W,
@@ -262,6 +284,22 @@ __global__ void up_concat_kernel(const uint16_t* d, const uint16_t* e, int N, in
     const int y = (int)((p / W) % H);
     const long b = p / ((long)W * H);
     cat[i] = c < Cu ? d[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + c] : e[p * Cs + (c - Cu)];
+  }
+}
+
+// The same, 8 channels (16 bytes) per thread with 32-bit pixel indices (Cu
+// and Cs multiples of 8, 16-byte aligned tensors, N H W < 2^31).
+__global__ void up_concat_v8_kernel(const uint16_t* d, const uint16_t* e, int N, int H, int W, int Cu, int Cs,
+                                    uint16_t* cat) {
+  const int C = Cu + Cs, G = C / 8;
+  const long n = (long)N * H * W * G;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const unsigned p = (unsigned)(i / G);  // output pixel
+    const int c = (int)(i - (long)p * G) * 8;
+    const unsigned x = p % W, r = p / W, y = r % H, b = r / H;
+    const uint16_t* src = c < Cu ? d + ((long)(b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + c
+                                 : e + (long)p * Cs + (c - Cu);
+    *reinterpret_cast<u16x8*>(cat + (long)p * C + c) = *reinterpret_cast<const u16x8*>(src);
   }
 }
 
@@ -412,8 +450,13 @@ hipError_t pack_input(const float* src, const float* dst, float scale, long P, i
   return hipGetLastError();
 }
 
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 hipError_t pool2(const uint16_t* x, int N, int H, int W, int C, uint16_t* y, hipStream_t s) {
-  hipLaunchKernelGGL(pool2_kernel, dim3(egrid((long)N * H * W * C / 4)), dim3(256), 0, s, x, N, H, W, C, y);
+  if (C % 8 == 0 && aligned16(x) && aligned16(y) && (long)N * H * W < (1L << 31))
+    hipLaunchKernelGGL(pool2_v8_kernel, dim3(egrid((long)N * H * W * C / 32)), dim3(256), 0, s, x, N, H, W, C, y);
+  else
+    hipLaunchKernelGGL(pool2_kernel, dim3(egrid((long)N * H * W * C / 4)), dim3(256), 0, s, x, N, H, W, C, y);
   return hipGetLastError();
 }
 
@@ -425,8 +468,12 @@ hipError_t pool2_bwd(const uint16_t* gy, const uint16_t* mask, const uint16_t* a
 
 hipError_t up_concat(const uint16_t* d, const uint16_t* e, int N, int H, int W, int Cu, int Cs, uint16_t* cat,
                      hipStream_t s) {
-  hipLaunchKernelGGL(up_concat_kernel, dim3(egrid((long)N * H * W * (Cu + Cs))), dim3(256), 0, s, d, e, N, H, W, Cu,
-                     Cs, cat);
+  if (Cu % 8 == 0 && Cs % 8 == 0 && aligned16(d) && aligned16(e) && aligned16(cat) && (long)N * H * W < (1L << 31))
+    hipLaunchKernelGGL(up_concat_v8_kernel, dim3(egrid((long)N * H * W * (Cu + Cs) / 8)), dim3(256), 0, s, d, e, N, H,
+                       W, Cu, Cs, cat);
+  else
+    hipLaunchKernelGGL(up_concat_kernel, dim3(egrid((long)N * H * W * (Cu + Cs))), dim3(256), 0, s, d, e, N, H, W, Cu,
+                       Cs, cat);
   return hipGetLastError();
 }
 
