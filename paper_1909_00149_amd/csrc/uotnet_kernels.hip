@@ -9,9 +9,10 @@
 // ([Cin][9][Cout], tap 8 - t).  The weight gradient is a product over
 // pixels: M = Cout, N = 9 * Cin, K = pixels, split over pixel ranges.
 //
-// One 256-thread workgroup computes a 64 x 64 output tile; each of its four
-// wavefronts owns a 32 x 32 quarter as 2 x 2 blocks of the 16x16x32 BF16
-// MFMA.  Operand tiles are staged in LDS with k contiguous (rows padded to
+// One 256-thread workgroup computes an output tile: 128 pixels x 64 (or
+// 32) channels for the convolution (convw_kernel), 64 x 64 for the weight
+// gradient, whose four wavefronts own 32 x 32 quarters as 2 x 2 blocks of
+// the 16x16x32 BF16 MFMA.  Operand tiles are staged in LDS with k contiguous (rows padded to
 // 40 elements so the 16-byte fragment reads of the 16 rows land in distinct
 // banks).  Lane l of a wavefront reads A row l%16 and B column l%16, k
 // elements 8*(l/16)..+7; it receives D rows 4*(l/16)+i, column l%16.
@@ -52,59 +53,91 @@ __device__ __forceinline__ void mma_tile(const uint16_t (*As)[LDK], const uint16
 // y = conv(x) (+ bias) (relu); optional mask multiplies the result by
 // (mask > 0) (the ReLU derivative of the layer that produced the input of
 // the forward conv, when this launch computes an input gradient).
-__global__ __launch_bounds__(256) void conv_kernel(ConvArgs A) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];
-  const int tid = threadIdx.x;
+// A workgroup computes 64 MI pixels x 16 NB output channels: each
+// wavefront owns 16 MI pixels x all NB blocks of 16 channels, so a k chunk
+// of 32 is MI NB MFMAs per wavefront, and the next chunk's operands are
+// loaded into registers while the current one multiplies.  For every output
+// element the MFMAs take the k chunks in increasing order.
+template <int MI, int NB>
+__global__ __launch_bounds__(256) void convw_kernel(ConvArgs A) {
+  constexpr int BMm = 64 * MI, BNn = 16 * NB;
+  __shared__ __attribute__((aligned(16))) uint16_t As[BMm][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BNn][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const long M = (long)A.N * A.H * A.W;
   const int K = 9 * A.Cin;
-  const long m0 = (long)blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
-  f32x4 acc[2][2];
+  const long m0 = (long)blockIdx.y * BMm;
+  const int n0 = blockIdx.x * BNn;
+  f32x4 acc[MI][NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // this thread's A row (pixel) and B row (output channel)
+    for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // this thread's A rows (pixels row + 64 h, h < MI) and, for the threads
+  // with row < 16 NB, its B row (output channel)
   const int row = tid >> 2, kc = (tid & 3) * 8;
-  const long m = m0 + row;
-  int py = 0, px = 0;
-  long pn = 0;
-  if (m < M) {
-    pn = m / ((long)A.H * A.W);
-    const long rem = m - pn * A.H * A.W;
-    py = (int)(rem / A.W);
-    px = (int)(rem - (long)py * A.W);
+  long pn[MI];
+  int py[MI], px[MI];
+  bool mv[MI];
+#pragma unroll
+  for (int h = 0; h < MI; ++h) {
+    const long m = m0 + row + 64 * h;
+    mv[h] = m < M;
+    pn[h] = 0;
+    py[h] = px[h] = 0;
+    if (mv[h]) {
+      pn[h] = m / ((long)A.H * A.W);
+      const long rem = m - pn[h] * A.H * A.W;
+      py[h] = (int)(rem / A.W);
+      px[h] = (int)(rem - (long)py[h] * A.W);
+    }
   }
   const int co = n0 + row;
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  const bool brow = row < BNn && co < A.Cout;
+  u16x8 va[MI], vb;
+  auto load = [&](int k0) {
     const int k = k0 + kc;
-    u16x8 va = {0, 0, 0, 0, 0, 0, 0, 0}, vb = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (m < M && k < K) {
-      const int tap = k / A.Cin, ci = k - tap * A.Cin;
-      const int iy = py + tap / 3 - 1, ix = px + tap % 3 - 1;
-      if (iy >= 0 && iy < A.H && ix >= 0 && ix < A.W)
-        va = *reinterpret_cast<const u16x8*>(A.X + (((pn * A.H + iy) * A.W + ix) * A.Cin + ci));
+    const bool kin = k < K;
+    const int tap = kin ? k / A.Cin : 0, ci = k - tap * A.Cin;
+#pragma unroll
+    for (int h = 0; h < MI; ++h) {
+      va[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      const int iy = py[h] + tap / 3 - 1, ix = px[h] + tap % 3 - 1;
+      if (mv[h] && kin && iy >= 0 && iy < A.H && ix >= 0 && ix < A.W)
+        va[h] = *reinterpret_cast<const u16x8*>(A.X + (((pn[h] * A.H + iy) * A.W + ix) * A.Cin + ci));
     }
-    if (co < A.Cout && k < K) vb = *reinterpret_cast<const u16x8*>(A.Wt + ((long)co * K + k));
-    *reinterpret_cast<u16x8*>(&As[row][kc]) = va;
-    *reinterpret_cast<u16x8*>(&Bs[row][kc]) = vb;
+    vb = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (brow && kin) vb = *reinterpret_cast<const u16x8*>(A.Wt + ((long)co * K + k));
+  };
+  load(0);
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int h = 0; h < MI; ++h) *reinterpret_cast<u16x8*>(&As[row + 64 * h][kc]) = va[h];
+    if (row < BNn) *reinterpret_cast<u16x8*>(&Bs[row][kc]) = vb;
     __syncthreads();
-    mma_tile(As, Bs, acc);
+    if (k0 + BK < K) load(k0 + BK);  // in flight during the MFMAs
+    bf16x8 a[MI], b[NB];
+#pragma unroll
+    for (int t = 0; t < MI; ++t) a[t] = *reinterpret_cast<const bf16x8*>(&As[wv * 16 * MI + t * 16 + r][kq]);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) b[t] = *reinterpret_cast<const bf16x8*>(&Bs[t * 16 + r][kq]);
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
-  const int lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + j * 16 + (lane & 15);
       if (n >= A.Cout) continue;
       const float bias = A.bias ? A.bias[n] : 0.f;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const long mm = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + e;
+        const long mm = m0 + wv * 16 * MI + i * 16 + (lane >> 4) * 4 + e;
         if (mm >= M) continue;
         float v = acc[i][j][e] + bias;
         if (A.relu) v = fmaxf(v, 0.f);
@@ -424,8 +457,13 @@ static int egrid(long n) { return (int)(n / 256 + 1 < 8192 ? n / 256 + 1 : 8192)
 
 hipError_t conv(const ConvArgs& a, hipStream_t s) {
   const long M = (long)a.N * a.H * a.W;
-  const dim3 grid((a.Cout + BN - 1) / BN, (unsigned)((M + BM - 1) / BM));
-  hipLaunchKernelGGL(conv_kernel, grid, dim3(256), 0, s, a);
+  // 128-pixel tiles (MI = 2; 64- and 256-pixel tiles were slower); 32
+  // channels per tile when the layer has no more
+  const unsigned gy = (unsigned)((M + 127) / 128);
+  if (a.Cout <= 32)
+    hipLaunchKernelGGL((convw_kernel<2, 2>), dim3((a.Cout + 31) / 32, gy), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((convw_kernel<2, 4>), dim3((a.Cout + 63) / 64, gy), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
