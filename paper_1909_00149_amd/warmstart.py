@@ -1,6 +1,6 @@
 """Learned warm start: solver-generated training data, training, evaluation.
 
-    python -m paper_1909_00149_amd.warmstart --train 20000 --eval 1000 --epochs 4 \
+    python -m paper_1909_00149_amd.warmstart --train 20000 --eval 1000 --epochs 20 \
         --out paper_1909_00149_amd/data/warmstart_256.npz
 
 Pairs follow the 256x256 unbalanced blob recipe (centres at least 24 px
@@ -201,7 +201,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--eval", type=int, default=1000)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--target-iters", type=int, default=40000)
