@@ -180,3 +180,24 @@ def test_profile_lines(dev, tmp_path, monkeypatch):
     stopped_at_checks = sum(int(w["stopped"]) for w in wins)
     assert stopped_at_checks == sum(r["status_name"] == "CONVERGED" and r["iters"] % 20 == 0 for r in ra)
     assert int(wins[0]["live_pairs"]) == 4
+
+
+def test_profile_lines_fixed_iterations(dev, tmp_path, monkeypatch):
+    """Without a stopping rule the profile has one line per window of plain
+    launches (no stopped count) and the end line names the tail that ends
+    the solve in a one-iteration launch."""
+    p, q = inputs((40, 90), 77)
+    path = tmp_path / "prof_fixed.txt"
+    monkeypatch.setenv("UOT_PROFILE", str(path))
+    s = G.Solver(G.Params(nx=90, ny=40, mu=1.2, max_iter=100, check_every=20, tol=0.0))
+    monkeypatch.delenv("UOT_PROFILE")
+    st, rep = s.solve(t(p, dev), t(q, dev))
+    torch.cuda.synchronize()
+    s.close()
+    assert rep["iters"] == 100
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("uot_profile solve=1 setup pairs=1 ") and "check=0" in lines[0]
+    wins = lines[1:-1]
+    assert len(wins) == 4 and all("stopped=" not in w and "live_pairs=1" in w for w in wins)
+    assert [int(w.split("iters=")[1].split()[0]) for w in wins] == [20, 40, 60, 80]
+    assert lines[-1].startswith("uot_profile solve=1 end windows=4 tail=20 ")
