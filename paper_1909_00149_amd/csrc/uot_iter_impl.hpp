@@ -44,9 +44,12 @@ __device__ __forceinline__ void flux_shrink(float vx, float vy, float tau1, floa
     oy = shrink1f(vy, tau1);
   } else {
     // max(1 - tau1 / ||v||, 0) v; at v = 0 the reciprocal square root is
-    // +inf and the factor is 0
+    // +inf and the factor is 0.  The hardware reciprocal square root
+    // without the rescaling of subnormal arguments: it gives the same bits
+    // for every normal ||v||^2, and for a subnormal one (||v|| < 1.1e-19,
+    // far below any step tau1) the factor is 0 either way.
     const float n2 = vx * vx + vy * vy;
-    const float s = fmaxf(1.f - tau1 * rsqrtf(n2), 0.f);
+    const float s = fmaxf(1.f - tau1 * __builtin_amdgcn_rsqf(n2), 0.f);
     ox = s * vx;
     oy = s * vy;
   }
