@@ -83,13 +83,13 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "fe6abb591f73e31adf7672b930ef79bdc8dc5c98314ad51ac459fc2ccc86a6cf"
+TRAFFIC_SHA256 = "6afeb883b3f8820ae923ab66ac692ead83659464c356277c84bda979a1bb0e20"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB, VALUBusy %, LdsUtil %,
 #              MeanOccupancyPerCU, SQ_INSTS_VALU, TCC hit rate) per dispatch
 COUNTERS = {
-    "ragged256": (4016, 173151.855, 231696.375, 65.37, 47.60, 12.18, 77294607, 0.553),
-    "pair512": (4008, 2923.878, 4096.000, 19.71, 12.24, 3.16, 2101824, 0.673),
+    "ragged256": (4016, 174567.733, 231696.375, 59.35, 49.68, 12.17, 67001115, 0.552),
+    "pair512": (4008, 2921.378, 4096.000, 18.14, 12.46, 3.21, 1897024, 0.674),
 }
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
 # 4 cycles (16 lanes), 2.4 GHz
