@@ -43,7 +43,7 @@ S_FLUX = NPX / 8.0
 S_DUAL = 1.0 / MU
 CH = (32, 64, 128, 128)
 EVAL_SEED0 = 1_000_000
-PROBE = 20  # iterations of the first check window, where the learned start is judged
+PROBE = 20  # iterations of the first check window, where the learned start is compared with the cold one
 
 
 def _pair(seed):
