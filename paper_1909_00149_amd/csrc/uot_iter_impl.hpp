@@ -633,6 +633,11 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   constexpr int RW = TX + 2 * H, RH = TH + 2 * H, NCELL = RW * RH;
   constexpr int NC = (NCELL + BLOCK - 1) / BLOCK;
   constexpr int NOWN = TX * TH / BLOCK;  // owned cells per thread: the first NOWN
+  // PERCELL: each phase of a step reads, computes and writes one cell at a
+  // time (fewer live registers, so more workgroups per CU); with 4-row
+  // tiles every cell's inputs are read first (more loads in flight for the
+  // few cells per thread).  The arithmetic is the same either way.
+  constexpr bool PERCELL = TH >= 8;
   static_assert(TX * TH % BLOCK == 0, "whole tile rows per thread");
   static_assert(!CHK || H >= 2, "the check needs one exact cell beyond the tile");
   // LDS: the region's RH rows of RW cells back to back, so that the
@@ -815,84 +820,151 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     auto one_step = [&](auto keep_tag, auto mask_tag) {
       constexpr bool KEEPSTEP = decltype(keep_tag)::value;
       constexpr bool MASK = decltype(mask_tag)::value;
-      // ---- new flux: read every cell's inputs, then compute and write ----
-      float ac_[NC], ar_[NC], au_[NC], mx_[NC], my_[NC];
+      if constexpr (PERCELL) {
+        // ---- new flux.  A cell reads the dual at itself and its right and
+        // upper neighbours and its own flux, and writes only its own flux,
+        // which no other cell reads in this phase: each cell is read,
+        // computed and written in turn ----
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int l = l_[k];
-        ac_[k] = sa[l];
-        ar_[k] = sa[l + 1];
-        au_[k] = sa[l + LW];
-        mx_[k] = smx[l];
-        my_[k] = smy[l];
-      }
-      if (KEEPSTEP) {
-#pragma unroll
-        for (int k = 0; k < NOWN; ++k) {
-          ka_[k] = ac_[k];
-          kr_[k] = ar_[k];
-          ku_[k] = au_[k];
-          kmx_[k] = mx_[k];
-          kmy_[k] = my_[k];
-          kro_[k] = r_[k];
-          kx0_[k] = x0_[k];
-          kx1_[k] = x1_[k];
+        for (int k = 0; k < NC; ++k) {
+          const int l = l_[k];
+          const float ac = sa[l], ar = sa[l + 1], au = sa[l + LW], mx = smx[l], my = smy[l];
+          if (KEEPSTEP && k < NOWN) {
+            ka_[k] = ac;
+            kr_[k] = ar;
+            ku_[k] = au;
+            kmx_[k] = mx;
+            kmy_[k] = my;
+            kro_[k] = r_[k];
+            kx0_[k] = x0_[k];
+            kx1_[k] = x1_[k];
+          }
+          float gxx = ac - ar;
+          float gyy = ac - au;
+          if ((BC & 1) == 0 && MASK) {
+            if (f_[k] & F_ZX) gxx = 0.f;
+            if (f_[k] & F_ZY) gyy = 0.f;
+          }
+          const float vx = mx - tau1 * gxx;
+          const float vy = my - tau1 * gyy;
+          float ox, oy;
+          flux_shrink<BC>(vx, vy, tau1, ox, oy);
+          const bool in = !MASK || (f_[k] & F_IN);
+          smx[l] = in ? ox : 0.f;
+          smy[l] = in ? oy : 0.f;
         }
-      }
+        __syncthreads();
+        // ---- element-wise steps and the dual update.  A cell reads the new
+        // flux at itself and its left and lower neighbours and its own dual,
+        // and writes only its own dual ----
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        float gxx = ac_[k] - ar_[k];
-        float gyy = ac_[k] - au_[k];
-        if ((BC & 1) == 0 && MASK) {
-          if (f_[k] & F_ZX) gxx = 0.f;
-          if (f_[k] & F_ZY) gyy = 0.f;
+        for (int k = 0; k < NC; ++k) {
+          const int l = l_[k];
+          const float dmn = smx[l] - smx[l - 1] + smy[l] - smy[l - LW];
+          const float a = sa[l];
+          float knew, x0n = 0.f, x1n = 0.f, rn = 0.f;
+          if (RES == R_P1) rn = shrink1f(r_[k] + tau1 * a, P.mutau);
+          if (RES == R_P2) rn = (r_[k] + tau1 * a) * P.inv2mt;
+          if (MODE == 0) {
+            knew = dmn + c0_[k];
+          } else if (MODE == 1) {
+            const float th = P.theta;
+            x0n = fmaxf(th * c0_[k] + (1.f - th) * (x0_[k] + tau1 * a), 0.f);
+            x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
+            knew = dmn - x0n + x1n;
+          } else {
+            const float th = P.theta;
+            x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
+            knew = dmn - c0_[k] + x1n;
+          }
+          if (RES != R_BAL) knew -= rn;
+          const bool in = !MASK || (f_[k] & F_IN);
+          sa[l] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
+          kp_[k] = knew;
+          r_[k] = rn;
+          x0_[k] = x0n;
+          x1_[k] = x1n;
         }
-        const float vx = mx_[k] - tau1 * gxx;
-        const float vy = my_[k] - tau1 * gyy;
-        float ox, oy;
-        flux_shrink<BC>(vx, vy, tau1, ox, oy);
-        const bool in = !MASK || (f_[k] & F_IN);
-        smx[l_[k]] = in ? ox : 0.f;
-        smy[l_[k]] = in ? oy : 0.f;
-      }
-      __syncthreads();
-      // ---- element-wise steps and the dual update ----
-      float nc_[NC], nl_[NC], yc_[NC], yd_[NC], a_[NC];
+      } else {
+        // ---- new flux: read every cell's inputs, then compute and write ----
+        float ac_[NC], ar_[NC], au_[NC], mx_[NC], my_[NC];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int l = l_[k];
-        nc_[k] = smx[l];
-        nl_[k] = smx[l - 1];
-        yc_[k] = smy[l];
-        yd_[k] = smy[l - LW];
-        a_[k] = sa[l];
-      }
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const float dmn = nc_[k] - nl_[k] + yc_[k] - yd_[k];
-        const float a = a_[k];
-        float knew, x0n = 0.f, x1n = 0.f, rn = 0.f;
-        if (RES == R_P1) rn = shrink1f(r_[k] + tau1 * a, P.mutau);
-        if (RES == R_P2) rn = (r_[k] + tau1 * a) * P.inv2mt;
-        if (MODE == 0) {
-          knew = dmn + c0_[k];
-        } else if (MODE == 1) {
-          const float th = P.theta;
-          x0n = fmaxf(th * c0_[k] + (1.f - th) * (x0_[k] + tau1 * a), 0.f);
-          x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
-          knew = dmn - x0n + x1n;
-        } else {
-          const float th = P.theta;
-          x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
-          knew = dmn - c0_[k] + x1n;
+        for (int k = 0; k < NC; ++k) {
+          const int l = l_[k];
+          ac_[k] = sa[l];
+          ar_[k] = sa[l + 1];
+          au_[k] = sa[l + LW];
+          mx_[k] = smx[l];
+          my_[k] = smy[l];
         }
-        if (RES != R_BAL) knew -= rn;
-        const bool in = !MASK || (f_[k] & F_IN);
-        sa[l_[k]] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
-        kp_[k] = knew;
-        r_[k] = rn;
-        x0_[k] = x0n;
-        x1_[k] = x1n;
+        if (KEEPSTEP) {
+#pragma unroll
+          for (int k = 0; k < NOWN; ++k) {
+            ka_[k] = ac_[k];
+            kr_[k] = ar_[k];
+            ku_[k] = au_[k];
+            kmx_[k] = mx_[k];
+            kmy_[k] = my_[k];
+            kro_[k] = r_[k];
+            kx0_[k] = x0_[k];
+            kx1_[k] = x1_[k];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          float gxx = ac_[k] - ar_[k];
+          float gyy = ac_[k] - au_[k];
+          if ((BC & 1) == 0 && MASK) {
+            if (f_[k] & F_ZX) gxx = 0.f;
+            if (f_[k] & F_ZY) gyy = 0.f;
+          }
+          const float vx = mx_[k] - tau1 * gxx;
+          const float vy = my_[k] - tau1 * gyy;
+          float ox, oy;
+          flux_shrink<BC>(vx, vy, tau1, ox, oy);
+          const bool in = !MASK || (f_[k] & F_IN);
+          smx[l_[k]] = in ? ox : 0.f;
+          smy[l_[k]] = in ? oy : 0.f;
+        }
+        __syncthreads();
+        // ---- element-wise steps and the dual update ----
+        float nc_[NC], nl_[NC], yc_[NC], yd_[NC], a_[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const int l = l_[k];
+          nc_[k] = smx[l];
+          nl_[k] = smx[l - 1];
+          yc_[k] = smy[l];
+          yd_[k] = smy[l - LW];
+          a_[k] = sa[l];
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const float dmn = nc_[k] - nl_[k] + yc_[k] - yd_[k];
+          const float a = a_[k];
+          float knew, x0n = 0.f, x1n = 0.f, rn = 0.f;
+          if (RES == R_P1) rn = shrink1f(r_[k] + tau1 * a, P.mutau);
+          if (RES == R_P2) rn = (r_[k] + tau1 * a) * P.inv2mt;
+          if (MODE == 0) {
+            knew = dmn + c0_[k];
+          } else if (MODE == 1) {
+            const float th = P.theta;
+            x0n = fmaxf(th * c0_[k] + (1.f - th) * (x0_[k] + tau1 * a), 0.f);
+            x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
+            knew = dmn - x0n + x1n;
+          } else {
+            const float th = P.theta;
+            x1n = fmaxf(th * c1_[k] + (1.f - th) * (x1_[k] - tau1 * a), 0.f);
+            knew = dmn - c0_[k] + x1n;
+          }
+          if (RES != R_BAL) knew -= rn;
+          const bool in = !MASK || (f_[k] & F_IN);
+          sa[l_[k]] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
+          kp_[k] = knew;
+          r_[k] = rn;
+          x0_[k] = x0n;
+          x1_[k] = x1n;
+        }
       }
       __syncthreads();
     };
