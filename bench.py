@@ -83,13 +83,13 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "0123cd95aea2e01a21646a05532f7b22650e8fb937f42e7ee3ffb1574dff613f"
+TRAFFIC_SHA256 = "153a44835a0698fa9ac71245f51d50caee554cade5213039aee5916d22336c84"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB, VALUBusy %, LdsUtil %,
 #              MeanOccupancyPerCU, SQ_INSTS_VALU, TCC hit rate) per dispatch
 COUNTERS = {
-    "ragged256": (4016, 180909.216, 231696.375, 63.71, 53.16, 15.24, 67279131, 0.542),
-    "pair512": (4008, 2922.378, 4096.000, 17.43, 11.97, 3.35, 1897024, 0.673),
+    "ragged256": (4016, 181660.970, 231696.375, 63.46, 52.96, 15.14, 67279131, 0.540),
+    "pair512": (4008, 2922.378, 4096.000, 17.44, 11.98, 3.26, 1897024, 0.673),
 }
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
 # 4 cycles (16 lanes), 2.4 GHz
