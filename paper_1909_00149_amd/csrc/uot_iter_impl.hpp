@@ -634,11 +634,12 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   constexpr int NC = (NCELL + BLOCK - 1) / BLOCK;
   constexpr int NOWN = TX * TH / BLOCK;  // owned cells per thread: the first NOWN
   // PERCELL: each phase of a step reads, computes and writes one cell at a
-  // time (fewer live registers, so more workgroups per CU).  With 4-row
-  // tiles, and in the check variant (whose occupancy its other registers
-  // set), every cell's inputs are read first: more loads in flight.  The
-  // arithmetic is the same either way.
-  constexpr bool PERCELL = TH >= 8 && !CHK;
+  // time (fewer live registers, so more workgroups per CU: the tall tiles
+  // of large grids and batches).  With 4- and 8-row tiles, whose grids are
+  // too small to fill more workgroups per CU, and in the check variant
+  // (whose occupancy its other registers set), every cell's inputs are read
+  // first: more loads in flight.  The arithmetic is the same either way.
+  constexpr bool PERCELL = TH >= 16 && !CHK;
   static_assert(TX * TH % BLOCK == 0, "whole tile rows per thread");
   static_assert(!CHK || H >= 2, "the check needs one exact cell beyond the tile");
   // LDS: the region's RH rows of RW cells back to back, so that the
