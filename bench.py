@@ -83,13 +83,13 @@ FLOPS = {(0, False): 26, (0, True): 22, (1, False): 37, (1, True): 33, (2, False
 # again.
 TRAFFIC_SOURCES = ("paper_1909_00149_amd/csrc/uot_iter_impl.hpp", "paper_1909_00149_amd/csrc/uot_iter_mode.hip",
                    "paper_1909_00149_amd/csrc/uot_internal.hpp")
-TRAFFIC_SHA256 = "0244c2dfa3f8d49313d27dcfe6c1e6f74dd1517ed9682e2060f04472c3cfde74"
+TRAFFIC_SHA256 = "c5d50bf0007c344fe1222539097d44a2af3e6d10fa00e059cd2620c80552e5e3"
 FETCH_SCALE, WRITE_SCALE = 2.000, 1.000
 # workload -> (tile_rows, FETCH_SIZE KiB, WRITE_SIZE KiB, VALUBusy %, LdsUtil %,
 #              MeanOccupancyPerCU, SQ_INSTS_VALU, TCC hit rate) per dispatch
 COUNTERS = {
-    "ragged256": (4016, 179737.002, 231696.375, 63.36, 52.87, 15.26, 67279131, 0.544),
-    "pair512": (4008, 2921.378, 4096.000, 17.87, 12.27, 3.08, 1897024, 0.674),
+    "ragged256": (4016, 180694.073, 231696.375, 63.63, 53.10, 15.26, 67279131, 0.542),
+    "pair512": (4008, 2921.378, 4096.000, 17.82, 12.24, 3.10, 1897024, 0.674),
 }
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
 # 4 cycles (16 lanes), 2.4 GHz

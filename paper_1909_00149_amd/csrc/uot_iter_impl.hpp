@@ -625,9 +625,12 @@ struct RegionPlane {
 
 // H: the halo, so up to H steps per launch keep the owned tile exact.  CHK:
 // the launch also evaluates the convergence check of the iterate pair of its
-// last step (steps <= H - 1, so that the new iterate is exact one cell
-// beyond the tile, where the check reads its neighbours); the last step's
-// input values the check needs are kept in registers for the owned cells.
+// last step (steps <= H - 1, so that the new dual is exact one cell beyond
+// the tile, where the check reads its right and upper neighbours).  The
+// stationarity residual splits into a part of the step's input and output
+// values, formed during the last step and kept in registers for the owned
+// cells, and the gradient of the new dual, added after it; the feasibility
+// residual is the last step's K(z) itself.
 template <int MODE, int RES, int BC, int TH, int H, bool CHK>
 __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   constexpr int RW = TX + 2 * H, RH = TH + 2 * H, NCELL = RW * RH;
@@ -636,10 +639,9 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   // PERCELL: each phase of a step reads, computes and writes one cell at a
   // time (fewer live registers, so more workgroups per CU: the tall tiles
   // of large grids and batches).  With 4- and 8-row tiles, whose grids are
-  // too small to fill more workgroups per CU, and in the check variant
-  // (whose occupancy its other registers set), every cell's inputs are read
+  // too small to fill more workgroups per CU, every cell's inputs are read
   // first: more loads in flight.  The arithmetic is the same either way.
-  constexpr bool PERCELL = TH >= 16 && !CHK;
+  constexpr bool PERCELL = TH >= 16;
   static_assert(TX * TH % BLOCK == 0, "whole tile rows per thread");
   static_assert(!CHK || H >= 2, "the check needs one exact cell beyond the tile");
   // LDS: the region's RH rows of RW cells back to back, so that the
@@ -653,12 +655,16 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
   constexpr int LW = RW;
   constexpr int NCHUNK = (NCELL + 63) / 64;  // 64-cell runs of the region, one per direct load
   constexpr int F_IN = 1, F_ZX = 2, F_ZY = 4, F_PAD = 8;  // per-cell flags
-  // a, Mx, My planes of the region; CHK: also the check's reduction buffer,
-  // used only between tiles (after the write of one, before the staging of
-  // the next)
+  // a, Mx, My planes of the region
   constexpr int PLANE = (RH + 4) * RW + PAD + 2;
-  constexpr int POOL = CHK && NS * BLOCK > (3 * PLANE + 1) / 2 ? NS * BLOCK : (3 * PLANE + 1) / 2;
-  __shared__ double pool[POOL];
+  __shared__ double pool[(3 * PLANE + 1) / 2];
+  // CHK: each thread's running sums of the stopping rule's summed terms
+  // over its block's run of tiles of one pair, one LDS word per thread and
+  // term (slots kSumSlot[0..NSUM)): held in registers across the steps they
+  // cost the check variant about 40 VGPRs and a workgroup per CU
+  constexpr int NSUM = 3 + (MODE == 1) + (MODE != 0);
+  __shared__ double runsum[CHK ? NSUM * BLOCK : 1];
+  __shared__ double wsum[CHK ? 4 * (NSUM + 1) : 1];  // per wave: the run's sums and non-finite count
   float* const sa = reinterpret_cast<float*>(pool);
   float* const smx = sa + PLANE;
   float* const smy = sa + 2 * PLANE;
@@ -675,16 +681,54 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     region_cell<TH, H>(tid + k * BLOCK, rx, ry);
     l_[k] = ry < RH ? (ry + 1) * RW + rx + 1 : (RH + 2) * RW + 1 + rx;
   }
-  // CHK: per-thread check sums over the block's run of tiles of one pair,
-  // reduced once per run into the row of its first tile (the run's other
-  // rows are zeroed, so the per-pair sum of the rows is unchanged).  Only
-  // the terms of the stopping rule are accumulated: the report's objective
-  // and bounds come from the final evaluation of a solve.
-  double acc[NS];
+  // CHK: per-thread check sums over the block's run of tiles of one pair
+  // (runsum, and the non-finite count), reduced once per run into the row
+  // of its first tile (the run's other rows are zeroed, so the per-pair sum
+  // of the rows is unchanged).  Only the terms of the stopping rule are
+  // accumulated: the report's objective and bounds come from the final
+  // evaluation of a solve.
+  constexpr int kSumSlot[5] = {S_PRES2, S_STAT2, S_KA2, MODE == 1 ? S_X0SQ : S_X1SQ, S_X1SQ};
+  int nonfin = 0;
   int run_pair = -1, run_row = 0;
+  // the run's sums reduced over the block into the row of partials of its
+  // first tile, and set back to zero: an xor butterfly within each wave
+  // (every lane ends with the same bits), then the four waves' values in a
+  // fixed order; the slots the check does not sum are written as zero.
+  // Runs are short on batches of small pairs (a workgroup's consecutive
+  // tiles lie a grid's width apart in the tile list), so the reduction
+  // leaves the region planes alone and costs one barrier.
+  auto flush_run = [&]() {
+    double v[NSUM + 1];
+#pragma unroll
+    for (int q = 0; q < NSUM; ++q) {
+      v[q] = runsum[q * BLOCK + tid];
+      runsum[q * BLOCK + tid] = 0.0;
+    }
+    v[NSUM] = (double)nonfin;
+    nonfin = 0;
+#pragma unroll
+    for (int q = 0; q <= NSUM; ++q)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q <= NSUM; ++q) wsum[(tid >> 6) * (NSUM + 1) + q] = v[q];
+    }
+    __syncthreads();
+    if (tid < NS) {
+      int q = tid == S_NONFIN ? NSUM : -1;
+#pragma unroll
+      for (int j = 0; j < NSUM; ++j)
+        if (kSumSlot[j] == tid) q = j;
+      double sum = 0.0;
+      if (q >= 0)
+        sum = (wsum[q] + wsum[(NSUM + 1) + q]) + (wsum[2 * (NSUM + 1) + q] + wsum[3 * (NSUM + 1) + q]);
+      A.chk[(long)run_row * NS + tid] = sum;
+    }
+  };
   if (CHK) {
 #pragma unroll
-    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NSUM; ++q) runsum[q * BLOCK + tid] = 0.0;
   }
 
   // the next tile's record is loaded while this one computes; its flag and
@@ -699,13 +743,7 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     if (!act) continue;  // uniform over the block
     if (CHK) {
       if (tl.pair != run_pair) {
-        if (run_pair >= 0) {
-          __syncthreads();  // the previous tile's write no longer reads the pool
-          block_reduce_lds(acc, kMaxSlotsCheck, A.chk + (long)run_row * NS, pool);
-#pragma unroll
-          for (int q = 0; q < NS; ++q) acc[q] = 0.0;
-          for (int i = tid; i < PLANE; i += BLOCK) sa[i] = smx[i] = smy[i] = 0.f;  // the zero border again
-        }
+        if (run_pair >= 0) flush_run();
         run_pair = tl.pair;
         run_row = tl.pad;
       } else if (tid < NS) {
@@ -715,11 +753,14 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const long off = P.off;
     const float tau1 = P.tau1, tau2 = P.tau2;
+    const float it1 = 1.f / tau1;
     const int bx = tl.x0 - H, by = tl.y0 - H;  // grid position of region cell (0, 0)
     int f_[NC];                                // flags of each cell
     float r_[NC], c0_[NC], c1_[NC], x0_[NC], x1_[NC], kp_[NC];
-    // CHK: the last step's input values of the owned cells
-    float ka_[NOWN], kr_[NOWN], ku_[NOWN], kmx_[NOWN], kmy_[NOWN], kro_[NOWN], kx0_[NOWN], kx1_[NOWN];
+    // CHK: the parts of the stationarity residual that the last step forms
+    // from its input and output values, per owned cell: flux (x, y), r, x0,
+    // x1; the new dual's gradient (and the new dual) complete them
+    float kpx_[NOWN], kpy_[NOWN], kpr_[NOWN], kp0_[NOWN], kp1_[NOWN];
 
     // the planes from region cell (0, 0); byte offsets of region cells are
     // below 4 GiB because the host runs blocked shapes only for pitches
@@ -831,16 +872,6 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
         for (int k = 0; k < NC; ++k) {
           const int l = l_[k];
           const float ac = sa[l], ar = sa[l + 1], au = sa[l + LW], mx = smx[l], my = smy[l];
-          if (KEEPSTEP && k < NOWN) {
-            ka_[k] = ac;
-            kr_[k] = ar;
-            ku_[k] = au;
-            kmx_[k] = mx;
-            kmy_[k] = my;
-            kro_[k] = r_[k];
-            kx0_[k] = x0_[k];
-            kx1_[k] = x1_[k];
-          }
           float gxx = ac - ar;
           float gyy = ac - au;
           if ((BC & 1) == 0 && MASK) {
@@ -851,6 +882,10 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
           const float vy = my - tau1 * gyy;
           float ox, oy;
           flux_shrink<BC>(vx, vy, tau1, ox, oy);
+          if (KEEPSTEP && k < NOWN) {
+            kpx_[k] = (mx - ox) * it1 - gxx;
+            kpy_[k] = (my - oy) * it1 - gyy;
+          }
           const bool in = !MASK || (f_[k] & F_IN);
           smx[l] = in ? ox : 0.f;
           smy[l] = in ? oy : 0.f;
@@ -880,6 +915,11 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
             knew = dmn - c0_[k] + x1n;
           }
           if (RES != R_BAL) knew -= rn;
+          if (KEEPSTEP && k < NOWN) {
+            if (RES != R_BAL) kpr_[k] = (r_[k] - rn) * it1 + a;
+            if (MODE == 1) kp0_[k] = (x0_[k] - x0n) * it1 + a;
+            if (MODE != 0) kp1_[k] = (x1_[k] - x1n) * it1 - a;
+          }
           const bool in = !MASK || (f_[k] & F_IN);
           sa[l] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
           kp_[k] = knew;
@@ -899,19 +939,6 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
           mx_[k] = smx[l];
           my_[k] = smy[l];
         }
-        if (KEEPSTEP) {
-#pragma unroll
-          for (int k = 0; k < NOWN; ++k) {
-            ka_[k] = ac_[k];
-            kr_[k] = ar_[k];
-            ku_[k] = au_[k];
-            kmx_[k] = mx_[k];
-            kmy_[k] = my_[k];
-            kro_[k] = r_[k];
-            kx0_[k] = x0_[k];
-            kx1_[k] = x1_[k];
-          }
-        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
           float gxx = ac_[k] - ar_[k];
@@ -924,6 +951,10 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
           const float vy = my_[k] - tau1 * gyy;
           float ox, oy;
           flux_shrink<BC>(vx, vy, tau1, ox, oy);
+          if (KEEPSTEP && k < NOWN) {
+            kpx_[k] = (mx_[k] - ox) * it1 - gxx;
+            kpy_[k] = (my_[k] - oy) * it1 - gyy;
+          }
           const bool in = !MASK || (f_[k] & F_IN);
           smx[l_[k]] = in ? ox : 0.f;
           smy[l_[k]] = in ? oy : 0.f;
@@ -960,6 +991,11 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
             knew = dmn - c0_[k] + x1n;
           }
           if (RES != R_BAL) knew -= rn;
+          if (KEEPSTEP && k < NOWN) {
+            if (RES != R_BAL) kpr_[k] = (r_[k] - rn) * it1 + a;
+            if (MODE == 1) kp0_[k] = (x0_[k] - x0n) * it1 + a;
+            if (MODE != 0) kp1_[k] = (x1_[k] - x1n) * it1 - a;
+          }
           const bool in = !MASK || (f_[k] & F_IN);
           sa[l_[k]] = in ? a + tau2 * (2.f * knew - kp_[k]) : 0.f;
           kp_[k] = knew;
@@ -992,71 +1028,49 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
 
     if (CHK) {
       // the stopping rule's terms for the iterate pair of the last step, per
-      // owned cell, with the expressions of check_kernel: the input values
-      // are in registers, the output ones in LDS, exact one cell beyond the
-      // tile, where the check reads the right and upper neighbours' a and
-      // the left and lower neighbours' flux
+      // owned cell, with the expressions of check_kernel: the new dual is
+      // exact one cell beyond the tile, where its gradient reads the right
+      // and upper neighbours; K(z) of the new iterate is the last step's
       constexpr float nid = (MODE == 0 ? 1 : (MODE == 1 ? 3 : 2)) - (RES == R_BAL ? 1 : 0);
-      const float it1 = 1.f / tau1;
+      double ts_[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // this tile's sums, in the order of kSumSlot
 #pragma unroll
       for (int k = 0; k < NOWN; ++k) {
         if (!(f_[k] & F_IN)) continue;
         const int l = l_[k];
-        const float a = sa[l], ap = ka_[k];
-        const float aR = sa[l + 1], apR = kr_[k];
-        const float aU = sa[l + LW], apU = ku_[k];
-        float gxx = a - aR, gyy = a - aU;
-        float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
+        const float a = sa[l], aR = sa[l + 1], aU = sa[l + LW];
         const bool zx = (BC & 1) == 0 && (f_[k] & F_ZX), zy = (BC & 1) == 0 && (f_[k] & F_ZY);
-        if (zx) gxx = dgx = 0.f;
-        if (zy) gyy = dgy = 0.f;
-        const float mx = zx ? 0.f : smx[l], my = zy ? 0.f : smy[l];
-        const float mxp = zx ? 0.f : kmx_[k], myp = zy ? 0.f : kmy_[k];
-        const float mxl = smx[l - 1];
-        const float myd = smy[l - LW];
-        const float dm = (mx - mxl) + (my - myd);
-        float x0 = 0.f, x1 = 0.f, e;
-        if (MODE == 0) {
-          e = dm + c0_[k];
-        } else if (MODE == 1) {
-          x0 = x0_[k];
-          x1 = x1_[k];
-          e = dm - x0 + x1;
-        } else {
-          x1 = x1_[k];
-          e = dm - c0_[k] + x1;
-        }
-        float r = 0.f, rp = 0.f;
+        const float gxx = zx ? 0.f : a - aR, gyy = zy ? 0.f : a - aU;
+        const float sx = kpx_[k] + gxx, sy = kpy_[k] + gyy;
+        float st2 = sx * sx + sy * sy;
+        float r = 0.f, x0 = 0.f, x1 = 0.f;
         if (RES != R_BAL) {
           r = r_[k];
-          rp = kro_[k];
-        }
-        const float kz = e - r;
-        const float da = ap - a;
-        const float sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
-        float st2 = sx * sx + sy * sy;
-        if (RES != R_BAL) {
-          const float sr = (rp - r) * it1 + da;
+          const float sr = kpr_[k] - a;
           st2 += sr * sr;
         }
         if (MODE == 1) {
-          const float s0 = (kx0_[k] - x0) * it1 + da;
+          x0 = x0_[k];
+          const float s0 = kp0_[k] - a;
           st2 += s0 * s0;
         }
         if (MODE != 0) {
-          const float s1 = (kx1_[k] - x1) * it1 - da;
+          x1 = x1_[k];
+          const float s1 = kp1_[k] + a;
           st2 += s1 * s1;
         }
+        const float kz = kp_[k];
         const float g2 = gxx * gxx + gyy * gyy;
-        acc[S_PRES2] += kz * kz;
-        acc[S_STAT2] += st2;
-        acc[S_KA2] += g2 + nid * a * a;
-        acc[S_X0SQ] += x0 * x0;
-        acc[S_X1SQ] += x1 * x1;
-        const bool fin = isfinite(a) && isfinite(mx) && isfinite(my) && isfinite(r) && isfinite(x0) &&
+        ts_[0] += kz * kz;
+        ts_[1] += st2;
+        ts_[2] += g2 + nid * a * a;
+        if (MODE == 1) ts_[3] += x0 * x0;
+        if (MODE != 0) ts_[NSUM - 1] += x1 * x1;
+        const bool fin = isfinite(a) && isfinite(smx[l]) && isfinite(smy[l]) && isfinite(r) && isfinite(x0) &&
                          isfinite(x1);
-        acc[S_NONFIN] += fin ? 0.0 : 1.0;
+        nonfin += fin ? 0 : 1;
       }
+#pragma unroll
+      for (int q = 0; q < NSUM; ++q) runsum[q * BLOCK + tid] += ts_[q];
     }
 
     // ---- write the owned tile ----
@@ -1076,10 +1090,7 @@ __device__ __forceinline__ void cp_iter_tb_body(const IterArgs& A) {
       if (MODE != 0) qx1.st(bo, x1_[k]);
     }
   }
-  if (CHK && run_pair >= 0) {
-    __syncthreads();
-    block_reduce_lds(acc, kMaxSlotsCheck, A.chk + (long)run_row * NS, pool);
-  }
+  if (CHK && run_pair >= 0) flush_run();
 }
 
 template <int MODE, int RES, int BC, int TH, int T>
@@ -1090,9 +1101,13 @@ __global__ __launch_bounds__(BLOCK) void cp_iter_tb_kernel(IterArgs A) {
 // The last launch of a check window on a blocked shape: up to H - 1 steps
 // of the blocked kernel with a halo of H that also leave the stopping rule's
 // partial rows of the iterate pair of its last step (so the window needs
-// neither a single-step launch nor a separate check).
+// neither a single-step launch nor a separate check).  Occupancy targets
+// that the variants meet without spilling: on tiles of up to 16 rows DIST
+// (flux, r and a per cell) fits 128 VGPRs, so a CU takes four workgroups,
+// and the modes with x0 and x1 take three; 32-row tiles take two.
 template <int MODE, int RES, int BC, int TH, int H>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void cp_iter_tb_check_kernel(IterArgs A) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(TH >= 32 ? 2 : (MODE == 0 ? 4 : 3)))) void
+cp_iter_tb_check_kernel(IterArgs A) {
   cp_iter_tb_body<MODE, RES, BC, TH, H, true>(A);
 }
 
@@ -1125,16 +1140,17 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
       const float a = C.a[o], ap = Q.a[o];
       const float aR = hasR ? C.a[o + 1] : 0.f, apR = hasR ? Q.a[o + 1] : 0.f;
       const float aU = hasU ? C.a[o + pitch] : 0.f, apU = hasU ? Q.a[o + pitch] : 0.f;
+      // the gradients of the dual and of the previous dual
       float gxx = a - aR, gyy = a - aU;
-      float dgx = (ap - a) - (apR - aR), dgy = (ap - a) - (apU - aU);
+      float gxo = ap - apR, gyo = ap - apU;
       const bool zx = ((BC & 1) == 0 && gx == nx - 1), zy = ((BC & 1) == 0 && gy == ny - 1);
-      if (zx) gxx = dgx = 0.f;
-      if (zy) gyy = dgy = 0.f;
+      if (zx) gxx = gxo = 0.f;
+      if (zy) gyy = gyo = 0.f;
       const float mx = zx ? 0.f : C.Mx[o], my = zy ? 0.f : C.My[o];
       const float mxp = zx ? 0.f : Q.Mx[o], myp = zy ? 0.f : Q.My[o];
       const float mxl = hasL ? C.Mx[o - 1] : 0.f;
       const float myd = hasD ? C.My[o - pitch] : 0.f;
-      const float dm = (mx - mxl) + (my - myd);
+      const float dm = mx - mxl + my - myd;  // the steps' order of the terms
       float x0 = 0.f, x1 = 0.f, e;
       if (MODE == 0) {
         e = dm + A.c[o];
@@ -1152,19 +1168,21 @@ __global__ __launch_bounds__(BLOCK) void check_kernel(CheckArgs A) {
         rp = Q.r[o];
       }
       const float kz = e - r;
-      const float da = ap - a;
-      const float sx = (mxp - mx) * it1 - dgx, sy = (myp - my) * it1 - dgy;
+      // the stationarity residual (z^{k-1} - z^k)/tau1 - K*(a^{k-1} - a^k),
+      // grouped as the blocked kernels form it: the previous dual's part
+      // with the step's values, then the dual's
+      const float sx = ((mxp - mx) * it1 - gxo) + gxx, sy = ((myp - my) * it1 - gyo) + gyy;
       float st2 = sx * sx + sy * sy;
       if (RES != R_BAL) {
-        const float sr = (rp - r) * it1 + da;
+        const float sr = ((rp - r) * it1 + ap) - a;
         st2 += sr * sr;
       }
       if (MODE == 1) {
-        const float s0 = (Q.x0[o] - x0) * it1 + da;
+        const float s0 = ((Q.x0[o] - x0) * it1 + ap) - a;
         st2 += s0 * s0;
       }
       if (MODE != 0) {
-        const float s1 = (Q.x1[o] - x1) * it1 - da;
+        const float s1 = ((Q.x1[o] - x1) * it1 - ap) + a;
         st2 += s1 * s1;
       }
       const float g2 = gxx * gxx + gyy * gyy;
