@@ -241,6 +241,38 @@ def test_fused_check_agrees_with_the_separate_check(dev, mode, tol, max_groups):
         assert torch.equal(sa[k], sb[k]), k
 
 
+@pytest.mark.parametrize("mode,bc,norm,p", [(G.PROX_FIXED, 0, G.NORM_ISO, 1), (DIST, 1, G.NORM_ISO, 1),
+                                             (DIST, 0, G.NORM_ANISO, 1), (PROX, 1, G.NORM_ISO, 2),
+                                             (G.PROX_FIXED, 1, G.NORM_ANISO, 2)])
+def test_fused_check_agrees_on_every_variant(dev, mode, bc, norm, p):
+    """The fused check forms the stationarity residual from partial terms of
+    the last step and the new dual's gradient, and the feasibility residual
+    from the last step's K(z); the separate check kernel forms both from the
+    two stored iterates.  On the one-argument-fixed mode, the free edges
+    (bc = 1), the anisotropic norm and the squared source term, with a capped
+    grid (long runs of tiles per workgroup), both give the same residual at
+    every check (up to the order of the FP64 sums), the same decisions and
+    bitwise equal iterates."""
+    shapes = SHAPES + [(300, 257)]
+    pairs, src, dst, nx, ny, offs = batch_of(shapes, dev, seed0=90)
+    out = []
+    for ty in (4016, 16):
+        s = G.Solver(G.Params(mode=mode, bc=bc, norm=norm, residual_p=p, mu=1.1, rho=0.8, max_iter=400,
+                              check_every=20, tol=1e-6, tile_rows=ty, flags=G.UOT_RECORD_HISTORY, max_groups=8))
+        st, reps = s.solve_batched(src, dst, nx, ny, offs)
+        torch.cuda.synchronize()
+        out.append((st, reps, [s.history(b) for b in range(len(shapes))]))
+        assert all(r["tile_rows"] == ty for r in reps)
+    (sa, ra, ha), (sb, rb, hb) = out
+    for b in range(len(shapes)):
+        assert ra[b]["iters"] == rb[b]["iters"] and ra[b]["status"] == rb[b]["status"], b
+        assert len(ha[b][0]) >= 1 and list(ha[b][0]) == list(hb[b][0]), b
+        assert np.all(np.isfinite(ha[b][1])) and np.all(ha[b][1] > 0), b
+        np.testing.assert_allclose(ha[b][1], hb[b][1], rtol=1e-9, atol=0)
+    for k in planes(mode, False):
+        assert torch.equal(sa[k], sb[k]), k
+
+
 @pytest.mark.parametrize("ty", [4016, 4004, 116, 8])
 def test_capped_grid_walks_the_tile_list(dev, ty):
     """max_groups = 8 gives each workgroup tens of tiles of several pairs
